@@ -1,0 +1,612 @@
+/*
+ * npm_oracle.c -- plain FP64 CPU oracle for the Neural Parametric Mixtures
+ * (NPM) hot path: multiresolution grid encoding, decoder MLP, the Table 1
+ * output mappings, vMF-mixture pdf and sampling, the Monte Carlo KL
+ * gradient, backpropagation with the grid scatter, and Adam.
+ *
+ * TEST INFRASTRUCTURE.  This file exists only to check the HIP library.  It
+ * shares no source, header, table or helper with it; the two agree only
+ * through the paper and the flat parameter layout documented below.  Only the
+ * test-suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It is deliberately simple: one vertex at a time, in the order the
+ * paper states the computation, in double precision.  The only float
+ * arithmetic is the position scaling of the grid lookup, which is part of the
+ * definition of the lattice cell (see oracle_cell) so that corner indices are
+ * comparable bit for bit.
+ *
+ * Paper sections followed (Dong, Wang, Li, "Neural Parametric Mixtures for
+ * Path Guiding", SIGGRAPH 2023):
+ *   - Preliminary / "Von Mises-Fisher Mixtures": single-lobe vMF density and
+ *     the K-lobe mixture.
+ *   - Sec. 4.1 "Radiance-based NPM", eq. npmradiance and Table 1
+ *     (tab:activations): exponential kappa, softmax lambda, logistic
+ *     (theta, phi) as normalised spherical coordinates of mu.
+ *   - Sec. 4.2 "Optimizing NPM": Monte Carlo KL estimator and its gradient,
+ *     eq. mcgradients, and the spatially varying objective.
+ *   - Sec. 5.1 "Multi-resolution Spatial Embedding": L uniform grids with
+ *     exponentially growing resolution, F features per lattice point,
+ *     interpolation over the eight cell corners, level concatenation.
+ *   - Sec. 5.3 "Guiding Network": ReLU MLP, K = 8 lobes, Adam, and the
+ *     numerically stable vMF sampling strategy of Jakob (2012).
+ *
+ * Readings where the paper is silent (all of them documented in the design
+ * notes of the repository, and fixed identically by the library):
+ *   - interpolation is trilinear over the 8 corners (the text says
+ *     "bilinear" but names eight corners);
+ *   - positions live in [0,1]^3, level l has (D_l+1)^3 lattice points, the
+ *     cell index is min(floor(x*D_l), D_l-1) with x*D_l one float multiply;
+ *   - D_l = floor(D_min * b^l + 1e-6), b = (D_max/D_min)^(1/(L-1)), last
+ *     level forced to D_max;
+ *   - levels with more than T = 2^log2T lattice points use the spatial hash
+ *     of Mueller et al. 2022 (cited by the paper for the embedding): XOR of
+ *     (x*1, y*2654435761, z*805459861) in 32-bit arithmetic, modulo T;
+ *   - the MLP has no biases; Theta' is lobe-major (theta', phi', kappa',
+ *     lambda'); mu = (sin T cos P, sin T sin P, cos T) with T = pi*theta,
+ *     P = 2*pi*phi; kappa' is clamped to [-80, 80] before exp;
+ *   - the training weight is w = L/p for finite L > 0, p > 0, else 0; the
+ *     batch mean divides by N including zero-weight samples;
+ *   - Adam: beta1 0.9, beta2 0.999, eps 1e-8 outside the square root, bias
+ *     correction with t counted from 1, dense update of every parameter;
+ *   - uniforms come from Philox4x32-10 (Salmon et al., SC'11) with counter
+ *     (vertex lo, vertex hi, stream, sample) and key (seed lo, seed hi),
+ *     u = (word >> 8) * 2^-24; lobe selection takes the first k with
+ *     u0*S < C_k over the inclusive prefix sums C of lambda (S = C_{K-1}),
+ *     falling back to K-1.
+ *
+ * Flat parameter layout (the one interface shared with the library): the
+ * grid tables first, level after level, entry-major with F features per entry
+ * (entry e of level l, feature f at (offset_l + e)*F + f); then the weight
+ * matrices W_0 .. W_{n_hidden}, each row-major [out][in].
+ *
+ * Parity pins: every function here is pinned by a CPU test against the
+ * mathematics (closed forms, quadrature, finite differences, invariants,
+ * published known-answer vectors).  The resolution-growth rule and the hash
+ * are readings, not results; they are pinned only by their properties.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NPMO_MAX_LEVELS 32
+#define NPMO_MAX_LAYERS 8
+#define NPMO_MAX_WIDTH 256
+#define NPMO_MAX_LOBES 16
+
+typedef struct {
+    int64_t size[NPMO_MAX_LEVELS];    /* table entries of each level          */
+    int64_t offset[NPMO_MAX_LEVELS];  /* first entry of each level            */
+    int64_t layer_offset[NPMO_MAX_LAYERS]; /* first weight of each matrix     */
+    int64_t grid_entries;
+    int64_t grid_params;              /* grid_entries * feat                  */
+    int64_t n_params;
+    int32_t res[NPMO_MAX_LEVELS];
+    int32_t hashed[NPMO_MAX_LEVELS];
+    int32_t layer_in[NPMO_MAX_LAYERS];
+    int32_t layer_out[NPMO_MAX_LAYERS];
+    int32_t n_levels, feat, log2_table, dense_only;
+    int32_t base_res, max_res;
+    int32_t n_in, width, n_hidden, n_lobes, n_layers, n_out;
+} npmo_net;
+
+static const double PI = 3.14159265358979323846264338327950288;
+
+/* ------------------------------------------------------------------------ */
+/* Level layout: Sec. 5.1, "D_l grows exponentially".                       */
+/* ------------------------------------------------------------------------ */
+int npmo_net_init(npmo_net *net, int L, int F, int base_res, int max_res,
+                  int log2T, int dense_only, int n_hidden, int width, int K)
+{
+    if (!net || L < 1 || L > NPMO_MAX_LEVELS || F < 1 || F > 8) return -1;
+    if (base_res < 1 || max_res < base_res) return -1;
+    if (n_hidden < 1 || n_hidden + 1 > NPMO_MAX_LAYERS) return -1;
+    if (width < 1 || width > NPMO_MAX_WIDTH || K < 1 || K > NPMO_MAX_LOBES) return -1;
+    if (L * F > NPMO_MAX_WIDTH) return -1;
+    if (!dense_only && (log2T < 1 || log2T > 30)) return -1;
+    memset(net, 0, sizeof(*net));
+    net->n_levels = L; net->feat = F; net->log2_table = log2T;
+    net->dense_only = dense_only; net->base_res = base_res; net->max_res = max_res;
+    for (int l = 0; l < L; ++l) {
+        int D;
+        if (l == L - 1) D = max_res;
+        else if (l == 0) D = base_res;
+        else {
+            double b = exp(log((double)max_res / (double)base_res) / (double)(L - 1));
+            D = (int)floor((double)base_res * pow(b, (double)l) + 1e-6);
+        }
+        net->res[l] = D;
+        double pts = (double)(D + 1) * (double)(D + 1) * (double)(D + 1);
+        if (dense_only || pts <= ldexp(1.0, log2T)) {
+            net->hashed[l] = 0;
+            net->size[l] = (int64_t)(D + 1) * (D + 1) * (D + 1);
+        } else {
+            net->hashed[l] = 1;
+            net->size[l] = (int64_t)1 << log2T;
+        }
+        net->offset[l] = net->grid_entries;
+        net->grid_entries += net->size[l];
+    }
+    net->grid_params = net->grid_entries * F;
+    net->n_in = L * F; net->width = width; net->n_hidden = n_hidden;
+    net->n_lobes = K; net->n_out = 4 * K; net->n_layers = n_hidden + 1;
+    int64_t off = net->grid_params;
+    for (int i = 0; i < net->n_layers; ++i) {
+        net->layer_in[i] = (i == 0) ? net->n_in : width;
+        net->layer_out[i] = (i == n_hidden) ? net->n_out : width;
+        net->layer_offset[i] = off;
+        off += (int64_t)net->layer_in[i] * net->layer_out[i];
+    }
+    net->n_params = off;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the      */
+/* 4-word S-box with multipliers 0xD2511F53 / 0xCD9E8D57 and key Weyl        */
+/* increments 0x9E3779B9 / 0xBB67AE85.                                       */
+/* ------------------------------------------------------------------------ */
+void npmo_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0;
+        uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+    out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+static void uniforms3(int64_t vertex, uint64_t seed, uint32_t stream, uint32_t sample, double u[3])
+{
+    uint32_t ctr[4] = {(uint32_t)((uint64_t)vertex & 0xffffffffu), (uint32_t)((uint64_t)vertex >> 32),
+                       stream, sample};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    npmo_philox(ctr, key, w);
+    for (int i = 0; i < 3; ++i) u[i] = (double)(w[i] >> 8) * (1.0 / 16777216.0);
+}
+
+void npmo_uniforms(int64_t n, const int64_t *vid, uint64_t seed, uint32_t stream,
+                   uint32_t sample, double *u /* [n][3] */)
+{
+    for (int64_t i = 0; i < n; ++i) uniforms3(vid ? vid[i] : i, seed, stream, sample, u + 3 * i);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 5.1: the cell of G_l enclosing x, its eight corners and weights.     */
+/* ------------------------------------------------------------------------ */
+static void oracle_cell(float x, int D, int *c, double *f)
+{
+    /* Clamp into the unit cube (NaN goes to 0), then one IEEE float multiply. */
+    float xc = fminf(fmaxf(x, 0.0f), 1.0f);
+    volatile float p = xc * (float)D;
+    int ci = (int)floorf(p);
+    if (ci > D - 1) ci = D - 1;
+    *c = ci;
+    *f = (double)(p - (float)ci); /* exact: p and ci are within a factor 2 */
+}
+
+static int64_t oracle_corner_index(const npmo_net *net, int l, int64_t x, int64_t y, int64_t z)
+{
+    int64_t D1 = (int64_t)net->res[l] + 1;
+    if (!net->hashed[l]) return net->offset[l] + x + y * D1 + z * D1 * D1;
+    uint32_t h = ((uint32_t)x * 1u) ^ ((uint32_t)y * 2654435761u) ^ ((uint32_t)z * 805459861u);
+    return net->offset[l] + (int64_t)(h % ((uint32_t)1u << net->log2_table));
+}
+
+/* idx[l][8] (global entry index) and w[l][8] for one position; corner b has
+ * x offset (b & 1), y offset ((b >> 1) & 1), z offset ((b >> 2) & 1).      */
+static void oracle_corners_one(const npmo_net *net, float px, float py, float pz,
+                               int64_t *idx, double *w)
+{
+    for (int l = 0; l < net->n_levels; ++l) {
+        int c[3]; double f[3];
+        oracle_cell(px, net->res[l], &c[0], &f[0]);
+        oracle_cell(py, net->res[l], &c[1], &f[1]);
+        oracle_cell(pz, net->res[l], &c[2], &f[2]);
+        for (int b = 0; b < 8; ++b) {
+            int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+            double wx = bx ? f[0] : 1.0 - f[0];
+            double wy = by ? f[1] : 1.0 - f[1];
+            double wz = bz ? f[2] : 1.0 - f[2];
+            w[l * 8 + b] = wx * wy * wz;
+            idx[l * 8 + b] = oracle_corner_index(net, l, c[0] + bx, c[1] + by, c[2] + bz);
+        }
+    }
+}
+
+void npmo_corners(const npmo_net *net, int64_t n, const float *pos /* [3][n] */,
+                  int64_t *idx /* [n][L][8] */, double *w /* [n][L][8] */)
+{
+    int L = net->n_levels;
+    for (int64_t i = 0; i < n; ++i)
+        oracle_corners_one(net, pos[i], pos[n + i], pos[2 * n + i], idx + i * L * 8, w + i * L * 8);
+}
+
+/* G(x) = concat_l sum_corners w_c V_l[c]  (level-major, index l*F + f).
+ * gscale receives sum_c |w_c V_l[c]| per output, the size of the terms.    */
+static void oracle_encode_one(const npmo_net *net, float px, float py, float pz,
+                              const double *params, double *G, double *gscale)
+{
+    int L = net->n_levels, F = net->feat;
+    int64_t idx[NPMO_MAX_LEVELS * 8];
+    double w[NPMO_MAX_LEVELS * 8];
+    oracle_corners_one(net, px, py, pz, idx, w);
+    for (int l = 0; l < L; ++l)
+        for (int f = 0; f < F; ++f) {
+            double s = 0.0, a = 0.0;
+            for (int b = 0; b < 8; ++b) {
+                double t = w[l * 8 + b] * params[idx[l * 8 + b] * F + f];
+                s += t; a += fabs(t);
+            }
+            G[l * F + f] = s;
+            if (gscale) gscale[l * F + f] = a;
+        }
+}
+
+void npmo_encode(const npmo_net *net, int64_t n, const float *pos, const double *params,
+                 double *G /* [n][n_in] */, double *gscale /* [n][n_in] or NULL */)
+{
+    int ni = net->n_in;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        oracle_encode_one(net, pos[i], pos[n + i], pos[2 * n + i], params, G + i * ni,
+                          gscale ? gscale + i * ni : NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Decoder MLP (Sec. 5.3): z_i = W_i h_i, h_{i+1} = ReLU(z_i) for the hidden */
+/* layers, raw output Theta' = W_last h_last.                                */
+/* acts[i] holds the input of layer i (acts[0] = G).                        */
+/* ------------------------------------------------------------------------ */
+static void oracle_mlp_one(const npmo_net *net, const double *G, const double *params,
+                           double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH],
+                           double *raw, double *rawscale)
+{
+    for (int j = 0; j < net->n_in; ++j) acts[0][j] = G[j];
+    for (int i = 0; i < net->n_layers; ++i) {
+        const double *W = params + net->layer_offset[i];
+        int nin = net->layer_in[i], nout = net->layer_out[i];
+        int last = (i == net->n_layers - 1);
+        for (int o = 0; o < nout; ++o) {
+            double s = 0.0, a = 0.0;
+            for (int k = 0; k < nin; ++k) {
+                double t = W[(int64_t)o * nin + k] * acts[i][k];
+                s += t; a += fabs(t);
+            }
+            if (last) {
+                raw[o] = s;
+                if (rawscale) rawscale[o] = a;
+            } else {
+                acts[i + 1][o] = s > 0.0 ? s : 0.0;
+            }
+        }
+    }
+}
+
+void npmo_mlp_forward(const npmo_net *net, int64_t n, const double *G, const double *params,
+                      double *raw /* [n][4K] */, double *rawscale /* [n][4K] or NULL */)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
+        oracle_mlp_one(net, G + i * net->n_in, params, acts, raw + i * net->n_out,
+                       rawscale ? rawscale + i * net->n_out : NULL);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Table 1 mappings and the lobe frames.                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double theta, phi, kappa, lambda, loglambda;
+    double mu[3], t1[3], t2[3];
+    double sinT;
+} oracle_lobe;
+
+static double clamp_kappa_raw(double k) { return k < -80.0 ? -80.0 : (k > 80.0 ? 80.0 : k); }
+
+static void oracle_map(const npmo_net *net, const double *raw, oracle_lobe *lob)
+{
+    int K = net->n_lobes;
+    double mx = -INFINITY;
+    for (int k = 0; k < K; ++k) if (raw[4 * k + 3] > mx) mx = raw[4 * k + 3];
+    double se = 0.0;
+    for (int k = 0; k < K; ++k) se += exp(raw[4 * k + 3] - mx);
+    double lse = mx + log(se);
+    for (int k = 0; k < K; ++k) {
+        oracle_lobe *b = &lob[k];
+        b->theta = 1.0 / (1.0 + exp(-raw[4 * k + 0]));
+        b->phi = 1.0 / (1.0 + exp(-raw[4 * k + 1]));
+        b->kappa = exp(clamp_kappa_raw(raw[4 * k + 2]));
+        b->loglambda = raw[4 * k + 3] - lse;
+        b->lambda = exp(b->loglambda);
+        double T = PI * b->theta, P = 2.0 * PI * b->phi;
+        double sT = sin(T), cT = cos(T), sP = sin(P), cP = cos(P);
+        b->sinT = sT;
+        b->mu[0] = sT * cP; b->mu[1] = sT * sP; b->mu[2] = cT;
+        b->t1[0] = cT * cP; b->t1[1] = cT * sP; b->t1[2] = -sT;
+        b->t2[0] = -sP;     b->t2[1] = cP;      b->t2[2] = 0.0;
+    }
+}
+
+/* log of the vMF normaliser kappa / (4 pi sinh kappa), written as
+ * kappa / (2 pi (1 - e^{-2 kappa})) * e^{-kappa} so that the exponent can be
+ * folded into kappa (mu.w - 1); this function returns log of the first
+ * factor.  The identity is exact; it only avoids overflow of sinh.         */
+static double log_vmf_norm(double kappa)
+{
+    return log(kappa / (-expm1(-2.0 * kappa))) - log(2.0 * PI);
+}
+
+/* Per-lobe log terms log(lambda_k v_k(w)) and the mixture log-density.      */
+static double oracle_logpdf(const npmo_net *net, const oracle_lobe *lob, const double w[3],
+                            double *terms /* [K] or NULL */)
+{
+    int K = net->n_lobes;
+    double t[NPMO_MAX_LOBES], mx = -INFINITY;
+    for (int k = 0; k < K; ++k) {
+        double d = lob[k].mu[0] * w[0] + lob[k].mu[1] * w[1] + lob[k].mu[2] * w[2];
+        t[k] = lob[k].loglambda + log_vmf_norm(lob[k].kappa) + lob[k].kappa * (d - 1.0);
+        if (t[k] > mx) mx = t[k];
+    }
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += exp(t[k] - mx);
+    if (terms) for (int k = 0; k < K; ++k) terms[k] = t[k];
+    return mx + log(s);
+}
+
+void npmo_head(const npmo_net *net, int64_t n, const double *raw, double *lobes /* [n][K][4] */)
+{
+    int K = net->n_lobes;
+    for (int64_t i = 0; i < n; ++i) {
+        oracle_lobe lob[NPMO_MAX_LOBES];
+        oracle_map(net, raw + i * net->n_out, lob);
+        for (int k = 0; k < K; ++k) {
+            double *o = lobes + (i * K + k) * 4;
+            o[0] = lob[k].theta; o[1] = lob[k].phi; o[2] = lob[k].kappa; o[3] = lob[k].lambda;
+        }
+    }
+}
+
+void npmo_logpdf(const npmo_net *net, int64_t n, const double *raw, const double *dir /* [n][3] */,
+                 double *logpdf)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        oracle_lobe lob[NPMO_MAX_LOBES];
+        oracle_map(net, raw + i * net->n_out, lob);
+        logpdf[i] = oracle_logpdf(net, lob, dir + 3 * i, NULL);
+    }
+}
+
+/* Sampling (Sec. 5.3, Jakob 2012): choose a lobe by the inverse CDF of the
+ * weights, draw the cosine t to mu from the marginal density proportional to
+ * e^{kappa t} on [-1, 1] by its inverse CDF in the log1p/expm1 form, and the
+ * azimuth uniformly in the lobe frame (t1, t2).                            */
+static void oracle_sample_one(const npmo_net *net, const oracle_lobe *lob, const double u[3],
+                              double w[3], int *lobe_out, double *margin)
+{
+    int K = net->n_lobes;
+    double C[NPMO_MAX_LOBES] = {0.0}, acc = 0.0;
+    for (int k = 0; k < K; ++k) { acc += lob[k].lambda; C[k] = acc; }
+    double S = C[K - 1], target = u[0] * S;
+    int sel = K - 1;
+    for (int k = 0; k < K; ++k) if (target < C[k]) { sel = k; break; }
+    if (margin) {
+        double m = INFINITY;
+        for (int k = 0; k < K - 1; ++k) { double d = fabs(target - C[k]) / S; if (d < m) m = d; }
+        *margin = m;
+    }
+    const oracle_lobe *b = &lob[sel];
+    double kappa = b->kappa;
+    double t = 1.0 + log1p((1.0 - u[1]) * expm1(-2.0 * kappa)) / kappa;
+    double s = sqrt(fmax(0.0, (1.0 - t) * (1.0 + t)));
+    double psi = 2.0 * PI * u[2];
+    double cp = cos(psi), sp = sin(psi);
+    for (int d = 0; d < 3; ++d) w[d] = t * b->mu[d] + s * (cp * b->t1[d] + sp * b->t2[d]);
+    *lobe_out = sel;
+}
+
+/* Query: lobes, log pdf at dir, one sample and its log pdf, per vertex.
+ * vid gives the vertex number used as the random counter (NULL = 0..n-1). */
+void npmo_query(const npmo_net *net, int64_t n, const float *pos, const float *dir /* [3][n] or NULL */,
+                const int64_t *vid, uint64_t seed, uint32_t stream, const double *params,
+                double *G_out /* [n][n_in] or NULL */, double *raw_out /* [n][4K] or NULL */,
+                double *lobes /* [n][K][4] or NULL */, double *logpdf /* [n] or NULL */,
+                double *sdir /* [n][3] or NULL */, double *slogpdf /* [n] or NULL */,
+                int32_t *slobe /* [n] or NULL */, double *smargin /* [n] or NULL */)
+{
+    int K = net->n_lobes;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double G[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES];
+        double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
+        oracle_lobe lob[NPMO_MAX_LOBES];
+        oracle_encode_one(net, pos[i], pos[n + i], pos[2 * n + i], params, G, NULL);
+        oracle_mlp_one(net, G, params, acts, raw, NULL);
+        oracle_map(net, raw, lob);
+        if (G_out) for (int j = 0; j < net->n_in; ++j) G_out[i * net->n_in + j] = G[j];
+        if (raw_out) for (int j = 0; j < net->n_out; ++j) raw_out[i * net->n_out + j] = raw[j];
+        if (lobes)
+            for (int k = 0; k < K; ++k) {
+                double *o = lobes + (i * K + k) * 4;
+                o[0] = lob[k].theta; o[1] = lob[k].phi; o[2] = lob[k].kappa; o[3] = lob[k].lambda;
+            }
+        if (logpdf && dir) {
+            double w[3] = {dir[i], dir[n + i], dir[2 * n + i]};
+            logpdf[i] = oracle_logpdf(net, lob, w, NULL);
+        }
+        if (sdir || slogpdf || slobe) {
+            double u[3], w[3];
+            int sel; double mg;
+            uniforms3(vid ? vid[i] : i, seed, stream, 0, u);
+            oracle_sample_one(net, lob, u, w, &sel, &mg);
+            if (sdir) for (int d = 0; d < 3; ++d) sdir[3 * i + d] = w[d];
+            if (slogpdf) slogpdf[i] = oracle_logpdf(net, lob, w, NULL);
+            if (slobe) slobe[i] = sel;
+            if (smargin) smargin[i] = mg;
+        }
+    }
+}
+
+/* Sampling from given raw outputs with explicit uniforms [n][3] (used by
+ * the statistical pins, where many draws share one mixture).               */
+void npmo_sample_raw(const npmo_net *net, int64_t n, const double *raw /* [n][4K] */,
+                     const double *u /* [n][3] */, double *sdir /* [n][3] */, int32_t *slobe)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        oracle_lobe lob[NPMO_MAX_LOBES];
+        double w[3]; int sel; double mg;
+        oracle_map(net, raw + i * net->n_out, lob);
+        oracle_sample_one(net, lob, u + 3 * i, w, &sel, &mg);
+        for (int d = 0; d < 3; ++d) sdir[3 * i + d] = w[d];
+        if (slobe) slobe[i] = sel;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 4.2: the Monte Carlo KL estimate and its gradient (eq. mcgradients).*/
+/* Per sample j with weight w_j = L_j / p_j the surrogate loss term is      */
+/* -(w_j / N) log V(w_j); its gradient is -(w_j / N) grad V / V, written in */
+/* terms of the raw outputs through the Table 1 mappings.                   */
+/* ------------------------------------------------------------------------ */
+static double oracle_weight(float rad, float pdf)
+{
+    if (!isfinite(rad) || !isfinite(pdf) || !(pdf > 0.0f) || !(rad > 0.0f)) return 0.0;
+    return (double)rad / (double)pdf;
+}
+
+/* Returns the sample's loss contribution -(w/N) log V; fills draw[4K].     */
+static double oracle_loss_grad_one(const npmo_net *net, const double *raw, const double w3[3],
+                                   double wgt, double invN, double *draw)
+{
+    int K = net->n_lobes;
+    for (int j = 0; j < net->n_out; ++j) draw[j] = 0.0;
+    if (wgt == 0.0) return 0.0;
+    oracle_lobe lob[NPMO_MAX_LOBES];
+    double terms[NPMO_MAX_LOBES];
+    oracle_map(net, raw, lob);
+    double lv = oracle_logpdf(net, lob, w3, terms);
+    double g = -wgt * invN;   /* d loss / d log V */
+    for (int k = 0; k < K; ++k) {
+        const oracle_lobe *b = &lob[k];
+        double r = exp(terms[k] - lv);            /* responsibility lambda_k v_k / V */
+        double kap = b->kappa;
+        double d = b->mu[0] * w3[0] + b->mu[1] * w3[1] + b->mu[2] * w3[2];
+        double dt1 = b->t1[0] * w3[0] + b->t1[1] * w3[1] + b->t1[2] * w3[2];
+        double dt2 = b->t2[0] * w3[0] + b->t2[1] * w3[1] + b->t2[2] * w3[2];
+        /* d log v / d theta' : kappa (t1.w) pi theta (1 - theta)          */
+        double dth = kap * dt1 * PI * b->theta * (1.0 - b->theta);
+        /* d log v / d phi'   : kappa sinT (t2.w) 2 pi phi (1 - phi)       */
+        double dph = kap * b->sinT * dt2 * 2.0 * PI * b->phi * (1.0 - b->phi);
+        /* d log v / d kappa' : kappa (1/kappa - 2/(e^{2k}-1) + mu.w - 1),
+         * zero where the clamp of kappa' is active.                         */
+        double rk = raw[4 * k + 2];
+        double dka = (rk < -80.0 || rk > 80.0) ? 0.0
+                   : 1.0 - 2.0 * kap / expm1(2.0 * kap) + kap * (d - 1.0);
+        draw[4 * k + 0] = g * r * dth;
+        draw[4 * k + 1] = g * r * dph;
+        draw[4 * k + 2] = g * r * dka;
+        /* d log V / d lambda'_k = r_k - lambda_k (softmax Jacobian)        */
+        draw[4 * k + 3] = g * (r - b->lambda);
+    }
+    return g * lv;
+}
+
+double npmo_loss_grad(const npmo_net *net, int64_t n, int64_t n_total, const double *raw,
+                      const float *dir /* [3][n] */, const float *rad, const float *spdf,
+                      double *draw /* [n][4K] */)
+{
+    double invN = 1.0 / (double)n_total, loss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
+        loss += oracle_loss_grad_one(net, raw + i * net->n_out, w3, oracle_weight(rad[i], spdf[i]),
+                                     invN, draw + i * net->n_out);
+    }
+    return loss;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Backpropagation (Fig. 2, dashed path): through the MLP into dG, then the */
+/* scatter of dG into the eight corners of every level (the transpose of    */
+/* the interpolation), with the encoding recomputed per vertex.  grad and   */
+/* gabs accumulate; gabs receives the sum of |contributions| per parameter. */
+/* ------------------------------------------------------------------------ */
+double npmo_backward(const npmo_net *net, int64_t n, int64_t n_total, const float *pos,
+                     const float *dir, const float *rad, const float *spdf, const double *params,
+                     double *grad /* [n_params] */, double *gabs /* [n_params] or NULL */,
+                     double *draw_out /* [n][4K] or NULL */, double *dG_out /* [n][n_in] or NULL */)
+{
+    int L = net->n_levels, F = net->feat;
+    double invN = 1.0 / (double)n_total, loss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double G[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES], draw[4 * NPMO_MAX_LOBES];
+        double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
+        double delta[NPMO_MAX_WIDTH], prev[NPMO_MAX_WIDTH];
+        int64_t idx[NPMO_MAX_LEVELS * 8];
+        double cw[NPMO_MAX_LEVELS * 8];
+        float px = pos[i], py = pos[n + i], pz = pos[2 * n + i];
+        oracle_encode_one(net, px, py, pz, params, G, NULL);
+        oracle_mlp_one(net, G, params, acts, raw, NULL);
+        double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
+        loss += oracle_loss_grad_one(net, raw, w3, oracle_weight(rad[i], spdf[i]), invN, draw);
+        if (draw_out) for (int j = 0; j < net->n_out; ++j) draw_out[i * net->n_out + j] = draw[j];
+        /* delta holds dLoss/d(output of layer i), i from last to first.    */
+        for (int j = 0; j < net->n_out; ++j) delta[j] = draw[j];
+        for (int li = net->n_layers - 1; li >= 0; --li) {
+            const double *W = params + net->layer_offset[li];
+            double *dW = grad + net->layer_offset[li];
+            double *aW = gabs ? gabs + net->layer_offset[li] : NULL;
+            int nin = net->layer_in[li], nout = net->layer_out[li];
+            /* hidden layer outputs pass through ReLU: derivative 0 at 0     */
+            if (li < net->n_layers - 1)
+                for (int o = 0; o < nout; ++o) if (!(acts[li + 1][o] > 0.0)) delta[o] = 0.0;
+            for (int o = 0; o < nout; ++o)
+                for (int k = 0; k < nin; ++k) {
+                    double t = delta[o] * acts[li][k];
+                    dW[(int64_t)o * nin + k] += t;
+                    if (aW) aW[(int64_t)o * nin + k] += fabs(t);
+                }
+            for (int k = 0; k < nin; ++k) {
+                double s = 0.0;
+                for (int o = 0; o < nout; ++o) s += W[(int64_t)o * nin + k] * delta[o];
+                prev[k] = s;
+            }
+            for (int k = 0; k < nin; ++k) delta[k] = prev[k];
+        }
+        if (dG_out) for (int j = 0; j < net->n_in; ++j) dG_out[i * net->n_in + j] = delta[j];
+        oracle_corners_one(net, px, py, pz, idx, cw);
+        for (int l = 0; l < L; ++l)
+            for (int b = 0; b < 8; ++b)
+                for (int f = 0; f < F; ++f) {
+                    double t = cw[l * 8 + b] * delta[l * F + f];
+                    grad[idx[l * 8 + b] * F + f] += t;
+                    if (gabs) gabs[idx[l * 8 + b] * F + f] += fabs(t);
+                }
+    }
+    return loss;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adam (Kingma and Ba), as the paper trains with it at a fixed rate.        */
+/* t is the 1-based step number of this update.                             */
+/* ------------------------------------------------------------------------ */
+void npmo_adam(int64_t np, double *params, const double *grad, double *m, double *v, int64_t t,
+               double lr, double beta1, double beta2, double eps)
+{
+    double c1 = 1.0 - pow(beta1, (double)t), c2 = 1.0 - pow(beta2, (double)t);
+    for (int64_t i = 0; i < np; ++i) {
+        double g = grad[i];
+        m[i] = beta1 * m[i] + (1.0 - beta1) * g;
+        v[i] = beta2 * v[i] + (1.0 - beta2) * g * g;
+        double mh = m[i] / c1, vh = v[i] / c2;
+        params[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
