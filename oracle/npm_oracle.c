@@ -407,6 +407,9 @@ static void oracle_sample_one(const npmo_net *net, const oracle_lobe *lob, const
     const oracle_lobe *b = &lob[sel];
     double kappa = b->kappa;
     double t = 1.0 + log1p((1.0 - u[1]) * expm1(-2.0 * kappa)) / kappa;
+    /* The inverse CDF is -1 at u1 = 0; e^{-2 kappa} underflows for large
+     * kappa and the formula then yields -inf, so bound t to [-1, 1].       */
+    t = fmin(1.0, fmax(-1.0, t));
     double s = sqrt(fmax(0.0, (1.0 - t) * (1.0 + t)));
     double psi = 2.0 * PI * u[2];
     double cp = cos(psi), sp = sin(psi);

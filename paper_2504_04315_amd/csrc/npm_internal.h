@@ -1,0 +1,137 @@
+// Internal host-side declarations of libnpm: the context, the derived network
+// description, and the launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "npm.h"
+
+namespace npm {
+
+constexpr int kLobes = 8;             // K (Sec. 5.3)
+constexpr int kOut = 4 * kLobes;      // raw outputs per vertex
+constexpr int kWave = 64;             // CDNA wavefront
+constexpr int kTile = 32;             // vertices per wave tile (32x32 MFMA)
+
+// Grid description passed to kernels by value.
+struct GridDesc {
+    uint32_t offset[NPM_MAX_LEVELS];  // first entry of each level
+    int32_t res[NPM_MAX_LEVELS];      // D_l
+    uint32_t hashed_mask;             // bit l set: level l is hashed
+    uint32_t table_mask;              // 2^log2T - 1
+    int32_t n_levels;
+    int32_t feat;
+};
+
+// MLP shape as the kernels see it: widths padded to MFMA tiles.
+struct MlpDesc {
+    int n_in, width, n_hidden;        // real sizes
+    int in_p, hid_p;                  // padded: in_p in {16, 32}, hid_p in {32, 64}
+    int64_t fwd_off[NPM_MAX_LAYERS];  // offset of each layer's image in the packed
+    int64_t bwd_off[NPM_MAX_LAYERS];  //   forward / backward weight images (elements)
+    int64_t fwd_elems, bwd_elems;
+};
+
+struct Net {
+    npm_config cfg;
+    npm_layout lay;
+    GridDesc grid;
+    MlpDesc mlp;
+};
+
+// Fills *net from *cfg; returns NPM_OK or NPM_ERR_INVALID_ARG with a message.
+npm_status describe(const npm_config *cfg, Net *net, std::string *err);
+
+// Per-kernel event timing.
+struct Timing {
+    bool enabled = false;
+    std::vector<std::string> names;
+    std::vector<int64_t> launches;
+    std::vector<double> total_ms;
+    struct Pending { int id; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> free_events;
+};
+
+}  // namespace npm
+
+struct npm_ctx {
+    npm::Net net;
+    int device = 0;
+    int64_t step = 0;
+    // FP32 master state, n_params each
+    float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+    // Low-precision copies (NPM_PREC_BF16): FP16 grid, BF16 packed MLP images
+    void *grid16 = nullptr;
+    // Packed MLP weight images (forward and backward), FP32 and BF16
+    float *mlp_img = nullptr;          // [fwd_elems + bwd_elems] FP32
+    void *mlp_img16 = nullptr;         // [fwd_elems + bwd_elems] BF16
+    // FP64 reduction scratch
+    double *partials = nullptr;        // kPartials doubles
+    double *stats = nullptr;           // 4 doubles: loss, gradnorm, spare
+    // Staged-path scratch, grown on demand
+    int64_t scratch_n = 0;
+    float *s_G = nullptr, *s_raw = nullptr, *s_acts = nullptr, *s_delta = nullptr,
+          *s_draw = nullptr, *s_dG = nullptr;
+    float *s_dw_part = nullptr;        // dW partials
+    int64_t dw_part_elems = 0;
+    npm::Timing timing;
+};
+
+namespace npm {
+
+constexpr int kPartials = 4096;        // FP64 partial slots per reduction
+
+// ---------------------------------------------------------------- launchers
+// All return hipSuccess or the first launch error.  `s` is the stream.
+struct Launch {
+    npm_ctx *ctx;
+    hipStream_t s;
+};
+
+// Timing bracket (no-op unless enabled).
+void timed_begin(npm_ctx *ctx, const char *name, hipStream_t s, int *token);
+void timed_end(npm_ctx *ctx, int token, hipStream_t s);
+
+// common kernels (k_common.hip)
+hipError_t launch_init_params(npm_ctx *ctx, hipStream_t s);
+hipError_t launch_pack_mlp(npm_ctx *ctx, hipStream_t s);
+hipError_t launch_refresh_lowp(npm_ctx *ctx, hipStream_t s);
+hipError_t launch_adam(npm_ctx *ctx, float *grad, double *gradnorm_out, hipStream_t s);
+hipError_t launch_reduce_partials(npm_ctx *ctx, int nparts, double *out, hipStream_t s);
+hipError_t launch_reduce_scaled(const double *part, int nparts, double scale, double *out,
+                                hipStream_t s);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
+
+// staged path (k_staged.hip)
+hipError_t staged_corner_index(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *idx,
+                               hipStream_t s);
+hipError_t staged_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, hipStream_t s);
+hipError_t staged_mlp_fwd(npm_ctx *ctx, int64_t n, const float *G, float *acts, float *raw,
+                          hipStream_t s);
+hipError_t staged_head(npm_ctx *ctx, int64_t n, const float *raw, const float *dir,
+                       uint64_t seed, uint32_t stream_id, float *lobes, float *pdf,
+                       float *sdir, float *spdf, hipStream_t s);
+hipError_t staged_loss_grad(npm_ctx *ctx, int64_t n, const float *raw, const float *dir,
+                            const float *rad, const float *spdf, float *draw, double *loss_out,
+                            hipStream_t s);
+hipError_t staged_mlp_bwd(npm_ctx *ctx, int64_t n, const float *draw, const float *acts,
+                          float *delta, float *dG, hipStream_t s);
+hipError_t staged_mlp_dw(npm_ctx *ctx, int64_t n, const float *G, const float *acts,
+                         const float *delta, const float *draw, float *grad, hipStream_t s);
+hipError_t staged_scatter(npm_ctx *ctx, int64_t n, const float *pos, const float *dG,
+                          float *grad, hipStream_t s);
+
+// fused path (k_fused.hip)
+hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                       uint64_t seed, uint32_t stream_id, float *lobes, float *pdf, float *sdir,
+                       float *spdf, hipStream_t s);
+hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                          const float *rad, const float *spdf, float *grad, double *loss_out,
+                          hipStream_t s);
+
+}  // namespace npm

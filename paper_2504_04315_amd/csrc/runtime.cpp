@@ -1,0 +1,594 @@
+// libnpm C ABI: configuration and layout, context lifetime, argument
+// validation, dispatch to the staged or fused kernels, state export/import
+// and kernel timing.  No C++ exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "npm_internal.h"
+
+using namespace npm;
+
+namespace {
+
+thread_local std::string g_err;
+
+npm_status fail(npm_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+npm_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? NPM_ERR_OOM : NPM_ERR_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define NPM_HIP(call, what)                                \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, what);   \
+    } while (0)
+
+bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// Configuration and layout (Sec. 5.1 grid levels, Sec. 5.3 MLP)
+// --------------------------------------------------------------------------
+npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
+{
+    auto bad = [&](const char *m) { *err = m; return NPM_ERR_INVALID_ARG; };
+    if (!cfg || !net) return bad("null argument");
+    const npm_config &c = *cfg;
+    if (c.grid_kind != NPM_GRID_DENSE && c.grid_kind != NPM_GRID_HASH) return bad("grid_kind");
+    if (c.n_levels < 1 || c.n_levels > NPM_MAX_LEVELS) return bad("n_levels must be 1..32");
+    if (c.feat_per_level != 1 && c.feat_per_level != 2 && c.feat_per_level != 4)
+        return bad("feat_per_level must be 1, 2 or 4");
+    if (c.n_levels * c.feat_per_level > 32) return bad("n_levels * feat_per_level must be <= 32");
+    if (c.grid_kind == NPM_GRID_HASH && (c.log2_table_size < 4 || c.log2_table_size > 26))
+        return bad("log2_table_size must be 4..26");
+    if (c.base_resolution < 1 || c.max_resolution < c.base_resolution ||
+        c.max_resolution > 65535)
+        return bad("resolutions must satisfy 1 <= base <= max <= 65535");
+    if (c.mlp_width < 1 || c.mlp_width > 64) return bad("mlp_width must be 1..64");
+    if (c.mlp_hidden_layers < 1 || c.mlp_hidden_layers > 4) return bad("mlp_hidden_layers must be 1..4");
+    if (c.n_lobes != kLobes) return bad("n_lobes must be 8");
+    if (c.precision != NPM_PREC_FP32 && c.precision != NPM_PREC_BF16) return bad("precision");
+    if (c.exec_mode != NPM_EXEC_STAGED && c.exec_mode != NPM_EXEC_FUSED) return bad("exec_mode");
+    if (c.precision == NPM_PREC_BF16 && c.exec_mode != NPM_EXEC_FUSED)
+        return bad("the BF16 precision form runs fused only");
+    if (c.grid_init != NPM_INIT_NORMAL && c.grid_init != NPM_INIT_UNIFORM) return bad("grid_init");
+    if (!(std::isfinite(c.grid_init_scale) && c.grid_init_scale >= 0.0f)) return bad("grid_init_scale");
+    if (!(std::isfinite(c.lr) && c.lr > 0.0f)) return bad("lr must be > 0");
+    if (!(c.beta1 >= 0.0f && c.beta1 < 1.0f && c.beta2 >= 0.0f && c.beta2 < 1.0f))
+        return bad("betas must be in [0, 1)");
+    if (!(std::isfinite(c.eps) && c.eps > 0.0f)) return bad("eps must be > 0");
+
+    Net n{};
+    n.cfg = c;
+    npm_layout &L = n.lay;
+    const int nl = c.n_levels;
+    int64_t entries = 0;
+    const double ratio = (double)c.max_resolution / (double)c.base_resolution;
+    for (int l = 0; l < nl; ++l) {
+        int D;
+        if (l == nl - 1) D = c.max_resolution;
+        else if (l == 0) D = c.base_resolution;
+        else {
+            const double b = std::exp(std::log(ratio) / (double)(nl - 1));
+            D = (int)std::floor((double)c.base_resolution * std::pow(b, (double)l) + 1e-6);
+        }
+        const int64_t pts = (int64_t)(D + 1) * (D + 1) * (D + 1);
+        const bool hashed = c.grid_kind == NPM_GRID_HASH && pts > ((int64_t)1 << c.log2_table_size);
+        L.resolution[l] = D;
+        L.hashed[l] = hashed ? 1 : 0;
+        L.level_size[l] = hashed ? ((int64_t)1 << c.log2_table_size) : pts;
+        L.level_offset[l] = entries;
+        entries += L.level_size[l];
+        if (entries > ((int64_t)1 << 31) - 1) return bad("grid too large (more than 2^31 entries)");
+    }
+    L.grid_entries = entries;
+    L.grid_params = entries * c.feat_per_level;
+    L.n_in = nl * c.feat_per_level;
+    L.n_out = 4 * kLobes;
+    L.n_layers = c.mlp_hidden_layers + 1;
+    int64_t off = L.grid_params;
+    for (int i = 0; i < L.n_layers; ++i) {
+        L.layer_in[i] = (i == 0) ? L.n_in : c.mlp_width;
+        L.layer_out[i] = (i == L.n_layers - 1) ? L.n_out : c.mlp_width;
+        L.layer_offset[i] = off;
+        off += (int64_t)L.layer_in[i] * L.layer_out[i];
+    }
+    L.n_params = off;
+
+    GridDesc &g = n.grid;
+    for (int l = 0; l < nl; ++l) {
+        g.offset[l] = (uint32_t)L.level_offset[l];
+        g.res[l] = L.resolution[l];
+        if (L.hashed[l]) g.hashed_mask |= 1u << l;
+    }
+    g.table_mask = c.grid_kind == NPM_GRID_HASH ? (uint32_t)((1u << c.log2_table_size) - 1u) : 0u;
+    g.n_levels = nl;
+    g.feat = c.feat_per_level;
+
+    MlpDesc &m = n.mlp;
+    m.n_in = L.n_in;
+    m.width = c.mlp_width;
+    m.n_hidden = c.mlp_hidden_layers;
+    m.in_p = L.n_in <= 16 ? 16 : 32;
+    m.hid_p = c.mlp_width <= 32 ? 32 : 64;
+    int64_t fo = 0;
+    for (int i = 0; i < L.n_layers; ++i) {
+        const int in_p = i == 0 ? m.in_p : m.hid_p;
+        const int out_p = i == L.n_layers - 1 ? 32 : m.hid_p;
+        m.fwd_off[i] = fo;
+        fo += (int64_t)in_p * out_p;
+    }
+    m.fwd_elems = fo;
+    int64_t bo = 0;   // backward images from the last layer to the first
+    for (int i = L.n_layers - 1; i >= 0; --i) {
+        const int in_p = i == 0 ? m.in_p : m.hid_p;
+        const int out_p = i == L.n_layers - 1 ? 32 : m.hid_p;
+        m.bwd_off[i] = bo;
+        bo += (int64_t)std::max(in_p, 32) * out_p;
+    }
+    m.bwd_elems = bo;
+    const int64_t img = m.fwd_elems + m.bwd_elems;
+    L.device_bytes = 16 * L.n_params + 6 * img + (int64_t)kPartials * 8 + 64 +
+                     (c.precision == NPM_PREC_BF16 ? 2 * L.grid_params : 0);
+    *net = n;
+    return NPM_OK;
+}
+
+// --------------------------------------------------------------------------
+extern "C" {
+
+const char *npm_last_error(void) { return g_err.c_str(); }
+
+const char *npm_version(void) { return "npm-mi355x 0.1 (gfx950)"; }
+
+npm_status npm_config_default(npm_config *cfg)
+{
+    if (!cfg) return fail(NPM_ERR_INVALID_ARG, "null cfg");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->grid_kind = NPM_GRID_HASH;
+    cfg->n_levels = 16;
+    cfg->feat_per_level = 2;
+    cfg->log2_table_size = 19;
+    cfg->base_resolution = 16;
+    cfg->max_resolution = 2048;
+    cfg->mlp_width = 64;
+    cfg->mlp_hidden_layers = 2;
+    cfg->n_lobes = kLobes;
+    cfg->precision = NPM_PREC_FP32;
+    cfg->exec_mode = NPM_EXEC_STAGED;
+    cfg->grid_init = NPM_INIT_UNIFORM;
+    cfg->grid_init_scale = 1e-4f;
+    cfg->lr = 5e-3f;
+    cfg->beta1 = 0.9f;
+    cfg->beta2 = 0.999f;
+    cfg->eps = 1e-8f;
+    cfg->seed = 1;
+    return NPM_OK;
+}
+
+npm_status npm_get_layout(const npm_config *cfg, npm_layout *out)
+{
+    if (!cfg || !out) return fail(NPM_ERR_INVALID_ARG, "null argument");
+    Net net;
+    std::string err;
+    npm_status st = describe(cfg, &net, &err);
+    if (st != NPM_OK) return fail(st, "invalid config: " + err);
+    *out = net.lay;
+    return NPM_OK;
+}
+
+static void free_scratch(npm_ctx *ctx)
+{
+    for (float **p : {&ctx->s_G, &ctx->s_raw, &ctx->s_acts, &ctx->s_delta, &ctx->s_draw, &ctx->s_dG}) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    ctx->scratch_n = 0;
+}
+
+static void free_ctx(npm_ctx *ctx)
+{
+    free_scratch(ctx);
+    for (void *p : {(void *)ctx->params, (void *)ctx->grads, (void *)ctx->adam_m,
+                    (void *)ctx->adam_v, ctx->grid16, (void *)ctx->mlp_img, ctx->mlp_img16,
+                    (void *)ctx->partials, (void *)ctx->stats, (void *)ctx->s_dw_part})
+        if (p) hipFree(p);
+    for (auto &p : ctx->timing.pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+    for (auto e : ctx->timing.free_events) hipEventDestroy(e);
+    delete ctx;
+}
+
+npm_status npm_create(const npm_config *cfg, npm_ctx **out)
+{
+    if (!cfg || !out) return fail(NPM_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    Net net;
+    std::string err;
+    npm_status st = describe(cfg, &net, &err);
+    if (st != NPM_OK) return fail(st, "invalid config: " + err);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(NPM_ERR_NO_DEVICE, "no HIP device");
+    int dev = 0;
+    NPM_HIP(hipGetDevice(&dev), "hipGetDevice");
+    hipDeviceProp_t prop;
+    NPM_HIP(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(NPM_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName +
+                                           ", the library is built for gfx950");
+    npm_ctx *ctx = new (std::nothrow) npm_ctx();
+    if (!ctx) return fail(NPM_ERR_OOM, "host allocation");
+    ctx->net = net;
+    ctx->device = dev;
+    const int64_t np = net.lay.n_params;
+    const int64_t img = net.mlp.fwd_elems + net.mlp.bwd_elems;
+    int64_t max_layer = 0;
+    for (int i = 0; i < net.lay.n_layers; ++i)
+        max_layer = std::max<int64_t>(max_layer, (int64_t)net.lay.layer_in[i] * net.lay.layer_out[i]);
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void **p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, bytes);
+    };
+    alloc((void **)&ctx->params, np * 4);
+    alloc((void **)&ctx->grads, np * 4);
+    alloc((void **)&ctx->adam_m, np * 4);
+    alloc((void **)&ctx->adam_v, np * 4);
+    alloc((void **)&ctx->mlp_img, img * 4);
+    alloc((void **)&ctx->mlp_img16, img * 2);
+    alloc((void **)&ctx->partials, kPartials * 8);
+    alloc((void **)&ctx->stats, 64);
+    // weight-gradient partials: 256 blocks x one layer (staged) or 1024 waves x
+    // all MLP weights (fused)
+    const int64_t mlp_w = np - net.lay.grid_params;
+    alloc((void **)&ctx->s_dw_part, std::max<int64_t>(256 * max_layer, 1024 * mlp_w) * 4);
+    if (net.cfg.precision == NPM_PREC_BF16) alloc(&ctx->grid16, net.lay.grid_params * 2);
+    if (e == hipSuccess) e = hipMemset(ctx->grads, 0, np * 4);
+    if (e == hipSuccess) e = hipMemset(ctx->adam_m, 0, np * 4);
+    if (e == hipSuccess) e = hipMemset(ctx->adam_v, 0, np * 4);
+    if (e == hipSuccess) e = launch_init_params(ctx, nullptr);
+    if (e == hipSuccess) e = launch_refresh_lowp(ctx, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_ctx(ctx);
+        return hip_fail(e, "npm_create");
+    }
+    *out = ctx;
+    return NPM_OK;
+}
+
+npm_status npm_destroy(npm_ctx *ctx)
+{
+    if (!ctx) return NPM_OK;
+    hipDeviceSynchronize();
+    free_ctx(ctx);
+    return NPM_OK;
+}
+
+static hipError_t ensure_scratch(npm_ctx *ctx, int64_t n)
+{
+    if (n <= ctx->scratch_n) return hipSuccess;
+    // buffers may still be in use by queued work
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    free_scratch(ctx);
+    const MlpDesc &m = ctx->net.mlp;
+    const size_t f = sizeof(float);
+    auto alloc = [&](float **p, int64_t elems) {
+        if (e == hipSuccess) e = hipMalloc((void **)p, (size_t)elems * f);
+    };
+    alloc(&ctx->s_G, (int64_t)m.n_in * n);
+    alloc(&ctx->s_raw, (int64_t)kOut * n);
+    alloc(&ctx->s_acts, (int64_t)m.n_hidden * m.width * n);
+    alloc(&ctx->s_delta, (int64_t)m.n_hidden * m.width * n);
+    alloc(&ctx->s_draw, (int64_t)kOut * n);
+    alloc(&ctx->s_dG, (int64_t)m.n_in * n);
+    if (e != hipSuccess) { free_scratch(ctx); return e; }
+    ctx->scratch_n = n;
+    return hipSuccess;
+}
+
+static npm_status check_batch(npm_ctx *ctx, int64_t n, const float *pos)
+{
+    if (!ctx) return fail(NPM_ERR_INVALID_ARG, "null context");
+    if (n < 0 || n > ((int64_t)1 << 31) - 1) return fail(NPM_ERR_INVALID_ARG, "n out of range");
+    if (n > 0 && (!pos || !aligned4(pos))) return fail(NPM_ERR_INVALID_ARG, "pos must be a 4-byte aligned device pointer");
+    return NPM_OK;
+}
+
+npm_status npm_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                     uint64_t rng_seed, uint32_t rng_stream, float *lobes, float *pdf,
+                     float *sample_dir, float *sample_pdf, void *stream)
+{
+    npm_status st = check_batch(ctx, n, pos);
+    if (st != NPM_OK) return st;
+    if (pdf && !dir) return fail(NPM_ERR_INVALID_ARG, "pdf needs dir");
+    for (const void *p : {(const void *)dir, (const void *)lobes, (const void *)pdf,
+                          (const void *)sample_dir, (const void *)sample_pdf})
+        if (p && !aligned4(p)) return fail(NPM_ERR_INVALID_ARG, "misaligned buffer");
+    if (n == 0) return NPM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
+            NPM_HIP(fused_query(ctx, n, pos, dir, rng_seed, rng_stream, lobes, pdf, sample_dir,
+                                sample_pdf, s), "fused query");
+            return NPM_OK;
+        }
+        NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
+        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");
+        NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s), "mlp forward");
+        if (lobes || pdf || sample_dir || sample_pdf)
+            NPM_HIP(staged_head(ctx, n, ctx->s_raw, dir, rng_seed, rng_stream, lobes, pdf,
+                                sample_dir, sample_pdf, s), "head");
+    } catch (...) {
+        return fail(NPM_ERR_HIP, "unexpected exception");
+    }
+    return NPM_OK;
+}
+
+static npm_status check_train(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                              const float *rad, const float *spdf)
+{
+    npm_status st = check_batch(ctx, n, pos);
+    if (st != NPM_OK) return st;
+    if (n > 0) {
+        for (const void *p : {(const void *)dir, (const void *)rad, (const void *)spdf})
+            if (!p || !aligned4(p))
+                return fail(NPM_ERR_INVALID_ARG, "dir, radiance and sampling_pdf are required device pointers");
+    }
+    return NPM_OK;
+}
+
+static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                                const float *rad, const float *spdf, float *grad, double *loss_out,
+                                hipStream_t s)
+{
+    if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
+        NPM_HIP(fused_backward(ctx, n, pos, dir, rad, spdf, grad, loss_out, s), "fused backward");
+        return NPM_OK;
+    }
+    NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
+    NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");
+    NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, ctx->s_acts, ctx->s_raw, s), "mlp forward");
+    NPM_HIP(staged_loss_grad(ctx, n, ctx->s_raw, dir, rad, spdf, ctx->s_draw, loss_out, s),
+            "loss gradient");
+    NPM_HIP(staged_mlp_bwd(ctx, n, ctx->s_draw, ctx->s_acts, ctx->s_delta, ctx->s_dG, s),
+            "mlp backward");
+    NPM_HIP(staged_mlp_dw(ctx, n, ctx->s_G, ctx->s_acts, ctx->s_delta, ctx->s_draw, grad, s),
+            "weight gradient");
+    NPM_HIP(staged_scatter(ctx, n, pos, ctx->s_dG, grad, s), "grid scatter");
+    return NPM_OK;
+}
+
+npm_status npm_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                        const float *radiance, const float *sampling_pdf, float *grad_out,
+                        double *loss_out, void *stream)
+{
+    npm_status st = check_train(ctx, n, pos, dir, radiance, sampling_pdf);
+    if (st != NPM_OK) return st;
+    if (grad_out && !aligned4(grad_out)) return fail(NPM_ERR_INVALID_ARG, "misaligned grad_out");
+    if (n == 0) return NPM_OK;
+    try {
+        return backward_impl(ctx, n, pos, dir, radiance, sampling_pdf,
+                             grad_out ? grad_out : ctx->grads, loss_out, (hipStream_t)stream);
+    } catch (...) {
+        return fail(NPM_ERR_HIP, "unexpected exception");
+    }
+}
+
+npm_status npm_loss(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                    const float *radiance, const float *sampling_pdf, double *loss_out,
+                    void *stream)
+{
+    npm_status st = check_train(ctx, n, pos, dir, radiance, sampling_pdf);
+    if (st != NPM_OK) return st;
+    if (n == 0) return NPM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
+        if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED && ctx->net.cfg.precision == NPM_PREC_BF16) {
+            // the loss of the precision form: the fused kernel with no gradient output
+            NPM_HIP(fused_backward(ctx, n, pos, dir, radiance, sampling_pdf, nullptr, loss_out, s),
+                    "fused loss");
+            return NPM_OK;
+        }
+        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");
+        NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s), "mlp forward");
+        NPM_HIP(staged_loss_grad(ctx, n, ctx->s_raw, dir, radiance, sampling_pdf, ctx->s_draw,
+                                 loss_out, s), "loss");
+    } catch (...) {
+        return fail(NPM_ERR_HIP, "unexpected exception");
+    }
+    return NPM_OK;
+}
+
+npm_status npm_optimizer_step(npm_ctx *ctx, float *grad, double *gradnorm_out, void *stream)
+{
+    if (!ctx) return fail(NPM_ERR_INVALID_ARG, "null context");
+    if (grad && !aligned4(grad)) return fail(NPM_ERR_INVALID_ARG, "misaligned grad");
+    ctx->step += 1;
+    hipError_t e = launch_adam(ctx, grad ? grad : ctx->grads, gradnorm_out, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        ctx->step -= 1;
+        return hip_fail(e, "adam");
+    }
+    return NPM_OK;
+}
+
+npm_status npm_train_step(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                          const float *radiance, const float *sampling_pdf, double *stats_out,
+                          void *stream)
+{
+    npm_status st = check_train(ctx, n, pos, dir, radiance, sampling_pdf);
+    if (st != NPM_OK) return st;
+    if (n > 0) {
+        try {
+            st = backward_impl(ctx, n, pos, dir, radiance, sampling_pdf, ctx->grads,
+                               stats_out, (hipStream_t)stream);
+        } catch (...) {
+            return fail(NPM_ERR_HIP, "unexpected exception");
+        }
+        if (st != NPM_OK) return st;
+    }
+    return npm_optimizer_step(ctx, nullptr, stats_out ? stats_out + 1 : nullptr, stream);
+}
+
+npm_status npm_corner_index(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *idx, void *stream)
+{
+    npm_status st = check_batch(ctx, n, pos);
+    if (st != NPM_OK) return st;
+    if (n > 0 && (!idx || !aligned4(idx))) return fail(NPM_ERR_INVALID_ARG, "idx required");
+    if (n == 0) return NPM_OK;
+    NPM_HIP(staged_corner_index(ctx, n, pos, idx, (hipStream_t)stream), "corner index");
+    return NPM_OK;
+}
+
+npm_status npm_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, void *stream)
+{
+    npm_status st = check_batch(ctx, n, pos);
+    if (st != NPM_OK) return st;
+    if (n > 0 && (!G || !aligned4(G))) return fail(NPM_ERR_INVALID_ARG, "G required");
+    if (n == 0) return NPM_OK;
+    NPM_HIP(staged_encode(ctx, n, pos, G, (hipStream_t)stream), "encode");
+    return NPM_OK;
+}
+
+npm_status npm_forward_raw(npm_ctx *ctx, int64_t n, const float *pos, float *raw, void *stream)
+{
+    npm_status st = check_batch(ctx, n, pos);
+    if (st != NPM_OK) return st;
+    if (n > 0 && (!raw || !aligned4(raw))) return fail(NPM_ERR_INVALID_ARG, "raw required");
+    if (n == 0) return NPM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
+    NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");
+    NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, raw, s), "mlp forward");
+    return NPM_OK;
+}
+
+static float *state_buf(npm_ctx *ctx, int which)
+{
+    switch (which) {
+    case NPM_STATE_PARAMS: return ctx->params;
+    case NPM_STATE_GRADS: return ctx->grads;
+    case NPM_STATE_ADAM_M: return ctx->adam_m;
+    case NPM_STATE_ADAM_V: return ctx->adam_v;
+    default: return nullptr;
+    }
+}
+
+npm_status npm_get_state(npm_ctx *ctx, int which, float *host, int64_t count)
+{
+    if (!ctx || !host) return fail(NPM_ERR_INVALID_ARG, "null argument");
+    float *src = state_buf(ctx, which);
+    if (!src) return fail(NPM_ERR_INVALID_ARG, "unknown state buffer");
+    if (count != ctx->net.lay.n_params) return fail(NPM_ERR_INVALID_ARG, "count must equal n_params");
+    NPM_HIP(hipDeviceSynchronize(), "synchronize");
+    NPM_HIP(hipMemcpy(host, src, count * 4, hipMemcpyDeviceToHost), "copy state");
+    return NPM_OK;
+}
+
+npm_status npm_set_state(npm_ctx *ctx, int which, const float *host, int64_t count)
+{
+    if (!ctx || !host) return fail(NPM_ERR_INVALID_ARG, "null argument");
+    float *dst = state_buf(ctx, which);
+    if (!dst) return fail(NPM_ERR_INVALID_ARG, "unknown state buffer");
+    if (count != ctx->net.lay.n_params) return fail(NPM_ERR_INVALID_ARG, "count must equal n_params");
+    NPM_HIP(hipDeviceSynchronize(), "synchronize");
+    NPM_HIP(hipMemcpy(dst, host, count * 4, hipMemcpyHostToDevice), "copy state");
+    if (which == NPM_STATE_PARAMS) {
+        NPM_HIP(launch_refresh_lowp(ctx, nullptr), "refresh packed weights");
+        NPM_HIP(hipDeviceSynchronize(), "synchronize");
+    }
+    return NPM_OK;
+}
+
+npm_status npm_get_step(npm_ctx *ctx, int64_t *step)
+{
+    if (!ctx || !step) return fail(NPM_ERR_INVALID_ARG, "null argument");
+    *step = ctx->step;
+    return NPM_OK;
+}
+
+npm_status npm_set_step(npm_ctx *ctx, int64_t step)
+{
+    if (!ctx || step < 0) return fail(NPM_ERR_INVALID_ARG, "bad argument");
+    ctx->step = step;
+    return NPM_OK;
+}
+
+npm_status npm_state_device_ptr(npm_ctx *ctx, int which, void **ptr)
+{
+    if (!ctx || !ptr) return fail(NPM_ERR_INVALID_ARG, "null argument");
+    float *p = state_buf(ctx, which);
+    if (!p) return fail(NPM_ERR_INVALID_ARG, "unknown state buffer");
+    *ptr = p;
+    return NPM_OK;
+}
+
+npm_status npm_set_timing(npm_ctx *ctx, int enabled)
+{
+    if (!ctx) return fail(NPM_ERR_INVALID_ARG, "null context");
+    ctx->timing.enabled = enabled != 0;
+    return NPM_OK;
+}
+
+static hipError_t collect_timing(npm_ctx *ctx)
+{
+    Timing &t = ctx->timing;
+    if (t.pending.empty()) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    for (auto &p : t.pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            t.total_ms[p.id] += ms;
+            t.launches[p.id] += 1;
+        }
+        t.free_events.push_back(p.a);
+        t.free_events.push_back(p.b);
+    }
+    t.pending.clear();
+    return hipSuccess;
+}
+
+npm_status npm_kernel_times(npm_ctx *ctx, npm_kernel_time *out, int32_t cap, int32_t *count)
+{
+    if (!ctx || !count || (cap > 0 && !out)) return fail(NPM_ERR_INVALID_ARG, "null argument");
+    NPM_HIP(collect_timing(ctx), "collect timing");
+    const Timing &t = ctx->timing;
+    const int nk = (int)t.names.size();
+    for (int i = 0; i < nk && i < cap; ++i) {
+        std::memset(out[i].name, 0, sizeof(out[i].name));
+        std::strncpy(out[i].name, t.names[i].c_str(), sizeof(out[i].name) - 1);
+        out[i].launches = t.launches[i];
+        out[i].total_ms = t.total_ms[i];
+    }
+    *count = nk;
+    return NPM_OK;
+}
+
+npm_status npm_reset_timing(npm_ctx *ctx)
+{
+    if (!ctx) return fail(NPM_ERR_INVALID_ARG, "null context");
+    NPM_HIP(collect_timing(ctx), "collect timing");
+    Timing &t = ctx->timing;
+    std::fill(t.launches.begin(), t.launches.end(), 0);
+    std::fill(t.total_ms.begin(), t.total_ms.end(), 0.0);
+    return NPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+"""Tolerance policy of the GPU-vs-oracle parity tests (test infrastructure).
+
+The plain FP32 path must match the FP64 oracle to 1e-5 relative, with
+integer work (grid corner indices) bit-exact.  "Relative" is taken against the
+size of the terms that produce each value (its condition scale), because
+FP32 sums of terms of mixed sign have errors proportional to sum |term|, not
+to the (possibly cancelled) result:
+
+* encoding G and raw MLP outputs: |d| <= 1e-5 * max(|ref|, sum |terms|);
+* mapped lobe parameters: the raw error bound propagated through the
+  Table 1 mapping's derivative, plus 1e-5 relative on the value itself;
+* log pdf: 1e-5 + 1e-5 * sum_j |d logV / d raw_j| * scale_j
+  + 4 * kappa_max * 2^-23 (an ulp of mu.w amplified by kappa);
+* sampled directions (same uniforms): |d|_inf <= 2e-5 except samples whose
+  CDF margin is below 1e-5, where FP32 and FP64 may pick different lobes;
+* gradients: |d| <= 1e-5 * sum |contributions| (atomic order is unspecified).
+"""
+import numpy as np
+
+RTOL = 1e-5
+FP32_EPS = 2.0 ** -23
+
+
+def report(name, err, bound):
+    ratio = float(np.max(err / bound)) if err.size else 0.0
+    return f"{name}: max err {float(np.max(err)) if err.size else 0:.3e}, max err/bound {ratio:.3f}"
+
+
+def assert_within(name, got, ref, bound):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape, (name, got.shape, ref.shape)
+    err = np.abs(got - ref)
+    bad = ~(err <= bound)
+    if bad.any():
+        i = np.flatnonzero(bad.ravel())[:8]
+        raise AssertionError(f"{name}: {bad.sum()} of {bad.size} out of tolerance; e.g. "
+                             f"got {got.ravel()[i]} ref {ref.ravel()[i]} bound {bound.ravel()[i]}")
+    return report(name, err, bound)
+
+
+def check_scaled(name, got, ref, scale, rtol=RTOL):
+    ref = np.asarray(ref, dtype=np.float64)
+    bound = rtol * np.maximum(np.abs(ref), scale) + 1e-30
+    return assert_within(name, got, ref, bound)
+
+
+def check_lobes(got, ref, raw_scale, rtol=RTOL):
+    """got/ref: [n][K][4] (theta, phi, kappa, lambda); raw_scale [n][4K]."""
+    s = raw_scale.reshape(-1, 8, 4)
+    th, ph, ka, la = (ref[..., i] for i in range(4))
+    msgs = []
+    b = rtol * (th + th * (1 - th) * s[..., 0]) + 1e-30
+    msgs.append(assert_within("theta", got[..., 0], th, b))
+    b = rtol * (ph + ph * (1 - ph) * s[..., 1]) + 1e-30
+    msgs.append(assert_within("phi", got[..., 1], ph, b))
+    b = rtol * ka * (1 + s[..., 2])
+    msgs.append(assert_within("kappa", got[..., 2], ka, b))
+    b = rtol * la * (1 + 2 * s[..., 3].max(axis=1, keepdims=True))
+    msgs.append(assert_within("lambda", got[..., 3], la, b))
+    return msgs
+
+
+def logpdf_bound(dlogv_draw, raw_scale, kappa_max, rtol=RTOL):
+    sens = np.sum(np.abs(dlogv_draw) * raw_scale, axis=1)
+    return rtol * (1.0 + sens) + 4.0 * kappa_max * FP32_EPS
+
+
+def check_logpdf(name, got_pdf, ref_logpdf, bound):
+    with np.errstate(divide="ignore"):
+        lg = np.log(np.asarray(got_pdf, dtype=np.float64))
+    return assert_within(name, lg, ref_logpdf, bound)
+
+
+def check_grads(name, got, ref, gabs, rtol=RTOL, atol=1e-12):
+    bound = rtol * gabs + atol
+    return assert_within(name, got, ref, bound)

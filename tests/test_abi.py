@@ -1,0 +1,95 @@
+"""The C ABI of libnpm.so, checked without a GPU: the library loads, exports
+every entry point include/npm.h declares, validates its arguments before
+touching a device, and lays out a configuration exactly as the oracle does
+(grid resolutions, dense/hashed levels, offsets, flat parameter layout)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2504_04315_amd import npm as B
+from paper_2504_04315_amd import workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in ("npm.h",):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"^\s*(?:npm_status|const char \*)\s*(npm_\w+)\s*\(", text, re.M))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = B.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(B.SIGNATURES) <= names
+
+
+def test_version_and_last_error():
+    lib = B.lib()
+    assert b"gfx950" in lib.npm_version()
+    assert lib.npm_create(None, None) == -1
+    assert b"null" in lib.npm_last_error()
+
+
+@pytest.mark.parametrize("net", [W.CFG1, W.CFG2, W.CFG5, W.TINY], ids=["cfg1", "cfg2", "cfg5", "tiny"])
+def test_layout_matches_oracle(O, net):
+    cfg = B.make_config(net)
+    L = B.layout_of(cfg)
+    on = O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table, net.dense_only,
+               net.n_hidden, net.width, net.n_lobes)
+    assert L.n_params == on.n_params and L.grid_params == on.grid_params
+    assert L.grid_entries == on.grid_entries
+    for l in range(net.n_levels):
+        assert L.resolution[l] == on.res[l]
+        assert L.hashed[l] == on.hashed[l]
+        assert L.level_size[l] == on.level_size[l]
+        assert L.level_offset[l] == on.level_offset[l]
+    assert L.n_layers == len(on.layer_offset)
+    for i in range(L.n_layers):
+        assert L.layer_offset[i] == on.layer_offset[i]
+        assert (L.layer_out[i], L.layer_in[i]) == on.layer_shape[i]
+
+
+def test_invalid_configs_rejected_without_device():
+    lib = B.lib()
+    base = B.make_config(W.CFG2)
+    out = B.npm_layout()
+    for field, value in [("n_levels", 0), ("n_levels", 33), ("feat_per_level", 3),
+                         ("n_lobes", 4), ("mlp_width", 65), ("mlp_hidden_layers", 0),
+                         ("log2_table_size", 40), ("precision", 7), ("lr", -1.0),
+                         ("beta1", 1.0), ("max_resolution", 8)]:
+        c = B.npm_config.from_buffer_copy(base)
+        setattr(c, field, value)
+        assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1, field
+        ctx = C.c_void_p()
+        assert lib.npm_create(C.byref(c), C.byref(ctx)) == -1, field
+        assert not ctx
+    c = B.npm_config.from_buffer_copy(base)
+    c.precision = B.PREC_BF16
+    c.exec_mode = B.EXEC_STAGED
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = B.lib()
+    assert lib.npm_destroy(None) == 0
+    assert lib.npm_query(None, 10, None, None, 0, 0, None, None, None, None, None) == -1
+    assert lib.npm_train_step(None, 10, None, None, None, None, None, None) == -1
+    assert lib.npm_optimizer_step(None, None, None, None) == -1
+    assert lib.npm_get_state(None, 0, None, 0) == -1
+
+
+def test_create_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cfg = B.make_config(W.CFG1)
+    ctx = C.c_void_p()
+    assert B.lib().npm_create(C.byref(cfg), C.byref(ctx)) == -2

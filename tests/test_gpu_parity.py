@@ -1,0 +1,260 @@
+"""GPU parity of the FP32 hot path against the FP64 oracle, through the C ABI.
+
+Each step is checked on identical FP32 inputs and the GPU context's own
+initial parameters (exported with npm_get_state): corner indices bit-exact,
+then encoding, raw MLP outputs, Table 1 lobe parameters, mixture pdf, samples
+drawn with the same Philox uniforms, the loss and every gradient entry, and
+the Adam update.  The tolerance policy is documented in tests/parity.py.
+
+Workloads: cfg1 (dense 4-level grid, 16,384 vertices) whole; cfg2 (16-level
+hash grid, 2^20 vertices) run whole on the GPU and checked on 4,096 sampled
+vertices for the query, and on a 16,384-vertex batch for training.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import parity as P
+from paper_2504_04315_amd import npm as B
+from paper_2504_04315_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"staged": B.EXEC_STAGED, "fused": B.EXEC_FUSED}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a device"
+    return T
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def adam_hp(net):
+    """Adam hyper-parameters as the library holds them (float32 values)."""
+    f = lambda x: float(np.float32(x))
+    return dict(lr=f(net.lr), beta1=f(net.beta1), beta2=f(net.beta2), eps=f(net.eps))
+
+
+def oracle_net(O, net):
+    return O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table,
+                 net.dense_only, net.n_hidden, net.width, net.n_lobes)
+
+
+def randomize(model, on, rng, grid_sd=1.0, mlp_gain=2.0):
+    """Parameters with a wider spread than at init, so the head sees varied
+    lobes (kappa over a few e-folds); set through the C ABI."""
+    p = np.zeros(on.n_params, dtype=np.float32)
+    p[:on.grid_params] = rng.normal(0, grid_sd, on.grid_params)
+    for i, (o, k) in enumerate(on.layer_shape):
+        a = mlp_gain * math.sqrt(6.0 / (o + k)) / math.sqrt(k / 8.0)
+        off = on.layer_offset[i]
+        p[off:off + o * k] = rng.uniform(-a, a, o * k)
+    model.set_state(p)
+    return p.astype(np.float64)
+
+
+def check_query(O, torch, model, on, params, batch, idx=None, seed=11, sid=3):
+    """Runs npm_query on the whole batch and checks it (at idx if given)."""
+    n = batch.n
+    pos, dirs = dev(torch, batch.pos), dev(torch, batch.dir)
+    out = model.query(pos, dirs, seed=seed, stream_id=sid)
+    torch.cuda.synchronize()
+    sel = np.arange(n) if idx is None else idx
+    sub = batch.subset(sel)
+    q = O.query(on, sub.pos, params, dirs=sub.dir, seed=seed, stream=sid, vid=sel)
+    raw_ref, raw_scale = O.mlp_forward(on, q["G"], params, with_scale=True)
+    msgs = []
+    lob = out["lobes"].cpu().numpy()[:, :, sel].transpose(2, 1, 0)
+    msgs += P.check_lobes(lob, q["lobes"], raw_scale)
+    # log pdf at the given directions
+    ones = np.ones(len(sel), dtype=np.float32)
+    _, d = O.loss_grad(on, q["raw"], sub.dir, ones, ones, n_total=1)
+    kmax = q["lobes"][..., 2].max(axis=1)
+    msgs.append(P.check_logpdf("pdf", out["pdf"].cpu().numpy()[sel], q["logpdf"],
+                               P.logpdf_bound(d, raw_scale, kmax)))
+    # samples: same uniforms; skip the ones at a CDF boundary
+    sd = out["sample_dir"].cpu().numpy()[:, sel].T
+    keep = q["margin"] > 1e-5
+    assert keep.mean() > 0.999
+    msgs.append(P.assert_within("sample_dir", sd[keep], q["sdir"][keep],
+                                np.full((keep.sum(), 3), 2e-5)))
+    _, d2 = O.loss_grad(on, q["raw"][keep], q["sdir"][keep].T.astype(np.float32), ones[keep],
+                        ones[keep], n_total=1)
+    msgs.append(P.check_logpdf("sample_pdf", out["sample_pdf"].cpu().numpy()[sel][keep],
+                               q["slogpdf"][keep],
+                               P.logpdf_bound(d2, raw_scale[keep], kmax[keep]) + 1e-4))
+    return msgs, q
+
+
+def check_stages(O, torch, model, on, params, pos_np):
+    n = pos_np.shape[1]
+    pos = dev(torch, pos_np)
+    idx = model.corner_index(pos).cpu().numpy().astype(np.uint32)
+    oidx, _ = O.corners(on, pos_np)
+    assert np.array_equal(idx.transpose(2, 0, 1).astype(np.int64), oidx), "corner indices differ"
+    G = model.encode(pos).cpu().numpy().T
+    Gr, Gs = O.encode(on, pos_np, params, with_scale=True)
+    msgs = [P.check_scaled("encode", G, Gr, Gs)]
+    raw = model.forward_raw(pos).cpu().numpy().T
+    rr, rs = O.mlp_forward(on, Gr, params, with_scale=True)
+    msgs.append(P.check_scaled("raw", raw, rr, rs))
+    return msgs
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+@pytest.mark.parametrize("params_kind", ["init", "random"])
+def test_cfg1_query_parity(O, torch, mode, params_kind):
+    model = B.NPM(B.make_config(W.CFG1, exec_mode=MODES[mode]))
+    on = oracle_net(O, W.CFG1)
+    rng = np.random.default_rng(5)
+    params = (model.get_state().astype(np.float64) if params_kind == "init"
+              else randomize(model, on, rng))
+    batch = W.make_batch("cube", W.N_CFG1, seed=1)
+    msgs = check_stages(O, torch, model, on, params, batch.pos)
+    edge = W.edge_positions(rng, 4096, on.res)
+    msgs += check_stages(O, torch, model, on, params, edge)
+    m2, _ = check_query(O, torch, model, on, params, batch)
+    print("\n".join(msgs + m2))
+    model.close()
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_cfg2_query_parity_full_batch(O, torch, mode):
+    model = B.NPM(B.make_config(W.CFG2, exec_mode=MODES[mode]))
+    on = oracle_net(O, W.CFG2)
+    rng = np.random.default_rng(6)
+    params = randomize(model, on, rng, grid_sd=0.5)
+    batch = W.make_batch("surface", W.N_CFG2, seed=2)
+    sel = np.sort(rng.choice(batch.n, 4096, replace=False))
+    sel[-1] = batch.n - 1                          # the ragged end of the batch
+    msgs = check_stages(O, torch, model, on, params, batch.subset(sel).pos)
+    m2, _ = check_query(O, torch, model, on, params, batch, idx=sel)
+    print("\n".join(msgs + m2))
+    model.close()
+
+
+def check_backward(O, torch, model, on, params, batch, tag):
+    pos, dirs = dev(torch, batch.pos), dev(torch, batch.dir)
+    rad, pdf = dev(torch, batch.radiance), dev(torch, batch.pdf)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(on.n_params, dtype=torch.float32, device="cuda")
+    model.backward(pos, dirs, rad, pdf, grad=grad, loss=loss)
+    torch.cuda.synchronize()
+    ref = O.backward(on, batch.pos, batch.dir, batch.radiance, batch.pdf, params)
+    g = grad.cpu().numpy().astype(np.float64)
+    msgs = [P.check_grads(f"{tag} grad(grid)", g[:on.grid_params], ref["grad"][:on.grid_params],
+                          ref["gabs"][:on.grid_params]),
+            P.check_grads(f"{tag} grad(mlp)", g[on.grid_params:], ref["grad"][on.grid_params:],
+                          ref["gabs"][on.grid_params:])]
+    lv = float(loss.cpu().numpy()[0])
+    assert abs(lv - ref["loss"]) <= 1e-5 * max(1.0, abs(ref["loss"])), (lv, ref["loss"])
+    msgs.append(f"{tag} loss {lv:.9g} vs oracle {ref['loss']:.9g}")
+    return msgs, g, ref
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_cfg1_train_step_parity(O, torch, mode):
+    model = B.NPM(B.make_config(W.CFG1, exec_mode=MODES[mode]))
+    on = oracle_net(O, W.CFG1)
+    params = randomize(model, on, np.random.default_rng(7))
+    batch = W.make_batch("cube", W.N_CFG1, seed=1)
+    msgs, g, ref = check_backward(O, torch, model, on, params, batch, "cfg1")
+    # Adam on the identical gradient buffer
+    model.set_state(g.astype(np.float32), B.STATE_GRADS)
+    gn = torch.zeros(1, dtype=torch.float64, device="cuda")
+    model.optimizer_step(gradnorm=gn)
+    torch.cuda.synchronize()
+    p_gpu = model.get_state().astype(np.float64)
+    p_ref, m, v = params.copy(), np.zeros(on.n_params), np.zeros(on.n_params)
+    O.adam(p_ref, g.copy(), m, v, 1, **adam_hp(W.CFG1))
+    msgs.append(P.check_scaled("adam params", p_gpu, p_ref, np.abs(p_ref - params) + 1e-30))
+    assert float(gn.cpu()[0]) == pytest.approx(float(np.sum(g * g)), rel=1e-6)
+    assert np.all(model.get_state(B.STATE_GRADS) == 0)      # the step consumes the gradient
+    assert model.step == 1
+    np.testing.assert_allclose(model.get_state(B.STATE_ADAM_M), m, rtol=2e-6, atol=1e-30)
+    np.testing.assert_allclose(model.get_state(B.STATE_ADAM_V), v, rtol=4e-6, atol=1e-30)
+    print("\n".join(msgs))
+    model.close()
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_cfg2_backward_parity(O, torch, mode):
+    model = B.NPM(B.make_config(W.CFG2, exec_mode=MODES[mode]))
+    on = oracle_net(O, W.CFG2)
+    params = randomize(model, on, np.random.default_rng(8), grid_sd=0.5)
+    batch = W.make_batch("surface", 16384 + 17, seed=22)        # ragged tile count
+    msgs, _, _ = check_backward(O, torch, model, on, params, batch, "cfg2")
+    print("\n".join(msgs))
+    model.close()
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_full_train_step_against_oracle(O, torch, mode):
+    """npm_train_step = backward + Adam, parameter by parameter, over three
+    steps.  Each step starts the oracle from the GPU's parameters and moments,
+    so every comparison is one step from an identical state; the bound adds
+    the Adam update's spread under the gradient's own rounding uncertainty
+    (1e-6 of its sum of |contributions|), which covers entries whose
+    gradient is within rounding of zero."""
+    model = B.NPM(B.make_config(W.TINY, exec_mode=MODES[mode]))
+    on = oracle_net(O, W.TINY)
+    hp = adam_hp(W.TINY)
+    for t in range(1, 4):
+        p0 = model.get_state().astype(np.float64)
+        m0 = model.get_state(B.STATE_ADAM_M).astype(np.float64)
+        v0 = model.get_state(B.STATE_ADAM_V).astype(np.float64)
+        batch = W.make_batch("cube", 997, seed=100 + t)
+        stats = torch.zeros(2, dtype=torch.float64, device="cuda")
+        model.train_step(dev(torch, batch.pos), dev(torch, batch.dir), dev(torch, batch.radiance),
+                         dev(torch, batch.pdf), stats=stats)
+        torch.cuda.synchronize()
+        ref = O.backward(on, batch.pos, batch.dir, batch.radiance, batch.pdf, p0)
+        outs = []
+        for dg in (0.0, 2e-6, -2e-6):
+            p, m, v = p0.copy(), m0.copy(), v0.copy()
+            O.adam(p, ref["grad"] + dg * ref["gabs"], m, v, t, **hp)
+            outs.append(p)
+        st = stats.cpu().numpy()
+        assert st[0] == pytest.approx(ref["loss"], rel=1e-5)
+        assert st[1] == pytest.approx(float(np.sum(ref["grad"] ** 2)), rel=1e-4)
+        p_gpu = model.get_state().astype(np.float64)
+        bound = 1e-5 * np.abs(outs[0]) + np.abs(outs[1] - outs[2]) + 1e-9 * hp["lr"]
+        print(P.assert_within(f"train step {t} params", p_gpu, outs[0], bound))
+        assert model.step == t
+    model.close()
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_edge_cases(O, torch, mode):
+    model = B.NPM(B.make_config(W.TINY, exec_mode=MODES[mode]))
+    on = oracle_net(O, W.TINY)
+    params = model.get_state().astype(np.float64)
+    # n = 0 is a no-op; n = 1 and a ragged n work; NULL outputs are skipped
+    empty = torch.zeros((3, 0), device="cuda")
+    model.query(empty, empty)
+    for n in (1, 31, 33, 65):
+        b = W.make_batch("cube", n, seed=n)
+        out = model.query(dev(torch, b.pos), dev(torch, b.dir), lobes=False, sample=True)
+        q = O.query(on, b.pos, params, dirs=b.dir)
+        assert out["lobes"] is None
+        np.testing.assert_allclose(np.log(out["pdf"].cpu().numpy()), q["logpdf"], atol=2e-5)
+    # invalid: pdf without dir
+    b = W.make_batch("cube", 8, seed=0)
+    with pytest.raises(B.NPMError):
+        model.query(dev(torch, b.pos), None, pdf=True)
+    # non-finite or non-positive radiance / pdf gives weight 0 (no gradient)
+    b = W.make_batch("cube", 64, seed=3)
+    rad = b.radiance.copy(); rad[:] = 0.0
+    g = torch.zeros(on.n_params, device="cuda")
+    model.backward(dev(torch, b.pos), dev(torch, b.dir), dev(torch, rad), dev(torch, b.pdf), grad=g)
+    pdf = b.pdf.copy(); pdf[:] = -1.0; rad2 = b.radiance.copy(); rad2[::2] = np.inf
+    model.backward(dev(torch, b.pos), dev(torch, b.dir), dev(torch, rad2), dev(torch, pdf), grad=g)
+    torch.cuda.synchronize()
+    assert float(g.abs().max()) == 0.0
+    model.close()
