@@ -1,0 +1,272 @@
+"""Benchmark of the NPM hot path on one MI355X.
+
+Workload: the production-size plain FP32 configuration -- a 16-level hashed
+grid (2^19 entries per level, F = 2, resolutions 16..2048), MLP
+32-64-64-64-32 decoding K = 8 vMF lobes, batches of 2^20 path vertices on a
+synthetic triangle set with directions and Exp(1)-noisy radiance from an
+analytic 8-lobe vMF field.  One step is one pass of the whole hot path over
+the batch: npm_query (encode + MLP + mappings + pdf at dir + one sample and
+its pdf per vertex) followed by npm_train_step (forward, KL gradient,
+backward, grid scatter, weight gradients, Adam over all parameters).
+
+Prints one JSON line.  `value` is vertices per second through a full step
+(query + train on the same batch), inputs resident in HBM.  The roofline
+entry is for the kernel with the largest share of the timed region, from the
+library's own HIP events on the stream the kernels run on; the CPU baseline
+is the FP64 oracle on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "vertex queries/s (encode+MLP+vMF sample/pdf), train vertices/s, p99 latency"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
+
+# Algorithmic work per vertex of each fused kernel on the production config
+# (16 levels x 8 corners x F = 2): streams in/out, element-granular grid
+# gathers, 8-byte read-modify-write per FP32 atomic, and MLP FLOPs
+# (2 x 12,288 weights per pass; training runs forward, delta chain and
+# weight gradient = 3 passes).
+GATHER_B = 16 * 8 * 2 * 4
+WORK = {
+    "fused_query": dict(bytes=24 + GATHER_B + 148, flops=2 * 12288),
+    "staged_encode": dict(bytes=12 + GATHER_B + 32 * 4, flops=0),
+    "fused_backward": dict(bytes=32 + GATHER_B + 2 * GATHER_B, flops=3 * 2 * 12288),
+}
+ADAM_BYTES_PER_PARAM = 32      # read p, g, m, v; write p, m, v, g
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2504_04315_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--mode", choices=["fused", "staged"], default="fused")
+    p.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
+    p.add_argument("--n", type=int, default=1 << 20)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="target CPU time of the oracle baseline sample")
+    p.add_argument("--profile", action="store_true",
+                   help="few steps, no CPU baseline, for rocprofv3 runs")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 1 GiB device copy (counter calibration)")
+    return p.parse_args()
+
+
+def cpu_baseline(netcfg, batch, params, seconds):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    query (OpenMP over vertices) and backward (serial) on vertex subsets,
+    Adam over every parameter; scaled to vertices per second of a step."""
+    from oracle import oracle as O
+    on = O.Net(netcfg.n_levels, netcfg.feat, netcfg.base_res, netcfg.max_res,
+               netcfg.log2_table, netcfg.dense_only, netcfg.n_hidden, netcfg.width,
+               netcfg.n_lobes)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # calibrate on small samples, then size them to the time budget
+    def t_query(m):
+        sub = batch.subset(np.arange(m))
+        t0 = time.perf_counter()
+        O.query(on, sub.pos, params, dirs=sub.dir, seed=1, stream=0)
+        return time.perf_counter() - t0
+
+    def t_backward(m):
+        sub = batch.subset(np.arange(m))
+        t0 = time.perf_counter()
+        O.backward(on, sub.pos, sub.dir, sub.radiance, sub.pdf, params, n_total=batch.n,
+                   with_abs=False)
+        return time.perf_counter() - t0
+
+    q0, b0 = t_query(2048) / 2048, t_backward(256) / 256
+    mq = int(min(batch.n, max(2048, 0.4 * seconds / q0)))
+    mb = int(min(batch.n, max(256, 0.4 * seconds / b0)))
+    tq, tb = t_query(mq), t_backward(mb)
+    p = params.copy()
+    g = np.zeros_like(p)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    t0 = time.perf_counter()
+    O.adam(p, g, m, v, 1, 1e-2)
+    ta = time.perf_counter() - t0
+    per_vertex = tq / mq + tb / mb + ta / batch.n
+    return {"value": 1.0 / per_vertex, "unit": "vertices/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle query on {mq} vertices ({threads} OpenMP threads, {tq:.2f} s), "
+                      f"backward on {mb} vertices (serial, {tb:.2f} s), Adam over all "
+                      f"{p.size} parameters ({ta:.2f} s), of the same 2^20-vertex batch; "
+                      f"per-vertex times summed and inverted",
+            "query_vertices_per_s": mq / tq, "train_vertices_per_s": 1.0 / (tb / mb + ta / batch.n)}
+
+
+def load_traffic(workload, sha):
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return {}
+    d = json.load(open(path))
+    return d if d.get("source_sha") == sha else {}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path: the hot path's sharding is described in DESIGN.md.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2504_04315_amd import npm as B
+    from paper_2504_04315_amd import workload as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    netcfg = W.CFG2 if args.precision == "fp32" else W.CFG3
+    n = args.n
+    mode = B.EXEC_FUSED if args.mode == "fused" else B.EXEC_STAGED
+    model = B.NPM(B.make_config(netcfg, exec_mode=mode))
+    batch = W.make_batch("surface", n, seed=2)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    pos, dirs, rad, pdf = t(batch.pos), t(batch.dir), t(batch.radiance), t(batch.pdf)
+    outs = dict(lobes=torch.empty((4, 8, n), device="cuda"), pdf=torch.empty(n, device="cuda"),
+                sdir=torch.empty((3, n), device="cuda"), spdf=torch.empty(n, device="cuda"))
+    stats = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lib = B.lib()
+    params0 = model.get_state().astype(np.float64) if not (args.no_cpu_baseline or args.profile) else None
+
+    def query(seed):
+        B.check(lib.npm_query(model.handle, n, B._ptr(pos), B._ptr(dirs), seed, 0,
+                              B._ptr(outs["lobes"]), B._ptr(outs["pdf"]), B._ptr(outs["sdir"]),
+                              B._ptr(outs["spdf"]), B._stream()))
+
+    def train():
+        B.check(lib.npm_train_step(model.handle, n, B._ptr(pos), B._ptr(dirs), B._ptr(rad),
+                                   B._ptr(pdf), B._ptr(stats), B._stream()))
+
+    steps = 3 if args.profile else args.steps
+    warm = 1 if args.profile else args.warmup
+    for i in range(warm):
+        query(i)
+        train()
+    torch.cuda.synchronize()
+    print(f"warmup done ({warm} steps)", file=sys.stderr, flush=True)
+
+    # ---- timed region: K full steps, each bracketed by events
+    model.set_timing(True)
+    model.reset_timing()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i in range(steps):
+        query(100 + i)
+        ev[3 * i + 1].record()
+        train()
+        ev[3 * i + 2].record()
+        ev[3 * i + 3].record()
+    ev[3 * steps].record()
+    torch.cuda.synchronize()
+    total_ms = ev[0].elapsed_time(ev[3 * steps])
+    step_ms, q_ms, t_ms = [], [], []
+    prev = ev[0]
+    for i in range(steps):
+        q_ms.append(prev.elapsed_time(ev[3 * i + 1]))
+        t_ms.append(ev[3 * i + 1].elapsed_time(ev[3 * i + 2]))
+        step_ms.append(prev.elapsed_time(ev[3 * i + 3]))
+        prev = ev[3 * i + 3]
+    kt = model.kernel_times()
+    model.set_timing(False)
+    ms_per_step = total_ms / steps
+    print(f"timed {steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # ---- roofline of the dominant kernel
+    sha = kernel_sources_sha()
+    traffic = load_traffic(f"cfg2_{args.precision}_{args.mode}", sha)
+    np_params = model.n_params
+    rows = {}
+    for name, (launches, tot) in kt.items():
+        if launches == 0:
+            continue
+        avg_s = tot / launches / 1e3
+        if name in WORK:
+            w = WORK[name]
+            rows[name] = dict(avg_ms=avg_s * 1e3, launches=launches,
+                              gbs=w["bytes"] * n / avg_s / 1e9,
+                              tflops=w["flops"] * n / avg_s / 1e12)
+        elif name == "adam":
+            rows[name] = dict(avg_ms=avg_s * 1e3, launches=launches,
+                              gbs=ADAM_BYTES_PER_PARAM * np_params / avg_s / 1e9, tflops=0.0)
+        else:
+            rows[name] = dict(avg_ms=avg_s * 1e3, launches=launches, gbs=None, tflops=None)
+    dom = max(kt, key=lambda k: kt[k][1])
+    r = rows[dom]
+    dtype = args.precision if args.precision == "bf16" else "f32"
+    peak_tf = PEAK_TFLOPS[dtype]
+    if dom == "adam" or dom not in WORK or r["tflops"] / peak_tf < r["gbs"] / HBM_PEAK_GBS:
+        bound, achieved, peak, unit = "hbm", r["gbs"], HBM_PEAK_GBS, "GB/s"
+        per_launch = (WORK[dom]["bytes"] * n if dom in WORK else ADAM_BYTES_PER_PARAM * np_params)
+    else:
+        bound, achieved, peak, unit = "mfma", r["tflops"], peak_tf, "TFLOP/s"
+        per_launch = WORK[dom]["flops"] * n
+    tr = traffic.get("kernels", {}).get(dom)
+    roof = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "kernel": dom,
+            "kernel_avg_ms": round(r["avg_ms"], 4), "algorithmic_per_launch": per_launch,
+            "traffic": (None if tr is None else {"fetch_bytes": tr["fetch_bytes"],
+                                                 "write_bytes": tr["write_bytes"]})}
+    line = {
+        "metric": METRIC,
+        "value": n / (ms_per_step / 1e3),
+        "unit": "vertices/s",
+        "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"cfg2 production size: 2^20 vertices on a synthetic triangle set, "
+                               f"16-level hash grid T=2^19 F=2 (16..2048), MLP 32-64-64-64-32, "
+                               f"K=8; step = query + train step",
+                   "n": n, "precision": args.precision, "exec": args.mode},
+        "query_vertices_per_s": n / (np.median(q_ms) / 1e3),
+        "train_vertices_per_s": n / (np.median(t_ms) / 1e3),
+        "step_latency_ms": {"p50": float(np.percentile(step_ms, 50)),
+                            "p99": float(np.percentile(step_ms, 99))},
+        "query_latency_ms": {"p50": float(np.percentile(q_ms, 50)),
+                             "p99": float(np.percentile(q_ms, 99))},
+        "train_latency_ms": {"p50": float(np.percentile(t_ms, 50)),
+                             "p99": float(np.percentile(t_ms, 99))},
+        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in rows.items()},
+        "roofline": roof,
+        "loss_last_step": float(stats[0].item()),
+    }
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    if not (args.no_cpu_baseline or args.profile):
+        print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(netcfg, batch, params0, args.cpu_seconds)
+    else:
+        line["cpu_baseline"] = None
+    model.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -46,6 +46,9 @@ struct Net {
 // Fills *net from *cfg; returns NPM_OK or NPM_ERR_INVALID_ARG with a message.
 npm_status describe(const npm_config *cfg, Net *net, std::string *err);
 
+// Sets the calling thread's npm_last_error() message.
+void set_error(const char *msg);
+
 // Per-kernel event timing.
 struct Timing {
     bool enabled = false;

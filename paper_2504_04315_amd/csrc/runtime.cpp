@@ -40,6 +40,8 @@ bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
 
 }  // namespace
 
+void npm::set_error(const char *msg) { g_err = msg ? msg : ""; }
+
 // --------------------------------------------------------------------------
 // Configuration and layout (Sec. 5.1 grid levels, Sec. 5.3 MLP)
 // --------------------------------------------------------------------------

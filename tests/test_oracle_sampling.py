@@ -127,3 +127,14 @@ def test_sample_pdf_matches_logpdf(O):
     q = O.query(net, pos, params, seed=5, stream=2)
     np.testing.assert_allclose(q["slogpdf"], O.logpdf(net, q["raw"], q["sdir"]), rtol=1e-13)
     np.testing.assert_allclose(np.linalg.norm(q["sdir"], axis=1), 1.0, atol=1e-12)
+
+
+def test_sample_cosine_bounded_for_huge_kappa(O, net1):
+    # At u1 = 0 the inverse CDF of the cosine is exactly -1 (the antipode of
+    # mu); the log1p/expm1 form underflows there for large kappa.
+    th, ph = 0.45, 0.3
+    raw = np.array([lobe_raw(th, ph, math.exp(80.0))])
+    d, _ = O.sample_raw(net1, raw, np.array([[0.5, 0.0, 0.25]]))
+    np.testing.assert_allclose(d[0], -mu_of(th, ph), atol=1e-12)
+    d, _ = O.sample_raw(net1, raw, np.array([[0.5, 0.5, 0.25]]))
+    np.testing.assert_allclose(d[0], mu_of(th, ph), atol=1e-12)
