@@ -37,6 +37,9 @@ __device__ __forceinline__ constexpr int nf(int h, int a) { return 8 * (a >> 2) 
 // --------------------------------------------------------------------------
 __device__ __forceinline__ void lattice_cell(float x, int D, int &c, float &f)
 {
+    // The fraction must come from the rounded product: without this the
+    // compiler fuses the multiply and the subtraction into one FMA.
+#pragma clang fp contract(off)
     const float p = __fmul_rn(fminf(fmaxf(x, 0.0f), 1.0f), (float)D);
     int ci = (int)floorf(p);
     ci = ci < D - 1 ? ci : D - 1;
@@ -205,16 +208,30 @@ __device__ __forceinline__ void mfma_layer_f32(const float *__restrict__ img, co
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
+    // weights double-buffered by hand: the next group's LDS reads are issued
+    // before this group's MFMAs, and the compiler barrier keeps them there
+    // (hoisting every read would cost 4 VGPRs per MFMA group).
+    f32x4 wc[NB], wn[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        wc[b] = *reinterpret_cast<const f32x4 *>(img + ((b * NS4 + 0) * 64 + lane) * 4);
 #pragma unroll
     for (int s4 = 0; s4 < NS4; ++s4) {
+        if (s4 + 1 < NS4) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                wn[b] = *reinterpret_cast<const f32x4 *>(img + ((b * NS4 + s4 + 1) * 64 + lane) * 4);
+        }
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const f32x4 w = *reinterpret_cast<const f32x4 *>(img + ((b * NS4 + s4) * 64 + lane) * 4);
-            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[0], x[4 * s4 + 0], acc[b], 0, 0, 0);
-            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[1], x[4 * s4 + 1], acc[b], 0, 0, 0);
-            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[2], x[4 * s4 + 2], acc[b], 0, 0, 0);
-            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[3], x[4 * s4 + 3], acc[b], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(wc[b][0], x[4 * s4 + 0], acc[b], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(wc[b][1], x[4 * s4 + 1], acc[b], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(wc[b][2], x[4 * s4 + 2], acc[b], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(wc[b][3], x[4 * s4 + 3], acc[b], 0, 0, 0);
         }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) wc[b] = wn[b];
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -232,16 +249,26 @@ __device__ __forceinline__ void mfma_layer_bf16(const __bf16 *__restrict__ img, 
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
+    bf16x8 wc[NB], wn[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        wc[b] = *reinterpret_cast<const bf16x8 *>(img + ((b * NS + 0) * 64 + lane) * 8);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
+        if (s + 1 < NS) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                wn[b] = *reinterpret_cast<const bf16x8 *>(img + ((b * NS + s + 1) * 64 + lane) * 8);
+        }
+        asm volatile("" ::: "memory");
         bf16x8 xb;
 #pragma unroll
         for (int e = 0; e < 8; ++e) xb[e] = (__bf16)x[8 * s + e];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const bf16x8 w = *reinterpret_cast<const bf16x8 *>(img + ((b * NS + s) * 64 + lane) * 8);
-            acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, xb, acc[b], 0, 0, 0);
-        }
+        for (int b = 0; b < NB; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wc[b], xb, acc[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) wc[b] = wn[b];
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b)

@@ -165,7 +165,9 @@ static PackDesc pack_desc(const Net &net)
         g.ld = L.layer_in[i];
         g.transpose = 0;
     }
-    for (int i = 0; i < L.n_layers; ++i) {
+    // backward images are stored from the last layer to the first; segments
+    // must be in increasing dst order for the lookup in k_pack
+    for (int i = L.n_layers - 1; i >= 0; --i) {
         PackSeg &g = d.seg[n++];
         g.dst = m.fwd_elems + m.bwd_off[i];
         g.src = L.layer_offset[i];

@@ -39,7 +39,7 @@ struct FusedArgs {
     float invN;
 };
 template <int IN_P, int HID_P, int NH, int F, bool BF>
-__global__ __launch_bounds__(256) void k_query_fused(FusedArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_query_fused(FusedArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ uint32_t s_off[NPM_MAX_LEVELS];

@@ -61,7 +61,7 @@ __device__ __forceinline__ void stage_bytes(char *dst, const void *src, int byte
 
 // Queries of requests [r0, r1) of the round; `which` selects the counter.
 template <int IN_P, int HID_P, int NH, int F>
-__global__ __launch_bounds__(256) void k_serve_query(RoundHdr *hdr, const DevReq *__restrict__ reqs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_serve_query(RoundHdr *hdr, const DevReq *__restrict__ reqs,
                                                      int r0, int r1, int n_chunks, int which)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
