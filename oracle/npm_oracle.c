@@ -290,6 +290,34 @@ static void oracle_mlp_one(const npmo_net *net, const double *G, const double *p
     }
 }
 
+/* The same forward, also carrying the condition scale of every value: the
+ * sum of |terms| that an FP32 evaluation rounds, propagated through the
+ * layers (cond(z_o) = sum_k |W_ok| cond(h_k); ReLU passes it where z > 0).
+ * The tolerance of a float evaluation of z is proportional to cond(z), not
+ * to |z|, which cancellation can make arbitrarily small.                   */
+static void oracle_mlp_cond_one(const npmo_net *net, const double *G, const double *Gcond,
+                                const double *params,
+                                double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH],
+                                double cacts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH],
+                                double *raw, double *rawcond)
+{
+    for (int j = 0; j < net->n_in; ++j) { acts[0][j] = G[j]; cacts[0][j] = Gcond[j]; }
+    for (int i = 0; i < net->n_layers; ++i) {
+        const double *W = params + net->layer_offset[i];
+        int nin = net->layer_in[i], nout = net->layer_out[i];
+        int last = (i == net->n_layers - 1);
+        for (int o = 0; o < nout; ++o) {
+            double s = 0.0, c = 0.0;
+            for (int k = 0; k < nin; ++k) {
+                s += W[(int64_t)o * nin + k] * acts[i][k];
+                c += fabs(W[(int64_t)o * nin + k]) * cacts[i][k];
+            }
+            if (last) { raw[o] = s; rawcond[o] = c; }
+            else { acts[i + 1][o] = s > 0.0 ? s : 0.0; cacts[i + 1][o] = s > 0.0 ? c : 0.0; }
+        }
+    }
+}
+
 void npmo_mlp_forward(const npmo_net *net, int64_t n, const double *G, const double *params,
                       double *raw /* [n][4K] */, double *rawscale /* [n][4K] or NULL */)
 {
@@ -523,6 +551,48 @@ static double oracle_loss_grad_one(const npmo_net *net, const double *raw, const
     return g * lv;
 }
 
+/* Condition scale of d loss / d raw for one sample: each derivative of
+ * oracle_loss_grad_one with its dot products and differences replaced by
+ * sums of absolute values, times a factor for the relative error of the
+ * responsibilities (log terms carry kappa times the rounding of mu.w) and for
+ * the rounding of the raw outputs themselves (condition rawcond, amplified by
+ * the head's sensitivity, of order 1 + kappa).                             */
+static void oracle_head_cond(const npmo_net *net, const double *raw, const double *rawcond,
+                             const double w3[3], double wgt, double invN, double *cdraw)
+{
+    int K = net->n_lobes;
+    for (int j = 0; j < net->n_out; ++j) cdraw[j] = 0.0;
+    if (wgt == 0.0) return;
+    oracle_lobe lob[NPMO_MAX_LOBES];
+    double terms[NPMO_MAX_LOBES];
+    oracle_map(net, raw, lob);
+    double lv = oracle_logpdf(net, lob, w3, terms);
+    double g = fabs(wgt * invN);
+    double rk_sum = 0.0, kmax = 0.0, cmax = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double r = exp(terms[k] - lv);
+        rk_sum += r * lob[k].kappa;
+        if (lob[k].kappa > kmax) kmax = lob[k].kappa;
+    }
+    for (int j = 0; j < net->n_out; ++j) if (rawcond[j] > cmax) cmax = rawcond[j];
+    double input = 1.0 + (1.0 + kmax) * cmax;
+    for (int k = 0; k < K; ++k) {
+        const oracle_lobe *b = &lob[k];
+        double r = exp(terms[k] - lv), kap = b->kappa;
+        double a1 = 0.0, a2 = 0.0, am = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            a1 += fabs(b->t1[d] * w3[d]);
+            a2 += fabs(b->t2[d] * w3[d]);
+            am += fabs(b->mu[d] * w3[d]);
+        }
+        double resp = (1.0 + kap + rk_sum) * input;
+        cdraw[4 * k + 0] = g * r * kap * PI * b->theta * (1.0 - b->theta) * a1 * resp;
+        cdraw[4 * k + 1] = g * r * kap * b->sinT * 2.0 * PI * b->phi * (1.0 - b->phi) * a2 * resp;
+        cdraw[4 * k + 2] = g * r * (1.0 + 2.0 * kap / expm1(2.0 * kap) + kap * (am + 1.0)) * resp;
+        cdraw[4 * k + 3] = g * (r + b->lambda) * resp;
+    }
+}
+
 double npmo_loss_grad(const npmo_net *net, int64_t n, int64_t n_total, const double *raw,
                       const float *dir /* [3][n] */, const float *rad, const float *spdf,
                       double *draw /* [n][4K] */)
@@ -542,6 +612,67 @@ double npmo_loss_grad(const npmo_net *net, int64_t n, int64_t n_total, const dou
 /* the interpolation), with the encoding recomputed per vertex.  grad and   */
 /* gabs accumulate; gabs receives the sum of |contributions| per parameter. */
 /* ------------------------------------------------------------------------ */
+/* Condition scales of the gradient (gcond, accumulated): the head seed of
+ * oracle_head_cond carried back through the layers alongside the values:
+ * cond(dz) = cond(dh) where z > 0; cond(dh_k) = sum_o |W_ok| cond(dz_o);
+ * cond(dW_ok) += cond(dz_o) |h_k| + |dz_o| cond(h_k); the grid entry of a
+ * corner gets w_c cond(dG).                                               */
+static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, const double w3[3],
+                                     double wgt, double invN, const double *params,
+                                     double *gcond)
+{
+    int L = net->n_levels, F = net->feat;
+    double G[NPMO_MAX_WIDTH], Gc[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES], rawc[4 * NPMO_MAX_LOBES];
+    double draw[4 * NPMO_MAX_LOBES], cdraw[4 * NPMO_MAX_LOBES];
+    double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH], cacts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
+    double delta[NPMO_MAX_WIDTH], cdelta[NPMO_MAX_WIDTH], prev[NPMO_MAX_WIDTH], cprev[NPMO_MAX_WIDTH];
+    int64_t idx[NPMO_MAX_LEVELS * 8];
+    double cw[NPMO_MAX_LEVELS * 8];
+    if (wgt == 0.0) return;
+    oracle_encode_one(net, pos3[0], pos3[1], pos3[2], params, G, Gc);
+    oracle_mlp_cond_one(net, G, Gc, params, acts, cacts, raw, rawc);
+    oracle_loss_grad_one(net, raw, w3, wgt, invN, draw);
+    oracle_head_cond(net, raw, rawc, w3, wgt, invN, cdraw);
+    for (int j = 0; j < net->n_out; ++j) { delta[j] = draw[j]; cdelta[j] = cdraw[j]; }
+    for (int li = net->n_layers - 1; li >= 0; --li) {
+        const double *W = params + net->layer_offset[li];
+        double *cW = gcond + net->layer_offset[li];
+        int nin = net->layer_in[li], nout = net->layer_out[li];
+        if (li < net->n_layers - 1)
+            for (int o = 0; o < nout; ++o)
+                if (!(acts[li + 1][o] > 0.0)) { delta[o] = 0.0; cdelta[o] = 0.0; }
+        for (int o = 0; o < nout; ++o)
+            for (int k = 0; k < nin; ++k)
+                cW[(int64_t)o * nin + k] += cdelta[o] * fabs(acts[li][k]) + fabs(delta[o]) * cacts[li][k];
+        for (int k = 0; k < nin; ++k) {
+            double sv = 0.0, sc = 0.0;
+            for (int o = 0; o < nout; ++o) {
+                sv += W[(int64_t)o * nin + k] * delta[o];
+                sc += fabs(W[(int64_t)o * nin + k]) * cdelta[o];
+            }
+            prev[k] = sv; cprev[k] = sc;
+        }
+        for (int k = 0; k < nin; ++k) { delta[k] = prev[k]; cdelta[k] = cprev[k]; }
+    }
+    oracle_corners_one(net, pos3[0], pos3[1], pos3[2], idx, cw);
+    for (int l = 0; l < L; ++l)
+        for (int b = 0; b < 8; ++b)
+            for (int f = 0; f < F; ++f)
+                gcond[idx[l * 8 + b] * F + f] += cw[l * 8 + b] * cdelta[l * F + f];
+}
+
+void npmo_backward_cond(const npmo_net *net, int64_t n, int64_t n_total, const float *pos,
+                        const float *dir, const float *rad, const float *spdf, const double *params,
+                        double *gcond /* [n_params], accumulated */)
+{
+    double invN = 1.0 / (double)n_total;
+    for (int64_t i = 0; i < n; ++i) {
+        float p3[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+        double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
+        oracle_backward_cond_one(net, p3, w3, oracle_weight(rad[i], spdf[i]), invN, params, gcond);
+    }
+}
+
 double npmo_backward(const npmo_net *net, int64_t n, int64_t n_total, const float *pos,
                      const float *dir, const float *rad, const float *spdf, const double *params,
                      double *grad /* [n_params] */, double *gabs /* [n_params] or NULL */,

@@ -63,6 +63,7 @@ def lib():
         L.npmo_loss_grad.restype = C.c_double
         L.npmo_backward.argtypes = [P, i64, i64, P, P, P, P, P, P, P, P, P]
         L.npmo_backward.restype = C.c_double
+        L.npmo_backward_cond.argtypes = [P, i64, i64, P, P, P, P, P, P]
         L.npmo_adam.argtypes = [i64, P, P, P, P, i64, C.c_double, C.c_double, C.c_double,
                                 C.c_double]
         _lib = L
@@ -232,6 +233,23 @@ def backward(net, pos, dirs, rad, spdf, params, n_total=None, with_abs=True, wit
     out = dict(grad=grad, gabs=gabs, loss=loss)
     if with_vertex:
         out.update(draw=draw, dG=dG)
+    return out
+
+
+def backward_cond(net, pos, dirs, rad, spdf, params, n_total=None):
+    """Condition scale of every gradient entry (float64): the sum of the
+    absolute sizes of the terms an FP32 evaluation of the backward rounds,
+    propagated from the KL-gradient head through the MLP and the scatter.
+    Parity tolerances are relative to it."""
+    n = pos.shape[1]
+    pos = _f32soa(pos, n)
+    dirs = _f32soa(dirs, n)
+    rad = np.ascontiguousarray(rad, dtype=np.float32)
+    spdf = np.ascontiguousarray(spdf, dtype=np.float32)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    out = np.zeros(net.n_params)
+    lib().npmo_backward_cond(net.ref, n, n if n_total is None else n_total, _p(pos), _p(dirs),
+                             _p(rad), _p(spdf), _p(params), _p(out))
     return out
 
 

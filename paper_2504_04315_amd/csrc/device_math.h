@@ -147,14 +147,22 @@ __device__ __forceinline__ float lobe_logterm(const Lobe &L, float wx, float wy,
     return L.loglam + log_vmf_norm(L.kappa) + L.kappa * (d - 1.0f);
 }
 
-// Direction drawn from one lobe (Jakob 2012): cosine from the inverse CDF of
-// e^{kappa t} on [-1, 1], bounded to [-1, 1], azimuth 2 pi u2 in (t1, t2).
+// Direction drawn from one lobe (Jakob 2012): cosine t from the inverse CDF
+// of e^{kappa t} on [-1, 1], bounded to [-1, 1], azimuth 2 pi u2 in (t1, t2).
+// 1 - t = -log1p((1 - u1) expm1(-2 kappa)) / kappa and
+// 1 + t =  log1p(u1 expm1(2 kappa)) / kappa are carried separately (they are
+// the same inverse CDF): each is accurate where the other cancels, near the
+// lobe axis and near its antipode, and s = sqrt((1 - t)(1 + t)) needs both.
 __device__ __forceinline__ void lobe_sample(const Lobe &L, float u1, float u2, float w[3])
 {
     const float k = L.kappa;
-    float t = 1.0f + log1pf((1.0f - u1) * expm1f(-2.0f * k)) / k;
-    t = fminf(1.0f, fmaxf(-1.0f, t));
-    const float s = sqrtf(fmaxf(0.0f, (1.0f - t) * (1.0f + t)));
+    const float omt = fminf(2.0f, fmaxf(0.0f, -log1pf((1.0f - u1) * expm1f(-2.0f * k)) / k));
+    // expm1(2 kappa) overflows beyond 2 kappa ~ 88; there 1 + t >= 1.6 and
+    // 2 - (1 - t) does not cancel
+    const float opt = (k < 40.0f) ? fminf(2.0f, fmaxf(0.0f, log1pf(u1 * expm1f(2.0f * k)) / k))
+                                  : 2.0f - omt;
+    const float t = omt < 1.0f ? 1.0f - omt : opt - 1.0f;
+    const float s = sqrtf(omt * opt);
     float sp, cp;
     sincospif(2.0f * u2, &sp, &cp);
 #pragma unroll

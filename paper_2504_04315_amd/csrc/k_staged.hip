@@ -510,7 +510,7 @@ hipError_t staged_mlp_fwd(npm_ctx *ctx, int64_t n, const float *G, float *acts, 
 {
     const int blocks = tile_blocks(n);
     int tok;
-    timed_begin(ctx, "staged_mlp_fwd", s, &tok);
+    timed_begin(ctx, acts ? "staged_mlp_fwd_train" : "staged_mlp_fwd", s, &tok);
     NPM_MLP_DISPATCH(MlpFwd, ::run(ctx, blocks, n, G, acts, raw, s));
     timed_end(ctx, tok, s);
     return hipGetLastError();

@@ -11,9 +11,15 @@ to the (possibly cancelled) result:
   Table 1 mapping's derivative, plus 1e-5 relative on the value itself;
 * log pdf: 1e-5 + 1e-5 * sum_j |d logV / d raw_j| * scale_j
   + 4 * kappa_max * 2^-23 (an ulp of mu.w amplified by kappa);
-* sampled directions (same uniforms): |d|_inf <= 2e-5 except samples whose
-  CDF margin is below 1e-5, where FP32 and FP64 may pick different lobes;
-* gradients: |d| <= 1e-5 * sum |contributions| (atomic order is unspecified).
+* sampled directions (same uniforms): |d|_inf <= 2e-5 plus the change of the
+  oracle's sample when each raw output moves by its own 1e-5 tolerance,
+  except samples whose CDF margin is below 1e-5, where FP32 and FP64 may
+  pick different lobes;
+* gradients: |d| <= 1e-5 * cond, where cond is the oracle's condition scale
+  of the entry: the sizes of all the terms an FP32 evaluation rounds,
+  propagated from the KL-gradient head through the MLP and the scatter
+  (sums of many signed terms -- dG = W^T delta, the atomic sums over
+  vertices -- have errors proportional to them, not to the result).
 """
 import numpy as np
 
@@ -70,6 +76,19 @@ def check_logpdf(name, got_pdf, ref_logpdf, bound):
     with np.errstate(divide="ignore"):
         lg = np.log(np.asarray(got_pdf, dtype=np.float64))
     return assert_within(name, lg, ref_logpdf, bound)
+
+
+def sample_bound(O, net, raw, raw_scale, u, base=2e-5, rtol=RTOL):
+    """|d omega| allowed per sample: base + sum_j |omega(raw + rtol scale_j e_j)
+    - omega(raw)| (first-order effect of each raw output's tolerance)."""
+    w0, _ = O.sample_raw(net, raw, u)
+    b = np.full(raw.shape[0], base)
+    for j in range(raw.shape[1]):
+        r = raw.copy()
+        r[:, j] += rtol * raw_scale[:, j]
+        w1, _ = O.sample_raw(net, r, u)
+        b += np.abs(w1 - w0).max(axis=1)
+    return b
 
 
 def check_grads(name, got, ref, gabs, rtol=RTOL, atol=1e-12):

@@ -167,3 +167,16 @@ def test_adam_alternating_gradient(O):
     # after +1, -1: m_hat = -(1 - b1)/(1 + b1), v_hat = 1
     mh = -(1 - b1) / (1 + b1)
     assert p[0] == pytest.approx(-lr * 1 / (1 + eps) - lr * mh / (1 + eps), rel=1e-12)
+
+
+def test_condition_scale_dominates_contributions(O):
+    # the propagated condition scale of every gradient entry is at least the
+    # sum of |contributions| (each seed and propagation step bounds |value|)
+    net = _tiny(O)
+    rng = np.random.default_rng(11)
+    params = rng.normal(scale=0.6, size=net.n_params)
+    pos, dirs, rad, pdf = _tiny_batch(rng, 64)
+    out = O.backward(net, pos, dirs, rad, pdf, params)
+    cond = O.backward_cond(net, pos, dirs, rad, pdf, params)
+    assert np.all(cond >= out["gabs"] * (1 - 1e-12))
+    assert np.all((cond > 0) == (out["gabs"] > 0))
