@@ -408,6 +408,55 @@ struct TrainIO {
     float invN;
 };
 
+// Scatter of a tile's dG into the grid gradient (the transpose of the
+// interpolation).  FP32 atomics are limited by the number of distinct 64-byte
+// lines per wave instruction, so lanes are assigned to the 8F contributions
+// of one (vertex, level) -- corner b = sub / F, feature f = sub % F -- where
+// the x-adjacent corners and the F features of an entry are contiguous, and
+// the 64 / (8F) vertex-levels of an instruction are consecutive vertices of
+// one level.  dGt: the tile's dG in LDS, rows = features, stride kStride.
+
+template <int F>
+__device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dGt,
+                                             const float *__restrict__ pos, int64_t n, int64_t t,
+                                             int lane, float *__restrict__ grad)
+{
+    constexpr int LPV = 8 * F;              // lanes per vertex-level
+    constexpr int VPI = 64 / LPV;           // vertex-levels per instruction
+    const int q = lane / LPV, sub = lane % LPV, b = sub / F, f = sub % F;
+    const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+    float px[32 / VPI], py[32 / VPI], pz[32 / VPI];
+#pragma unroll
+    for (int jj = 0; jj < 32 / VPI; ++jj) {
+        const int64_t v = t * 32 + jj * VPI + q;
+        const int64_t vv = v < n ? v : n - 1;
+        px[jj] = pos[vv]; py[jj] = pos[n + vv]; pz[jj] = pos[2 * n + vv];
+    }
+    for (int l = 0; l < gv.n_levels; ++l) {
+        const int D = gv.res[l];
+        const uint32_t d1 = (uint32_t)D + 1u;
+        const bool hashed = (gv.hashed_mask >> l) & 1u;
+        const uint32_t off = gv.off[l];
+#pragma unroll
+        for (int jj = 0; jj < 32 / VPI; ++jj) {
+            const int j = jj * VPI + q;
+            if (t * 32 + j >= n) continue;
+            const float d = dGt[(l * F + f) * kStride + j];
+            if (d == 0.0f) continue;
+            int cx, cy, cz;
+            float fx, fy, fz;
+            lattice_cell(px[jj], D, cx, fx);
+            lattice_cell(py[jj], D, cy, fy);
+            lattice_cell(pz[jj], D, cz, fz);
+            const uint32_t X = cx + bx, Y = cy + by, Z = cz + bz;
+            const uint32_t e = off + (hashed ? ((X ^ (Y * 2654435761u) ^ (Z * 805459861u)) & gv.table_mask)
+                                             : X + d1 * (Y + d1 * Z));
+            const float w = (bx ? fx : 1.0f - fx) * (by ? fy : 1.0f - fy) * (bz ? fz : 1.0f - fz);
+            unsafeAtomicAdd(grad + (size_t)e * F + f, w * d);
+        }
+    }
+}
+
 // One tile of the backward: forward with activations in registers, the
 // KL-gradient head, the delta chain, the weight gradients into dw, and the
 // grid scatter.  lacc accumulates -w log V (FP64) of half 0's vertices.
@@ -475,40 +524,11 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
     }
     float dG[OUT0 / 2];
     layer<BF, HID_P, OUT0>(im, dh, dG, lane);
-    // ---- grid scatter: recompute this half's corners, add w * dG
-    if (!valid) return;
-    constexpr int PER = 4 / F;
-#pragma unroll
-    for (int g = 0; g < IN_P / 8; ++g) {
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int l = (8 * g + 4 * h) / F + j;
-            if (l >= gv.n_levels) continue;
-            float df[F];
-            bool any = false;
-#pragma unroll
-            for (int f = 0; f < F; ++f) { df[f] = dG[4 * g + j * F + f]; any |= df[f] != 0.0f; }
-            if (!any) continue;
-            const int D = gv.res[l];
-            int cx, cy, cz;
-            float fx, fy, fz;
-            lattice_cell(px, D, cx, fx);
-            lattice_cell(py, D, cy, fy);
-            lattice_cell(pz, D, cz, fz);
-            const uint32_t d1 = (uint32_t)D + 1u;
-            const bool hashed = (gv.hashed_mask >> l) & 1u;
-            const float wxs[2] = {1.0f - fx, fx}, wys[2] = {1.0f - fy, fy}, wzs[2] = {1.0f - fz, fz};
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const uint32_t X = cx + (b & 1), Y = cy + ((b >> 1) & 1), Z = cz + ((b >> 2) & 1);
-                const uint32_t e = gv.off[l] + (hashed ? ((X ^ (Y * 2654435761u) ^ (Z * 805459861u)) & gv.table_mask)
-                                                       : X + d1 * (Y + d1 * Z));
-                const float w = wxs[b & 1] * wys[(b >> 1) & 1] * wzs[(b >> 2) & 1];
-#pragma unroll
-                for (int f = 0; f < F; ++f) unsafeAtomicAdd(io.grad + (size_t)e * F + f, w * df[f]);
-            }
-        }
-    }
+    // ---- grid scatter, coalesced: dG through the wave's LDS buffer
+    wave_lds_fence();
+    t32_to_lds<OUT0 / 2>(tbuf, dG, lane);
+    wave_lds_fence();
+    scatter_tile<F>(gv, tbuf, io.pos, n, t, lane, io.grad);
 }
 
 // Writes (or atomically adds) a wave's weight gradients in the flat layer

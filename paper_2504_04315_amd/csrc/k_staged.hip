@@ -420,26 +420,34 @@ __global__ __launch_bounds__(256) void k_loss_grad(int64_t n, const float *__res
 }
 
 // ============================================================= scatter
-// dV_l[corner] += w_corner * dG[l F + f]: FP32 atomics straight to L2.
+// dV_l[corner] += w_corner * dG[l F + f] with FP32 atomics.  Their throughput
+// is set by the distinct 64-byte lines per wave instruction, so 8F
+// consecutive threads take the corners x features of one vertex (the
+// x-adjacent corners and the features of an entry are contiguous) and a wave
+// covers 64 / (8F) consecutive vertices of one level.
 template <int F>
 __global__ __launch_bounds__(256) void k_scatter(GridDesc g, int64_t n, const float *__restrict__ pos,
                                                  const float *__restrict__ dG,
                                                  float *__restrict__ grad)
 {
-    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    constexpr int LPV = 8 * F;
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t v = gid / LPV;
+    const int sub = (int)(gid % LPV), b = sub / F, f = sub % F;
     const int l = blockIdx.y;
     if (v >= n) return;
-    float d[F];
-    bool any = false;
-#pragma unroll
-    for (int f = 0; f < F; ++f) { d[f] = dG[((int64_t)l * F + f) * n + v]; any |= d[f] != 0.0f; }
-    if (!any) return;
-    Corners c;
-    level_corners(g, l, pos[v], pos[n + v], pos[2 * n + v], c);
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-#pragma unroll
-        for (int f = 0; f < F; ++f) unsafeAtomicAdd(grad + (size_t)c.e[b] * F + f, c.w[b] * d[f]);
+    const float d = dG[((int64_t)l * F + f) * n + v];
+    if (d == 0.0f) return;
+    const int D = g.res[l];
+    int cx, cy, cz;
+    float fx, fy, fz;
+    lattice_cell(pos[v], D, cx, fx);
+    lattice_cell(pos[n + v], D, cy, fy);
+    lattice_cell(pos[2 * n + v], D, cz, fz);
+    const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+    const uint32_t e = corner_entry(g, l, cx + bx, cy + by, cz + bz);
+    const float w = (bx ? fx : 1.0f - fx) * (by ? fy : 1.0f - fy) * (bz ? fz : 1.0f - fz);
+    unsafeAtomicAdd(grad + (size_t)e * F + f, w * d);
 }
 
 // ============================================================= launchers
@@ -589,7 +597,7 @@ hipError_t staged_scatter(npm_ctx *ctx, int64_t n, const float *pos, const float
                           float *grad, hipStream_t s)
 {
     const GridDesc &g = ctx->net.grid;
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)g.n_levels);
+    dim3 grid((unsigned)((n * 8 * g.feat + 255) / 256), (unsigned)g.n_levels);
     int tok;
     timed_begin(ctx, "staged_scatter", s, &tok);
     switch (g.feat) {
