@@ -76,6 +76,7 @@ def parse():
     p.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
     p.add_argument("--n", type=int, default=1 << 20)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-serving", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU time of the oracle baseline sample")
     p.add_argument("--profile", action="store_true",
@@ -126,6 +127,46 @@ def cpu_baseline(netcfg, batch, params, seconds):
                       f"{p.size} parameters ({ta:.2f} s), of the same 2^20-vertex batch; "
                       f"per-vertex times summed and inverted",
             "query_vertices_per_s": mq / tq, "train_vertices_per_s": 1.0 / (tb / mb + ta / batch.n)}
+
+
+def serving_bench(n_sessions=32, per_session=6, load=0.7):
+    """The serving form on its workload: n_sessions guiding sessions (16-level
+    FP16 hash grid, T = 2^17, MLP 32-64-64-64-32), each a Poisson stream of
+    query batches with sizes log-uniform in 2^10..2^18 and a training batch
+    after every 4 queries.  First the saturation throughput (everything
+    submitted at once), then the same plan offered at `load` times it; both
+    for the shared persistent kernels (BF16) and the per-session plain FP32
+    path."""
+    from paper_2504_04315_amd import npm as B
+    from paper_2504_04315_amd import serve as S
+    from paper_2504_04315_amd import workload as W
+    from dataclasses import replace
+    mean_n = (2.0 ** 18 - 2.0 ** 10) / math.log(2.0 ** 8)
+    out = {"sessions": n_sessions, "requests_per_session": None, "offered_load": load}
+    for name, plain in (("shared_bf16", False), ("plain_fp32", True)):
+        srv = S.Server(budget_bytes=200 << 30, max_sessions=n_sessions, round_vertices=1 << 20,
+                       plain_path=plain)
+        sids = [srv.create_session(B.make_config(replace(W.CFG5, seed=100 + i)))
+                for i in range(n_sessions)]
+        plan = S.plan_requests(n_sessions, per_session, rate_hz=1e9, train_every=4, seed=1)
+        out["requests_per_session"] = len(plan) / n_sessions
+        S.make_request_buffers(plan)
+        for r in plan:                  # warm the kernels once
+            r["t"] = 0.0
+        S.run_load(srv, sids, plan[:n_sessions])
+        sat = S.run_load(srv, sids, plan)
+        rate = load * sat["vertices_per_s"] / (n_sessions * mean_n * 1.25)
+        plan2 = S.plan_requests(n_sessions, per_session, rate_hz=rate, train_every=4, seed=2)
+        S.make_request_buffers(plan2)
+        res = S.run_load(srv, sids, plan2)
+        out[name] = {"saturation_vertices_per_s": sat["vertices_per_s"],
+                     "saturation_latency_ms": sat["latency_ms"],
+                     "offered_vertices_per_s": load * sat["vertices_per_s"],
+                     "vertices_per_s": res["vertices_per_s"], "latency_ms": res["latency_ms"],
+                     "query_latency_ms": res["query_latency_ms"],
+                     "train_latency_ms": res["train_latency_ms"], "rounds": res["rounds"]}
+        srv.close()
+    return out
 
 
 def load_traffic(workload, sha):
@@ -272,6 +313,10 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+    if not (args.no_serving or args.profile):
+        print("serving ...", file=sys.stderr, flush=True)
+        line["serving"] = serving_bench()
+        line["p99_latency_ms"] = line["serving"]["shared_bf16"]["latency_ms"]["p99"]
     if not (args.no_cpu_baseline or args.profile):
         print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(netcfg, batch, params0, args.cpu_seconds)

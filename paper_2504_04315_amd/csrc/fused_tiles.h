@@ -358,7 +358,11 @@ __device__ __forceinline__ void dw_tile(float *buf, const float *dz, const float
     }
 }
 
-template <int OUT_P, int IN_P, bool ATOMIC>
+// How dw_store writes: plain store, add to what is there (the caller makes
+// the writes exclusive), or FP32 atomic add.
+enum { DW_STORE = 0, DW_ADD = 1, DW_ATOMIC = 2 };
+
+template <int OUT_P, int IN_P, int MODE>
 __device__ __forceinline__ void dw_store(float *dst, int out_r, int in_r, f32x16 (*acc)[IN_P / 32],
                                          int lane)
 {
@@ -371,7 +375,8 @@ __device__ __forceinline__ void dw_store(float *dst, int out_r, int in_r, f32x16
             for (int r = 0; r < 16; ++r) {
                 const int row = 32 * bo + nf(h, r), col = 32 * bi + j;
                 if (row < out_r && col < in_r) {
-                    if (ATOMIC) unsafeAtomicAdd(dst + row * in_r + col, acc[bo][bi][r]);
+                    if (MODE == DW_ATOMIC) unsafeAtomicAdd(dst + row * in_r + col, acc[bo][bi][r]);
+                    else if (MODE == DW_ADD) dst[row * in_r + col] += acc[bo][bi][r];
                     else dst[row * in_r + col] = acc[bo][bi][r];
                 }
             }
@@ -406,7 +411,14 @@ struct TrainIO {
     const float *pos, *dir, *rad, *spdf;
     float *grad;      // flat gradient (grid part scattered here), or null: loss only
     float invN;
+    const uint32_t *perm;   // visiting order of the vertices, or null: 0..n-1
 };
+
+// The vertex at position v of the visiting order.
+__device__ __forceinline__ int64_t visit(const uint32_t *perm, int64_t v)
+{
+    return perm ? (int64_t)perm[v] : v;
+}
 
 // Scatter of a tile's dG into the grid gradient (the transpose of the
 // interpolation).  FP32 atomics are limited by the number of distinct 64-byte
@@ -418,8 +430,9 @@ struct TrainIO {
 
 template <int F>
 __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dGt,
-                                             const float *__restrict__ pos, int64_t n, int64_t t,
-                                             int lane, float *__restrict__ grad)
+                                             const float *__restrict__ pos, const uint32_t *perm,
+                                             int64_t n, int64_t t, int lane,
+                                             float *__restrict__ grad)
 {
     constexpr int LPV = 8 * F;              // lanes per vertex-level
     constexpr int VPI = 64 / LPV;           // vertex-levels per instruction
@@ -429,7 +442,7 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
 #pragma unroll
     for (int jj = 0; jj < 32 / VPI; ++jj) {
         const int64_t v = t * 32 + jj * VPI + q;
-        const int64_t vv = v < n ? v : n - 1;
+        const int64_t vv = visit(perm, v < n ? v : n - 1);
         px[jj] = pos[vv]; py[jj] = pos[n + vv]; pz[jj] = pos[2 * n + vv];
     }
     for (int l = 0; l < gv.n_levels; ++l) {
@@ -472,7 +485,7 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
     const int64_t n = io.n;
     const int64_t v = t * 32 + (lane & 31);
     const bool valid = v < n;
-    const int64_t vv = valid ? v : n - 1;
+    const int64_t vv = visit(io.perm, valid ? v : n - 1);
     const float px = io.pos[vv], py = io.pos[n + vv], pz = io.pos[2 * n + vv];
     float x[IN0 / 2];
     encode_tile<IN_P, F, BF>(gv, h, px, py, pz, x);
@@ -528,24 +541,24 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
     wave_lds_fence();
     t32_to_lds<OUT0 / 2>(tbuf, dG, lane);
     wave_lds_fence();
-    scatter_tile<F>(gv, tbuf, io.pos, n, t, lane, io.grad);
+    scatter_tile<F>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad);
 }
 
 // Writes (or atomically adds) a wave's weight gradients in the flat layer
 // layout of the MLP part of the parameters.
-template <int IN_P, int HID_P, int NH, bool ATOMIC>
+template <int IN_P, int HID_P, int NH, int MODE>
 __device__ __forceinline__ void dw_flush(float *dst, int n_in, int width, DwAcc<IN_P, HID_P, NH> &dw,
                                          int lane)
 {
     constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
-    dw_store<HID_P, IN0, ATOMIC>(dst, width, n_in, dw.l0, lane);
+    dw_store<HID_P, IN0, MODE>(dst, width, n_in, dw.l0, lane);
     dst += width * n_in;
 #pragma unroll
     for (int li = 0; li < NH - 1; ++li) {
-        dw_store<HID_P, HID_P, ATOMIC>(dst, width, width, dw.hid[li], lane);
+        dw_store<HID_P, HID_P, MODE>(dst, width, width, dw.hid[li], lane);
         dst += width * width;
     }
-    dw_store<32, HID_P, ATOMIC>(dst, 32, width, dw.last, lane);
+    dw_store<32, HID_P, MODE>(dst, 32, width, dw.last, lane);
 }
 
 }  // namespace npm

@@ -37,9 +37,10 @@ struct FusedArgs {
     float *dw_part;          // per-wave weight-gradient partials (backward)
     double *partials;        // per-block FP64 loss partials
     float invN;
+    const uint32_t *perm;    // visiting order of the vertices (backward), or null
 };
 template <int IN_P, int HID_P, int NH, int F, bool BF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_query_fused(FusedArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_query_fused(FusedArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ uint32_t s_off[NPM_MAX_LEVELS];
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     stage_levels(a.g, s_off, s_res);
     __syncthreads();
     const GridView gv = grid_view(a.g, s_off, s_res, a.grid32, a.grid16);
-    const TrainIO io{a.n, a.pos, a.dir, a.rad, a.spdf, a.grad, a.invN};
+    const TrainIO io{a.n, a.pos, a.dir, a.rad, a.spdf, a.grad, a.invN, a.perm};
     const char *fwd = smem;
     const char *bwd = smem + (size_t)a.fwd_elems * ESZ;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -98,9 +99,19 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     }
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
     if (!a.grad) return;
-    // ---- per-wave weight-gradient partials
-    dw_flush<IN_P, HID_P, NH, false>(a.dw_part + gwave * (int64_t)mlp_weights, a.n_in, a.width, dw,
-                                     lane);
+    // ---- the block's weight-gradient partial: the four waves add theirs in
+    // turn into LDS (the weight images are no longer needed), then one store
+    float *acc = reinterpret_cast<float *>(smem);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+            if (w == 0) dw_flush<IN_P, HID_P, NH, DW_STORE>(acc, a.n_in, a.width, dw, lane);
+            else dw_flush<IN_P, HID_P, NH, DW_ADD>(acc, a.n_in, a.width, dw, lane);
+        }
+        __syncthreads();
+    }
+    float *dst = a.dw_part + (int64_t)blockIdx.x * mlp_weights;
+    for (int i = threadIdx.x; i < mlp_weights; i += blockDim.x) dst[i] = acc[i];
 }
 
 // Sums the per-wave partials of the MLP weight gradient into grad.
@@ -210,9 +221,10 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *d
 
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                           const float *rad, const float *spdf, float *grad, double *loss_out,
-                          hipStream_t s)
+                          const uint32_t *perm, hipStream_t s)
 {
     FusedArgs a = fused_args(ctx, n, pos);
+    a.perm = perm;
     a.dir = dir;
     a.rad = rad;
     a.spdf = spdf;
@@ -232,7 +244,7 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
         const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
         timed_begin(ctx, "fused_dw_sum", s, &tok);
         hipLaunchKernelGGL(k_dw_sum, dim3((count + 255) / 256), dim3(256), 0, s, ctx->s_dw_part,
-                           waves, count, grad + ctx->net.lay.grid_params);
+                           waves / 4, count, grad + ctx->net.lay.grid_params);
         timed_end(ctx, tok, s);
         e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_serve_train(RoundHdr *hdr, const DevReq
         const int64_t t0 = ((int64_t)(chunk - q.chunk_begin) * 4 + wave) * kTrainWaveTiles;
         if (t0 * 32 < q.n) {
             const GridView gv = grid_view(q.g, s_off, s_res, nullptr, q.grid16);
-            const TrainIO io{q.n, q.pos, q.dir, q.rad, q.spdf, q.grad, q.invN};
+            const TrainIO io{q.n, q.pos, q.dir, q.rad, q.spdf, q.grad, q.invN, nullptr};
             const char *fwd = smem;
             const char *bwd = smem + (size_t)q.fwd_elems * 2;
             DwAcc<IN_P, HID_P, NH> dw;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_serve_train(RoundHdr *hdr, const DevReq
                 if (t * 32 >= q.n) break;
                 backward_tile<IN_P, HID_P, NH, F, true>(gv, fwd, bwd, tbuf, io, t, lane, dw, lacc);
             }
-            dw_flush<IN_P, HID_P, NH, true>(q.grad + q.mlp_off, q.n_in, q.width, dw, lane);
+            dw_flush<IN_P, HID_P, NH, DW_ATOMIC>(q.grad + q.mlp_off, q.n_in, q.width, dw, lane);
             // FP64 loss of the wave (half 0 holds it), one atomic per wave
             double l = lacc;
             for (int off = 16; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);

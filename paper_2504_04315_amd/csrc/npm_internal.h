@@ -82,6 +82,10 @@ struct npm_ctx {
           *s_draw = nullptr, *s_dG = nullptr;
     float *s_dw_part = nullptr;        // dW partials
     int64_t dw_part_elems = 0;
+    // spatial order of a training batch (fused path)
+    uint32_t *s_perm = nullptr;        // [sort_n]
+    uint32_t *s_cells = nullptr;       // cell counts / offsets
+    int64_t sort_n = 0;
     npm::Timing timing;
 };
 
@@ -129,12 +133,18 @@ hipError_t staged_mlp_dw(npm_ctx *ctx, int64_t n, const float *G, const float *a
 hipError_t staged_scatter(npm_ctx *ctx, int64_t n, const float *pos, const float *dG,
                           float *grad, hipStream_t s);
 
+// spatial order of a batch (k_sort.hip): perm lists the vertices by cell
+hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *perm,
+                         uint32_t *cells, hipStream_t s);
+constexpr int64_t kSortMinBatch = 1 << 15;     // smaller batches are not reordered
+
 // fused path (k_fused.hip)
 hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                        uint64_t seed, uint32_t stream_id, float *lobes, float *pdf, float *sdir,
                        float *spdf, hipStream_t s);
+// perm (optional): the order in which to visit the vertices
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                           const float *rad, const float *spdf, float *grad, double *loss_out,
-                          hipStream_t s);
+                          const uint32_t *perm, hipStream_t s);
 
 }  // namespace npm

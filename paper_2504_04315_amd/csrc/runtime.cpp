@@ -207,7 +207,8 @@ static void free_ctx(npm_ctx *ctx)
     free_scratch(ctx);
     for (void *p : {(void *)ctx->params, (void *)ctx->grads, (void *)ctx->adam_m,
                     (void *)ctx->adam_v, ctx->grid16, (void *)ctx->mlp_img, ctx->mlp_img16,
-                    (void *)ctx->partials, (void *)ctx->stats, (void *)ctx->s_dw_part})
+                    (void *)ctx->partials, (void *)ctx->stats, (void *)ctx->s_dw_part,
+                    (void *)ctx->s_perm, (void *)ctx->s_cells})
         if (p) hipFree(p);
     for (auto &p : ctx->timing.pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : ctx->timing.free_events) hipEventDestroy(e);
@@ -354,12 +355,33 @@ static npm_status check_train(npm_ctx *ctx, int64_t n, const float *pos, const f
     return NPM_OK;
 }
 
+static hipError_t ensure_sort(npm_ctx *ctx, int64_t n)
+{
+    if (n <= ctx->sort_n) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    if (ctx->s_perm) hipFree(ctx->s_perm);
+    ctx->s_perm = nullptr;
+    ctx->sort_n = 0;
+    e = hipMalloc((void **)&ctx->s_perm, (size_t)n * 4);
+    if (e == hipSuccess && !ctx->s_cells) e = hipMalloc((void **)&ctx->s_cells, (size_t)4 << 18);
+    if (e != hipSuccess) return e;
+    ctx->sort_n = n;
+    return hipSuccess;
+}
+
 static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                                 const float *rad, const float *spdf, float *grad, double *loss_out,
                                 hipStream_t s)
 {
     if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
-        NPM_HIP(fused_backward(ctx, n, pos, dir, rad, spdf, grad, loss_out, s), "fused backward");
+        const uint32_t *perm = nullptr;
+        if (n >= kSortMinBatch && grad) {
+            NPM_HIP(ensure_sort(ctx, n), "order scratch allocation");
+            NPM_HIP(spatial_order(ctx, n, pos, ctx->s_perm, ctx->s_cells, s), "spatial order");
+            perm = ctx->s_perm;
+        }
+        NPM_HIP(fused_backward(ctx, n, pos, dir, rad, spdf, grad, loss_out, perm, s), "fused backward");
         return NPM_OK;
     }
     NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
@@ -403,8 +425,8 @@ npm_status npm_loss(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
         NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
         if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED && ctx->net.cfg.precision == NPM_PREC_BF16) {
             // the loss of the precision form: the fused kernel with no gradient output
-            NPM_HIP(fused_backward(ctx, n, pos, dir, radiance, sampling_pdf, nullptr, loss_out, s),
-                    "fused loss");
+            NPM_HIP(fused_backward(ctx, n, pos, dir, radiance, sampling_pdf, nullptr, loss_out,
+                                   nullptr, s), "fused loss");
             return NPM_OK;
         }
         NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");

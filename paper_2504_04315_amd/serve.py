@@ -160,23 +160,32 @@ def plan_requests(n_sessions, per_session, rate_hz, min_log2=10, max_log2=18, tr
     return out
 
 
-def make_request_buffers(plan, phases, base_seed=500):
-    """Device input/output tensors for every planned request (made before the
-    timed run so the submission loop does no allocation or host work)."""
+def make_request_buffers(plan, n_pools=4, pool_size=1 << 18, base_seed=500):
+    """Device input/output tensors for every planned request, made before the
+    timed run so the submission loop does no allocation or host work.  Inputs
+    are contiguous slices of a few seeded surface batches (one per session
+    group, with the field's phase varied)."""
     import torch
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    for i, r in enumerate(plan):
-        b = W.make_batch("surface", r["n"], seed=base_seed + i, phase=phases[r["session"]],
-                         tris_seed=r["session"])
-        r["pos"], r["dir"] = t(b.pos), t(b.dir)
+    pools = []
+    for i in range(n_pools):
+        b = W.make_batch("surface", pool_size, seed=base_seed + i, phase=0.3 * i, tris_seed=i)
+        pools.append([t(b.pos), t(b.dir), t(b.radiance), t(b.pdf)])
+    rng = np.random.default_rng(base_seed)
+    for r in plan:
+        P = pools[r["session"] % n_pools]
+        n = r["n"]
+        o = int(rng.integers(0, pool_size - n + 1))
+        r["pos"] = P[0][:, o:o + n].contiguous()
+        r["dir"] = P[1][:, o:o + n].contiguous()
         if r["kind"] == 0:
-            n = r["n"]
             r["lobes"] = torch.empty((4, 8, n), device="cuda")
             r["pdf"] = torch.empty(n, device="cuda")
             r["sdir"] = torch.empty((3, n), device="cuda")
             r["spdf"] = torch.empty(n, device="cuda")
         else:
-            r["rad"], r["spdfin"] = t(b.radiance), t(b.pdf)
+            r["rad"] = P[2][o:o + n].contiguous()
+            r["spdfin"] = P[3][o:o + n].contiguous()
             r["stats"] = torch.zeros(2, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     return plan

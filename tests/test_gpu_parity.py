@@ -186,11 +186,14 @@ def test_cfg1_train_step_parity(O, torch, mode):
 
 
 @pytest.mark.parametrize("mode", ["staged", "fused"])
-def test_cfg2_backward_parity(O, torch, mode):
+@pytest.mark.parametrize("n", [16384 + 17, 40001])
+def test_cfg2_backward_parity(O, torch, mode, n):
+    """Ragged tile counts; the larger batch is visited in spatial order by the
+    fused path."""
     model = B.NPM(B.make_config(W.CFG2, exec_mode=MODES[mode]))
     on = oracle_net(O, W.CFG2)
     params = randomize(model, on, np.random.default_rng(8), grid_sd=0.5)
-    batch = W.make_batch("surface", 16384 + 17, seed=22)        # ragged tile count
+    batch = W.make_batch("surface", n, seed=22)
     msgs, _, _ = check_backward(O, torch, model, on, params, batch, "cfg2")
     print("\n".join(msgs))
     model.close()

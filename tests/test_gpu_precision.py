@@ -1,0 +1,134 @@
+"""Precision form (BF16 MLP on MFMA with FP32 accumulation, FP16 grid, FP32
+mappings/softmax/log-density/sampling) against the FP64 oracle.
+
+On the production shape (16-level hash grid, 2^20 vertices, first 4,096 of
+them compared) it reports, and bounds:
+* pdf relative error (median, p99, max): p99 <= 1e-2, the target;
+* KL(oracle || precision form) per vertex, by quadrature of both mixtures on a
+  Fibonacci sphere;
+* cosine between the precision form's gradient and the oracle's, grid and MLP;
+* a chi-square test of the precision form's samples against the oracle pdf.
+The figures are also written to gpurun_out/precision_metrics.json when that
+directory exists.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2504_04315_amd import npm as B
+from paper_2504_04315_amd import workload as W
+from test_gpu_parity import dev, oracle_net, randomize
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+def fibonacci_sphere(m):
+    i = np.arange(m) + 0.5
+    z = 1 - 2 * i / m
+    a = i * math.pi * (3 - math.sqrt(5))
+    r = np.sqrt(1 - z * z)
+    return np.stack([r * np.cos(a), r * np.sin(a), z], 1)
+
+
+def lobes_to_raw(lobes):
+    """Raw outputs whose Table 1 mapping gives these lobe parameters, so the
+    oracle can evaluate the precision form's own mixture exactly."""
+    th, ph, ka, la = (np.clip(lobes[..., i].astype(np.float64), 1e-300, None) for i in range(4))
+    th = np.clip(th, 1e-12, 1 - 1e-12)
+    ph = np.clip(ph, 1e-12, 1 - 1e-12)
+    raw = np.stack([np.log(th / (1 - th)), np.log(ph / (1 - ph)), np.log(ka), np.log(la)], -1)
+    return raw.reshape(raw.shape[0], -1)
+
+
+def test_precision_form_metrics(O, torch):
+    net = W.CFG3
+    model = B.NPM(B.make_config(net))
+    on = oracle_net(O, net)
+    params = randomize(model, on, np.random.default_rng(31), grid_sd=0.5)
+    batch = W.make_batch("surface", W.N_CFG2, seed=3)
+    out = model.query(dev(torch, batch.pos), dev(torch, batch.dir), seed=9, stream_id=1)
+    torch.cuda.synchronize()
+    m = 4096
+    sub = batch.subset(np.arange(m))
+    q = O.query(on, sub.pos, params, dirs=sub.dir, seed=9, stream=1)
+    metrics = {}
+    # pdf relative error at the given directions
+    pdf = out["pdf"].cpu().numpy()[:m].astype(np.float64)
+    rel = np.abs(pdf / np.exp(q["logpdf"]) - 1.0)
+    metrics["pdf_rel_err"] = dict(median=float(np.median(rel)), p99=float(np.percentile(rel, 99)),
+                                  max=float(rel.max()))
+    # KL(oracle || precision form) by quadrature on 2^14 sphere points, 256 vertices
+    lob = out["lobes"].cpu().numpy()[:, :, :256].transpose(2, 1, 0)
+    raw_b = lobes_to_raw(lob)
+    d = fibonacci_sphere(1 << 14)
+    w = 4 * math.pi / d.shape[0]
+    kls = []
+    for i in range(256):
+        lo = O.logpdf(on, np.broadcast_to(q["raw"][i], (d.shape[0], 32)), d)
+        lb = O.logpdf(on, np.broadcast_to(raw_b[i], (d.shape[0], 32)), d)
+        po = np.exp(lo)
+        kls.append(float(np.sum(po * (lo - lb)) * w))
+    kls = np.array(kls)
+    metrics["kl_oracle_to_bf16"] = dict(median=float(np.median(kls)), max=float(kls.max()))
+    # gradient cosine on a training batch
+    tb = W.make_batch("surface", 16384, seed=33)
+    g = torch.zeros(on.n_params, device="cuda")
+    model.backward(dev(torch, tb.pos), dev(torch, tb.dir), dev(torch, tb.radiance),
+                   dev(torch, tb.pdf), grad=g)
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy().astype(np.float64)
+    ref = O.backward(on, tb.pos, tb.dir, tb.radiance, tb.pdf, params, with_abs=False)["grad"]
+    cos = lambda a, b: float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+    gp = on.grid_params
+    metrics["grad_cosine"] = dict(grid=cos(gg[:gp], ref[:gp]), mlp=cos(gg[gp:], ref[gp:]))
+    # chi-square of samples at 8 vertices (4096 draws each) against the oracle pdf
+    rng = np.random.default_rng(5)
+    verts = rng.choice(m, 8, replace=False)
+    pos8 = np.repeat(sub.pos[:, verts], 4096, axis=1)
+    so = model.query(dev(torch, pos8), None, seed=77, stream_id=2, lobes=False, pdf=False)
+    torch.cuda.synchronize()
+    sd = so["sample_dir"].cpu().numpy().T.astype(np.float64)
+    pvals = []
+    for k, v in enumerate(verts):
+        s = sd[k * 4096:(k + 1) * 4096]
+        mu_axis = np.array([0.0, 0.0, 1.0])
+        zb = np.linspace(-1, 1, 9)
+        pb = np.linspace(-math.pi, math.pi, 9)
+        H, _, _ = np.histogram2d(s[:, 2], np.arctan2(s[:, 1], s[:, 0]), bins=[zb, pb])
+        x, wx = np.polynomial.legendre.leggauss(16)
+        E = np.zeros((8, 8))
+        for i in range(8):
+            z = 0.5 * (zb[i + 1] - zb[i]) * (x + 1) + zb[i]
+            wz = 0.5 * (zb[i + 1] - zb[i]) * wx
+            for j in range(8):
+                p = 0.5 * (pb[j + 1] - pb[j]) * (x + 1) + pb[j]
+                wp = 0.5 * (pb[j + 1] - pb[j]) * wx
+                Z, P = np.meshgrid(z, p, indexing="ij")
+                R = np.sqrt(1 - Z * Z)
+                dd = np.stack([R * np.cos(P), R * np.sin(P), Z], -1).reshape(-1, 3)
+                lp = O.logpdf(on, np.broadcast_to(q["raw"][v], (dd.shape[0], 32)), dd)
+                E[i, j] = np.sum(np.exp(lp) * np.outer(wz, wp).reshape(-1))
+        E *= 4096 / E.sum()
+        keep = E > 5
+        chi = float(((H[keep] - E[keep]) ** 2 / E[keep]).sum())
+        pvals.append(float(stats.chi2.sf(chi, keep.sum() - 1)))
+    metrics["sample_chi2_pvalues"] = pvals
+    print(json.dumps(metrics, indent=1))
+    if os.path.isdir("gpurun_out"):
+        json.dump(metrics, open("gpurun_out/precision_metrics.json", "w"), indent=1)
+    assert metrics["pdf_rel_err"]["p99"] <= 1e-2
+    assert metrics["kl_oracle_to_bf16"]["median"] < 1e-3
+    assert metrics["grad_cosine"]["grid"] > 0.99 and metrics["grad_cosine"]["mlp"] > 0.99
+    assert min(pvals) > 1e-4
+    model.close()

@@ -128,7 +128,7 @@ def test_every_request_completes_once(torch):
     srv = S.Server(budget_bytes=8 << 30, max_sessions=8, round_vertices=1 << 14)
     sids = [srv.create_session(small_cfg(50 + i)) for i in range(4)]
     plan = S.plan_requests(4, 6, rate_hz=2000.0, min_log2=10, max_log2=14, train_every=3, seed=1)
-    S.make_request_buffers(plan, phases=[0.1 * i for i in range(4)])
+    S.make_request_buffers(plan, n_pools=2, pool_size=1 << 15)
     res = S.run_load(srv, sids, plan)
     st = srv.stats()
     assert st.requests_done == len(plan)
