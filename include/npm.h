@@ -66,6 +66,14 @@ enum { NPM_PREC_FP32 = 0, NPM_PREC_BF16 = 1 };
  * grid lookup to the sampled direction (and, in training, to the scatter).  */
 enum { NPM_EXEC_STAGED = 0, NPM_EXEC_FUSED = 1 };
 enum { NPM_INIT_NORMAL = 0, NPM_INIT_UNIFORM = 1 };
+/* Order in which the fused backward visits a training batch.
+ * NPM_ORDER_SPATIAL sorts the batch by the Morton code of each vertex's 64^3
+ * cell (a counting sort on the device, kept in context scratch) so that a
+ * wave's consecutive tiles touch nearby grid entries; NPM_ORDER_NONE keeps
+ * the caller's order; NPM_ORDER_AUTO picks the faster of the two for the
+ * batch size.  The order changes only the order of the floating-point
+ * gradient sums.                                                            */
+enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
 
 /* Network configuration (copied at create).
  * Grid (Sec. 5.1): n_levels uniform grids over the unit cube with
@@ -83,7 +91,8 @@ enum { NPM_INIT_NORMAL = 0, NPM_INIT_UNIFORM = 1 };
  * Init: grid N(0, scale^2) (NPM_INIT_NORMAL) or U(-scale, scale)
  *   (NPM_INIT_UNIFORM); MLP Xavier-uniform; all from `seed`.
  * Adam (Sec. 5.3): lr, beta1, beta2, eps, bias-corrected, eps outside the
- *   square root.                                                            */
+ *   square root.
+ * batch_order: one of NPM_ORDER_* (fused training only).                   */
 typedef struct {
     int32_t grid_kind;
     int32_t n_levels;
@@ -102,7 +111,7 @@ typedef struct {
     float beta1;
     float beta2;
     float eps;
-    int32_t reserved;
+    int32_t batch_order;
     uint64_t seed;
 } npm_config;
 

@@ -85,10 +85,16 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     DwAcc<IN_P, HID_P, NH> dw;
     dw.zero();
     double lacc = 0.0;
+    // Each wave takes a contiguous run of tiles: in a spatially ordered batch
+    // the waves resident at one time then work on distant regions (no two
+    // contending for the same grid lines) while each wave's consecutive tiles
+    // reuse the lines its previous tile brought into L2.
     const int64_t ntiles = (a.n + 31) / 32;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     const int64_t gwave = blockIdx.x * (int64_t)(blockDim.x / 64) + wave;
-    for (int64_t t = gwave; t < ntiles; t += nwaves)
+    const int64_t per = (ntiles + nwaves - 1) / nwaves;
+    const int64_t t_end = (gwave + 1) * per < ntiles ? (gwave + 1) * per : ntiles;
+    for (int64_t t = gwave * per; t < t_end; ++t)
         backward_tile<IN_P, HID_P, NH, F, BF>(gv, fwd, bwd, tbuf, io, t, lane, dw, lacc);
     // ---- loss partial of the block (FP64)
     red[threadIdx.x] = lacc;

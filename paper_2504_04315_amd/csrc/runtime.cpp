@@ -68,6 +68,7 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     if (c.precision == NPM_PREC_BF16 && c.exec_mode != NPM_EXEC_FUSED)
         return bad("the BF16 precision form runs fused only");
     if (c.grid_init != NPM_INIT_NORMAL && c.grid_init != NPM_INIT_UNIFORM) return bad("grid_init");
+    if (c.batch_order < NPM_ORDER_AUTO || c.batch_order > NPM_ORDER_SPATIAL) return bad("batch_order");
     if (!(std::isfinite(c.grid_init_scale) && c.grid_init_scale >= 0.0f)) return bad("grid_init_scale");
     if (!(std::isfinite(c.lr) && c.lr > 0.0f)) return bad("lr must be > 0");
     if (!(c.beta1 >= 0.0f && c.beta1 < 1.0f && c.beta2 >= 0.0f && c.beta2 < 1.0f))
@@ -376,7 +377,9 @@ static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const
 {
     if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
         const uint32_t *perm = nullptr;
-        if (n >= kSortMinBatch && grad) {
+        const int order = ctx->net.cfg.batch_order;
+        if (grad && n > 1 &&
+            (order == NPM_ORDER_SPATIAL || (order == NPM_ORDER_AUTO && n >= kSortMinBatch))) {
             NPM_HIP(ensure_sort(ctx, n), "order scratch allocation");
             NPM_HIP(spatial_order(ctx, n, pos, ctx->s_perm, ctx->s_cells, s), "spatial order");
             perm = ctx->s_perm;

@@ -185,12 +185,15 @@ def test_cfg1_train_step_parity(O, torch, mode):
     model.close()
 
 
-@pytest.mark.parametrize("mode", ["staged", "fused"])
+ORDERS = {"auto": B.ORDER_AUTO, "none": B.ORDER_NONE, "spatial": B.ORDER_SPATIAL}
+
+
+@pytest.mark.parametrize("mode,order", [("staged", "auto"), ("fused", "auto"),
+                                        ("fused", "none"), ("fused", "spatial")])
 @pytest.mark.parametrize("n", [16384 + 17, 40001])
-def test_cfg2_backward_parity(O, torch, mode, n):
-    """Ragged tile counts; the larger batch is visited in spatial order by the
-    fused path."""
-    model = B.NPM(B.make_config(W.CFG2, exec_mode=MODES[mode]))
+def test_cfg2_backward_parity(O, torch, mode, order, n):
+    """Ragged tile counts, in the caller's order and in spatial order."""
+    model = B.NPM(B.make_config(W.CFG2, exec_mode=MODES[mode], batch_order=ORDERS[order]))
     on = oracle_net(O, W.CFG2)
     params = randomize(model, on, np.random.default_rng(8), grid_sd=0.5)
     batch = W.make_batch("surface", n, seed=22)

@@ -43,3 +43,30 @@ def test_field_density_normalised_and_sampler_consistent():
     f = W.field_pdf(np.repeat(x[:1], d.shape[0], 0), d)
     mean_q = (d * (f * w)[:, None]).sum(0)
     assert np.all(np.abs(s.mean(0) - mean_q) < 5e-3)
+
+
+def test_device_batch_generator_matches_numpy_field():
+    """The torch restatement of the field (used for fresh device batches in
+    long training runs) equals the numpy definition, and its batches follow
+    the same distribution: the mean log field density of the sampled
+    directions (minus the field's expected entropy) and the mean weight L/p
+    agree with make_batch's within their Monte Carlo error."""
+    import torch
+    import field_torch as FT
+    rng = np.random.default_rng(0)
+    x = rng.random((4096, 3))
+    w = W.uniform_sphere(rng, 4096)
+    for a, b in zip(W.field_params(x, 0.0), FT.field_params(torch, torch.from_numpy(x))):
+        np.testing.assert_allclose(b.numpy(), a, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(FT.field_pdf(torch, torch.from_numpy(x), torch.from_numpy(w)).numpy(),
+                               W.field_pdf(x, w), rtol=1e-12)
+    n = 1 << 16
+    gen = FT.SurfaceBatches(torch, seed=3, tris_seed=3, device="cpu")
+    pos, d, rad, pdf = (t.numpy().astype(np.float64) for t in gen.next(n))
+    ref = W.make_batch("surface", n, seed=3)
+    assert np.abs(np.linalg.norm(d, axis=0) - 1).max() < 1e-6
+    for got, exp in ((np.log(pdf), np.log(ref.pdf.astype(np.float64))),
+                     (rad / pdf, ref.radiance.astype(np.float64) / ref.pdf)):
+        se = math.sqrt(got.var() / n + exp.var() / n)
+        assert abs(got.mean() - exp.mean()) < 5 * se, (got.mean(), exp.mean(), se)
+    assert np.allclose(pos.mean(axis=1), ref.pos.mean(axis=1), atol=0.01)
