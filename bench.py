@@ -43,8 +43,13 @@ ACT_B = 3 * 64 * 4               # hidden activations of one vertex
 MLP_F = 2 * 12288                # FLOPs of one pass over the 12,288 weights
 WORK = {
     # fused: streams + gathers + atomics only, intermediates stay on chip
+    # except the tile kernel's dG (32 FP32 per vertex), which the aggregated
+    # scatter reads back; the visiting order adds 4 B per vertex to each
     "fused_query": dict(bytes=24 + GATHER_B + 148, flops=MLP_F),
-    "fused_backward": dict(bytes=32 + GATHER_B + ATOMIC_B, flops=3 * MLP_F),
+    "fused_backward": dict(bytes=32 + 4 + GATHER_B + 32 * 4, flops=3 * MLP_F),
+    "fused_scatter": dict(bytes=12 + 4 + 32 * 4 + ATOMIC_B, flops=0),
+    # counting sort: positions read twice, two counter atomics, perm written
+    "spatial_sort": dict(bytes=2 * 12 + 2 * 8 + 4, flops=0),
     # staged: each kernel's own streams (feature-major intermediates)
     "staged_encode": dict(bytes=12 + GATHER_B + 32 * 4, flops=0),
     "staged_mlp_fwd": dict(bytes=32 * 4 + 32 * 4, flops=MLP_F),

@@ -427,12 +427,22 @@ __device__ __forceinline__ int64_t visit(const uint32_t *perm, int64_t v)
 // the x-adjacent corners and the F features of an entry are contiguous, and
 // the 64 / (8F) vertex-levels of an instruction are consecutive vertices of
 // one level.  dGt: the tile's dG in LDS, rows = features, stride kStride.
+//
+// Window: at a level where the lattice points around the tile's bounding box
+// (lo, hi: clamped positions) number at most WIN_PTS, the contributions are
+// first summed in a dense LDS window over that box (LDS atomics), and each
+// touched lattice point then costs one global atomic per feature, issued in
+// window order so that x-neighbours share lines.  In a spatially ordered
+// batch this covers the coarse levels, where the 32 vertices of a tile share
+// most corners.  The cell lookup is monotone in the position, so every corner
+// lies in the window; a corner that did not would take the direct path.
 
-template <int F>
+template <int F, int WIN_PTS>
 __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dGt,
                                              const float *__restrict__ pos, const uint32_t *perm,
                                              int64_t n, int64_t t, int lane,
-                                             float *__restrict__ grad)
+                                             float *__restrict__ grad, const float *lo,
+                                             const float *hi, float *win)
 {
     constexpr int LPV = 8 * F;              // lanes per vertex-level
     constexpr int VPI = 64 / LPV;           // vertex-levels per instruction
@@ -450,6 +460,29 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
         const uint32_t d1 = (uint32_t)D + 1u;
         const bool hashed = (gv.hashed_mask >> l) & 1u;
         const uint32_t off = gv.off[l];
+        auto entry = [&](uint32_t X, uint32_t Y, uint32_t Z) {
+            return off + (hashed ? ((X ^ (Y * 2654435761u) ^ (Z * 805459861u)) & gv.table_mask)
+                                 : X + d1 * (Y + d1 * Z));
+        };
+        int x0 = 0, y0 = 0, z0 = 0, ex = 0, ey = 0, ez = 0;
+        bool use_win = false;
+        if constexpr (WIN_PTS > 0) {
+            float fr;
+            int c1;
+            lattice_cell(lo[0], D, x0, fr); lattice_cell(hi[0], D, c1, fr); ex = c1 - x0 + 2;
+            lattice_cell(lo[1], D, y0, fr); lattice_cell(hi[1], D, c1, fr); ey = c1 - y0 + 2;
+            lattice_cell(lo[2], D, z0, fr); lattice_cell(hi[2], D, c1, fr); ez = c1 - z0 + 2;
+            // each extent is bounded before the product is formed: at fine
+            // levels an unordered tile spans ~2000 cells a side, whose cube
+            // overflows 32-bit arithmetic
+            use_win = ex <= WIN_PTS && ey <= WIN_PTS && ez <= WIN_PTS &&
+                      ex * ey <= WIN_PTS && ex * ey * ez <= WIN_PTS;
+        }
+        if (use_win) {
+            const int nw = ex * ey * ez * F;
+            for (int i = lane; i < nw; i += 64) win[i] = 0.0f;
+            wave_lds_fence();
+        }
 #pragma unroll
         for (int jj = 0; jj < 32 / VPI; ++jj) {
             const int j = jj * VPI + q;
@@ -462,21 +495,60 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
             lattice_cell(py[jj], D, cy, fy);
             lattice_cell(pz[jj], D, cz, fz);
             const uint32_t X = cx + bx, Y = cy + by, Z = cz + bz;
-            const uint32_t e = off + (hashed ? ((X ^ (Y * 2654435761u) ^ (Z * 805459861u)) & gv.table_mask)
-                                             : X + d1 * (Y + d1 * Z));
             const float w = (bx ? fx : 1.0f - fx) * (by ? fy : 1.0f - fy) * (bz ? fz : 1.0f - fz);
-            unsafeAtomicAdd(grad + (size_t)e * F + f, w * d);
+            const uint32_t wx = X - (uint32_t)x0, wy = Y - (uint32_t)y0, wz = Z - (uint32_t)z0;
+            if (use_win && wx < (uint32_t)ex && wy < (uint32_t)ey && wz < (uint32_t)ez)
+                __hip_atomic_fetch_add(win + ((wz * ey + wy) * ex + wx) * F + f, w * d,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            else
+                unsafeAtomicAdd(grad + (size_t)entry(X, Y, Z) * F + f, w * d);
         }
+        if (use_win) {
+            wave_lds_fence();
+            const int nw = ex * ey * ez * F;
+            for (int i = lane; i < nw; i += 64) {
+                const float s = win[i];
+                if (s != 0.0f) {
+                    const int p = i / F, pf = i % F;
+                    const int pyz = p / ex, wx = p - pyz * ex, wz = pyz / ey, wy = pyz - wz * ey;
+                    unsafeAtomicAdd(grad + (size_t)entry(x0 + wx, y0 + wy, z0 + wz) * F + pf, s);
+                }
+            }
+            wave_lds_fence();
+        }
+    }
+}
+
+// Bounding box of the tile's clamped positions (the lattice lookup clamps to
+// the unit cube), over the 32 vertices of a T32 tile.
+__device__ __forceinline__ void tile_bbox(float px, float py, float pz, float *lo, float *hi)
+{
+    const float c[3] = {fminf(fmaxf(px, 0.0f), 1.0f), fminf(fmaxf(py, 0.0f), 1.0f),
+                        fminf(fmaxf(pz, 0.0f), 1.0f)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float mn = c[a], mx = c[a];
+#pragma unroll
+        for (int m = 1; m < 32; m <<= 1) {
+            mn = fminf(mn, __shfl_xor(mn, m, 64));
+            mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+        }
+        lo[a] = mn;
+        hi[a] = mx;
     }
 }
 
 // One tile of the backward: forward with activations in registers, the
 // KL-gradient head, the delta chain, the weight gradients into dw, and the
 // grid scatter.  lacc accumulates -w log V (FP64) of half 0's vertices.
-template <int IN_P, int HID_P, int NH, int F, bool BF>
+// STORE_DG: the tile's dG is stored at dg_tiles + t * OUT0 * 32 (row r =
+// feature r, 32 vertices of the visiting order) for the aggregated scatter
+// kernel; otherwise it is scattered into the grid here.
+template <int IN_P, int HID_P, int NH, int F, bool BF, bool STORE_DG = false>
 __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fwd, const char *bwd,
                                               float *tbuf, const TrainIO &io, int64_t t, int lane,
-                                              DwAcc<IN_P, HID_P, NH> &dw, double &lacc)
+                                              DwAcc<IN_P, HID_P, NH> &dw, double &lacc,
+                                              float *dg_tiles = nullptr)
 {
     constexpr int ESZ = BF ? 2 : 4;
     constexpr int IN0 = IN_P < 32 ? 32 : IN_P;       // layer-0 input rows padded to a 32 block
@@ -537,11 +609,22 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
     }
     float dG[OUT0 / 2];
     layer<BF, HID_P, OUT0>(im, dh, dG, lane);
-    // ---- grid scatter, coalesced: dG through the wave's LDS buffer
-    wave_lds_fence();
-    t32_to_lds<OUT0 / 2>(tbuf, dG, lane);
-    wave_lds_fence();
-    scatter_tile<F>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad);
+    if constexpr (STORE_DG) {
+        float *dst = dg_tiles + (size_t)t * OUT0 * 32 + (lane & 31);
+#pragma unroll
+        for (int a = 0; a < OUT0 / 2; ++a) dst[nf(h, a) * 32] = dG[a];
+    } else {
+        // ---- grid scatter, coalesced: dG through the wave's LDS buffer, the
+        // rows above it as the aggregation window
+        constexpr int WIN_PTS = (HID_P - OUT0) * kStride / F;
+        float lo[3], hi[3];
+        if constexpr (WIN_PTS > 0) tile_bbox(px, py, pz, lo, hi);
+        wave_lds_fence();
+        t32_to_lds<OUT0 / 2>(tbuf, dG, lane);
+        wave_lds_fence();
+        scatter_tile<F, WIN_PTS>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad, lo, hi,
+                                 tbuf + OUT0 * kStride);
+    }
 }
 
 // Writes (or atomically adds) a wave's weight gradients in the flat layer

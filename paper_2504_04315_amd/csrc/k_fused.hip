@@ -38,6 +38,7 @@ struct FusedArgs {
     double *partials;        // per-block FP64 loss partials
     float invN;
     const uint32_t *perm;    // visiting order of the vertices (backward), or null
+    float *dg_tiles;         // per-tile dG for the aggregated scatter (backward)
 };
 template <int IN_P, int HID_P, int NH, int F, bool BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_query_fused(FusedArgs a)
@@ -95,7 +96,8 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     const int64_t per = (ntiles + nwaves - 1) / nwaves;
     const int64_t t_end = (gwave + 1) * per < ntiles ? (gwave + 1) * per : ntiles;
     for (int64_t t = gwave * per; t < t_end; ++t)
-        backward_tile<IN_P, HID_P, NH, F, BF>(gv, fwd, bwd, tbuf, io, t, lane, dw, lacc);
+        backward_tile<IN_P, HID_P, NH, F, BF, true>(gv, fwd, bwd, tbuf, io, t, lane, dw, lacc,
+                                                    a.dg_tiles);
     // ---- loss partial of the block (FP64)
     red[threadIdx.x] = lacc;
     __syncthreads();
@@ -118,6 +120,54 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     }
     float *dst = a.dw_part + (int64_t)blockIdx.x * mlp_weights;
     for (int i = threadIdx.x; i < mlp_weights; i += blockDim.x) dst[i] = acc[i];
+}
+
+// Aggregated grid scatter of the per-tile dG (stride `rows` rows of 32 per
+// tile) in the same visiting order.  A wave takes a contiguous run of tiles;
+// per tile it stages the n_levels * F dG rows in LDS, takes the tile's
+// bounding box and scatters with the LDS window (scatter_tile).  Kept apart
+// from the MLP kernel: the atomics are bound by the rate of line requests
+// the memory system accepts, and at the one wave per SIMD the MLP kernel's
+// registers allow, a wave waiting on its atomics leaves its SIMD idle, while
+// this kernel runs four waves per SIMD.
+constexpr int kScatterRows = 64;    // per wave: 32 dG rows + 32 window rows
+
+template <int F>
+__global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
+                                                       const float *__restrict__ pos,
+                                                       const uint32_t *perm,
+                                                       const float *__restrict__ dgt, int rows,
+                                                       float *__restrict__ grad)
+{
+    __shared__ uint32_t s_off[NPM_MAX_LEVELS];
+    __shared__ int s_res[NPM_MAX_LEVELS];
+    __shared__ __attribute__((aligned(16))) float buf[4 * kScatterRows * kStride];
+    stage_levels(g, s_off, s_res);
+    __syncthreads();
+    const GridView gv = grid_view(g, s_off, s_res, nullptr, nullptr);
+    constexpr int WIN_PTS = (kScatterRows - 32) * kStride / F;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float *tb = buf + wave * kScatterRows * kStride;
+    const int lr = g.n_levels * g.feat;           // dG rows the scatter reads (<= 32)
+    const int64_t ntiles = (n + 31) / 32;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t gwave = blockIdx.x * (int64_t)4 + wave;
+    const int64_t per = (ntiles + nwaves - 1) / nwaves;
+    const int64_t t_end = (gwave + 1) * per < ntiles ? (gwave + 1) * per : ntiles;
+    for (int64_t t = gwave * per; t < t_end; ++t) {
+        const int64_t v = t * 32 + (lane & 31);
+        const int64_t vv = visit(perm, v < n ? v : n - 1);
+        float lo[3], hi[3];
+        tile_bbox(pos[vv], pos[n + vv], pos[2 * n + vv], lo, hi);
+        const float *src = dgt + (size_t)t * rows * 32;
+        for (int i = lane; i < lr * 8; i += 64) {
+            const f32x4 q = reinterpret_cast<const f32x4 *>(src)[i];
+            *reinterpret_cast<f32x4 *>(tb + (i >> 3) * kStride + (i & 7) * 4) = q;
+        }
+        wave_lds_fence();
+        scatter_tile<F, WIN_PTS>(gv, tb, pos, perm, n, t, lane, grad, lo, hi, tb + 32 * kStride);
+        wave_lds_fence();
+    }
 }
 
 // Sums the per-wave partials of the MLP weight gradient into grad.
@@ -227,7 +277,7 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *d
 
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                           const float *rad, const float *spdf, float *grad, double *loss_out,
-                          const uint32_t *perm, hipStream_t s)
+                          const uint32_t *perm, float *dg_tiles, hipStream_t s)
 {
     FusedArgs a = fused_args(ctx, n, pos);
     a.perm = perm;
@@ -238,6 +288,7 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
     a.dw_part = ctx->s_dw_part;
     a.partials = ctx->partials;
     a.invN = 1.0f / (float)n;
+    a.dg_tiles = grad ? dg_tiles : nullptr;
     hipError_t e = hipSuccess;
     int tok;
     timed_begin(ctx, "fused_backward", s, &tok);
@@ -245,6 +296,23 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
     else NPM_FUSED_DISPATCH(run_backward, false);
     timed_end(ctx, tok, s);
     if (e != hipSuccess) return e;
+    if (grad) {
+        const int64_t tiles = (n + 31) / 32;
+        const int64_t waves = std::min<int64_t>(tiles, 4096);
+        const int rows = std::max(ctx->net.mlp.in_p, 32);
+        timed_begin(ctx, "fused_scatter", s, &tok);
+        switch (ctx->net.grid.feat) {
+        case 1: hipLaunchKernelGGL(k_scatter_tiles<1>, dim3((waves + 3) / 4), dim3(256), 0, s,
+                                   ctx->net.grid, n, pos, perm, dg_tiles, rows, grad); break;
+        case 2: hipLaunchKernelGGL(k_scatter_tiles<2>, dim3((waves + 3) / 4), dim3(256), 0, s,
+                                   ctx->net.grid, n, pos, perm, dg_tiles, rows, grad); break;
+        default: hipLaunchKernelGGL(k_scatter_tiles<4>, dim3((waves + 3) / 4), dim3(256), 0, s,
+                                    ctx->net.grid, n, pos, perm, dg_tiles, rows, grad); break;
+        }
+        timed_end(ctx, tok, s);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const int waves = backward_waves(n);
     if (grad) {
         const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);

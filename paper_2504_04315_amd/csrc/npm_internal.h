@@ -86,6 +86,9 @@ struct npm_ctx {
     uint32_t *s_perm = nullptr;        // [sort_n]
     uint32_t *s_cells = nullptr;       // cell counts / offsets
     int64_t sort_n = 0;
+    // per-tile dG of a fused training batch, for the aggregated scatter
+    float *s_dgt = nullptr;            // [dgt_tiles][max(in_p, 32)][32]
+    int64_t dgt_tiles = 0;
     npm::Timing timing;
 };
 
@@ -136,19 +139,21 @@ hipError_t staged_scatter(npm_ctx *ctx, int64_t n, const float *pos, const float
 // spatial order of a batch (k_sort.hip): perm lists the vertices by cell
 hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *perm,
                          uint32_t *cells, hipStream_t s);
-// Smallest batch NPM_ORDER_AUTO sorts.  Measured on the 16-level hash grid at
-// 2^20 vertices the sorted batch alone is slower (4.92 + 0.22 ms against
-// 4.75 ms): the backward is bound by atomic requests, which sorting does not
-// remove, and nearby vertices make the same lines hot.  So AUTO never sorts.
-constexpr int64_t kSortMinBatch = INT64_MAX;
+// Smallest batch NPM_ORDER_AUTO sorts.  On the 16-level hash grid at 2^20
+// vertices the sort (0.22 ms) halves the scatter's line requests through the
+// LDS window (4.43 -> 2.42 ms) and speeds the tile kernel's gathers (1.61 ->
+// 1.28 ms); a batch of 2^15 vertices is still dense enough for the window to
+// cover the coarse levels.
+constexpr int64_t kSortMinBatch = 1 << 15;
 
 // fused path (k_fused.hip)
 hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                        uint64_t seed, uint32_t stream_id, float *lobes, float *pdf, float *sdir,
                        float *spdf, hipStream_t s);
-// perm (optional): the order in which to visit the vertices
+// perm (optional): the order in which to visit the vertices; dg_tiles: the
+// per-tile dG buffer (required when grad is set)
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                           const float *rad, const float *spdf, float *grad, double *loss_out,
-                          const uint32_t *perm, hipStream_t s);
+                          const uint32_t *perm, float *dg_tiles, hipStream_t s);
 
 }  // namespace npm

@@ -209,7 +209,7 @@ static void free_ctx(npm_ctx *ctx)
     for (void *p : {(void *)ctx->params, (void *)ctx->grads, (void *)ctx->adam_m,
                     (void *)ctx->adam_v, ctx->grid16, (void *)ctx->mlp_img, ctx->mlp_img16,
                     (void *)ctx->partials, (void *)ctx->stats, (void *)ctx->s_dw_part,
-                    (void *)ctx->s_perm, (void *)ctx->s_cells})
+                    (void *)ctx->s_perm, (void *)ctx->s_cells, (void *)ctx->s_dgt})
         if (p) hipFree(p);
     for (auto &p : ctx->timing.pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : ctx->timing.free_events) hipEventDestroy(e);
@@ -371,6 +371,22 @@ static hipError_t ensure_sort(npm_ctx *ctx, int64_t n)
     return hipSuccess;
 }
 
+static hipError_t ensure_dgt(npm_ctx *ctx, int64_t n)
+{
+    const int64_t tiles = (n + 31) / 32;
+    if (tiles <= ctx->dgt_tiles) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    if (ctx->s_dgt) hipFree(ctx->s_dgt);
+    ctx->s_dgt = nullptr;
+    ctx->dgt_tiles = 0;
+    const int64_t rows = std::max(ctx->net.mlp.in_p, 32);
+    e = hipMalloc((void **)&ctx->s_dgt, (size_t)tiles * rows * 32 * sizeof(float));
+    if (e != hipSuccess) return e;
+    ctx->dgt_tiles = tiles;
+    return hipSuccess;
+}
+
 static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                                 const float *rad, const float *spdf, float *grad, double *loss_out,
                                 hipStream_t s)
@@ -384,7 +400,9 @@ static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const
             NPM_HIP(spatial_order(ctx, n, pos, ctx->s_perm, ctx->s_cells, s), "spatial order");
             perm = ctx->s_perm;
         }
-        NPM_HIP(fused_backward(ctx, n, pos, dir, rad, spdf, grad, loss_out, perm, s), "fused backward");
+        if (grad) NPM_HIP(ensure_dgt(ctx, n), "dG scratch allocation");
+        NPM_HIP(fused_backward(ctx, n, pos, dir, rad, spdf, grad, loss_out, perm,
+                               grad ? ctx->s_dgt : nullptr, s), "fused backward");
         return NPM_OK;
     }
     NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
@@ -429,7 +447,7 @@ npm_status npm_loss(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
         if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED && ctx->net.cfg.precision == NPM_PREC_BF16) {
             // the loss of the precision form: the fused kernel with no gradient output
             NPM_HIP(fused_backward(ctx, n, pos, dir, radiance, sampling_pdf, nullptr, loss_out,
-                                   nullptr, s), "fused loss");
+                                   nullptr, nullptr, s), "fused loss");
             return NPM_OK;
         }
         NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");
