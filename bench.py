@@ -114,9 +114,9 @@ def cpu_baseline(netcfg, batch, params, seconds):
                    with_abs=False)
         return time.perf_counter() - t0
 
-    q0, b0 = t_query(2048) / 2048, t_backward(256) / 256
-    mq = int(min(batch.n, max(2048, 0.4 * seconds / q0)))
-    mb = int(min(batch.n, max(256, 0.4 * seconds / b0)))
+    q0, b0 = t_query(8192) / 8192, t_backward(4096) / 4096
+    mq = int(min(batch.n, max(8192, 0.2 * seconds / q0)))
+    mb = int(min(batch.n, max(4096, 0.8 * seconds / b0)))
     tq, tb = t_query(mq), t_backward(mb)
     p = params.copy()
     g = np.zeros_like(p)
@@ -285,8 +285,10 @@ def main():
     roof = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "kernel": dom,
             "kernel_avg_ms": round(r["avg_ms"], 4), "algorithmic_per_launch": per_launch,
-            "traffic": (None if tr is None else {"fetch_bytes": tr["fetch_bytes"],
-                                                 "write_bytes": tr["write_bytes"]})}
+            # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters
+            # (copy-calibrated), null when the kernels changed since
+            "traffic": None if tr is None else tr["fetch_bytes"] + tr["write_bytes"],
+            "traffic_fetch_write": (None if tr is None else [tr["fetch_bytes"], tr["write_bytes"]])}
     line = {
         "metric": METRIC,
         "value": n / (ms_per_step / 1e3),
