@@ -174,6 +174,54 @@ def serving_bench(n_sessions=32, per_session=6, load=0.7):
     return out
 
 
+def paper_config_bench(reps=20, warm=5):
+    """The paper's own network (8 dense levels 8..86 x F=4, MLP 32-64-64-32,
+    lr 5e-3) on its own batch sizes: queries of one 1280x720 wavefront
+    (921,600 vertices; dir given, lobes + pdf + sample + sample pdf) and
+    training steps of 2^18 vertices, fused FP32 and precision form; median of
+    `reps` HIP-event timings after `warm` warm-ups.  The paper's figures
+    (about 3 ms and 10 ms on an RTX 3070) are context: another GPU."""
+    import torch
+    from paper_2504_04315_amd import npm as B
+    from paper_2504_04315_amd import workload as W
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nq, nt = W.N_PAPER_QUERY, W.N_PAPER_TRAIN
+    qb = W.make_batch("surface", nq, seed=71)
+    tb = W.make_batch("surface", nt, seed=72)
+    qa = [t(qb.pos), t(qb.dir)]
+    ta = [t(tb.pos), t(tb.dir), t(tb.radiance), t(tb.pdf)]
+    out = {"network": "8 dense levels 8..86 x F=4, MLP 32-64-64-32, K=8",
+           "query_batch": nq, "train_batch": nt,
+           "paper": {"query_ms": 3.0, "train_ms": 10.0, "hardware": "RTX 3070"}}
+    for prec in ("fp32", "bf16"):
+        m = B.NPM(B.make_config(W.PAPER, exec_mode=B.EXEC_FUSED, precision=prec))
+        o = dict(lobes=torch.empty((4, 8, nq), device="cuda"), pdf=torch.empty(nq, device="cuda"),
+                 sample_dir=torch.empty((3, nq), device="cuda"),
+                 sample_pdf=torch.empty(nq, device="cuda"))
+        def timed(fn):
+            for i in range(warm):
+                fn(i)
+            ms = []
+            for i in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn(100 + i)
+                b.record()
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+            return float(np.median(ms))
+        lib = B.lib()
+        q_ms = timed(lambda i: B.check(lib.npm_query(
+            m.handle, nq, B._ptr(qa[0]), B._ptr(qa[1]), i, 0, B._ptr(o["lobes"]),
+            B._ptr(o["pdf"]), B._ptr(o["sample_dir"]), B._ptr(o["sample_pdf"]), B._stream())))
+        t_ms = timed(lambda i: m.train_step(*ta))
+        out[prec] = {"query_ms": q_ms, "train_ms": t_ms,
+                     "query_vertices_per_s": nq / (q_ms / 1e3),
+                     "train_vertices_per_s": nt / (t_ms / 1e3)}
+        m.close()
+    return out
+
+
 def load_traffic(workload, sha):
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
@@ -324,6 +372,9 @@ def main():
         print("serving ...", file=sys.stderr, flush=True)
         line["serving"] = serving_bench()
         line["p99_latency_ms"] = line["serving"]["shared_bf16"]["latency_ms"]["p99"]
+    if not (args.no_serving or args.profile):
+        print("paper configuration ...", file=sys.stderr, flush=True)
+        line["paper_config"] = paper_config_bench()
     if not (args.no_cpu_baseline or args.profile):
         print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(netcfg, batch, params0, args.cpu_seconds)

@@ -170,15 +170,21 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
     }
 }
 
-// Sums the per-wave partials of the MLP weight gradient into grad.
-__global__ void k_dw_sum(const float *__restrict__ part, int nparts, int count,
-                         float *__restrict__ grad)
+// Sums the per-block partials of the MLP weight gradient into grad: a block
+// of 256 threads covers 64 weights, its four thread rows a quarter of the
+// partials each, then the rows add in LDS.
+__global__ __launch_bounds__(256) void k_dw_sum(const float *__restrict__ part, int nparts,
+                                                int count, float *__restrict__ grad)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
+    __shared__ float red[4][64];
+    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + x;
     float s = 0.0f;
-    for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * count + i];
-    grad[i] += s;
+    if (i < count)
+        for (int p = y; p < nparts; p += 4) s += part[(int64_t)p * count + i];
+    red[y][x] = s;
+    __syncthreads();
+    if (y == 0 && i < count) grad[i] += (red[0][x] + red[1][x]) + (red[2][x] + red[3][x]);
 }
 
 // ------------------------------------------------------------------ launch
@@ -317,7 +323,7 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
     if (grad) {
         const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
         timed_begin(ctx, "fused_dw_sum", s, &tok);
-        hipLaunchKernelGGL(k_dw_sum, dim3((count + 255) / 256), dim3(256), 0, s, ctx->s_dw_part,
+        hipLaunchKernelGGL(k_dw_sum, dim3((count + 63) / 64), dim3(256), 0, s, ctx->s_dw_part,
                            waves / 4, count, grad + ctx->net.lay.grid_params);
         timed_end(ctx, tok, s);
         e = hipGetLastError();

@@ -46,15 +46,15 @@ __global__ void k_sort_count(const float *__restrict__ pos, int64_t n, uint32_t 
     if (v < n) atomicAdd(cnt + sort_cell(pos, n, v), 1u);
 }
 
-// Exclusive prefix sum of the 2^18 counts in one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ cnt)
+// Exclusive prefix sum of the 2^18 counts in two coalesced passes: each block
+// of 1024 threads scans its 1024 counts in LDS and records their total; then
+// each block adds the totals of the blocks before it.
+constexpr int kScanBlocks = kSortCells / 1024;     // 256
+
+__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *part)
 {
-    constexpr int PER = kSortCells / 1024;
-    __shared__ uint32_t part[1024];
     const int t = threadIdx.x;
-    uint32_t s = 0;
-    for (int i = 0; i < PER; ++i) s += cnt[t * PER + i];
-    part[t] = s;
+    part[t] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         const uint32_t add = t >= off ? part[t - off] : 0u;
@@ -62,12 +62,32 @@ __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ cnt)
         part[t] += add;
         __syncthreads();
     }
-    uint32_t run = part[t] - s;                     // exclusive prefix of this chunk
-    for (int i = 0; i < PER; ++i) {
-        const uint32_t c = cnt[t * PER + i];
-        cnt[t * PER + i] = run;
-        run += c;
+    return part[t];
+}
+
+__global__ __launch_bounds__(1024) void k_sort_scan_local(uint32_t *__restrict__ cnt,
+                                                          uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t part[1024];
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    const uint32_t v = cnt[i];
+    const uint32_t incl = block_inclusive_scan(v, part);
+    cnt[i] = incl - v;
+    if (threadIdx.x == 1023) sums[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(1024) void k_sort_scan_add(uint32_t *__restrict__ cnt,
+                                                        const uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t part[kScanBlocks];
+    const int t = threadIdx.x;
+    if (t < kScanBlocks) part[t] = t < (int)blockIdx.x ? sums[t] : 0u;
+    __syncthreads();
+    for (int w = kScanBlocks / 2; w > 0; w >>= 1) {
+        if (t < w) part[t] += part[t + w];
+        __syncthreads();
     }
+    cnt[blockIdx.x * 1024 + t] += part[0];
 }
 
 __global__ void k_sort_place(const float *__restrict__ pos, int64_t n, uint32_t *__restrict__ off,
@@ -77,6 +97,7 @@ __global__ void k_sort_place(const float *__restrict__ pos, int64_t n, uint32_t 
     if (v < n) perm[atomicAdd(off + sort_cell(pos, n, v), 1u)] = (uint32_t)v;
 }
 
+// cells: kSortCells counters followed by kScanBlocks block totals
 hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *perm,
                          uint32_t *cells, hipStream_t s)
 {
@@ -85,7 +106,10 @@ hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *pe
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_sort_zero, dim3(256), dim3(256), 0, s, cells);
     hipLaunchKernelGGL(k_sort_count, dim3(blocks), dim3(256), 0, s, pos, n, cells);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, cells);
+    hipLaunchKernelGGL(k_sort_scan_local, dim3(kScanBlocks), dim3(1024), 0, s, cells,
+                       cells + kSortCells);
+    hipLaunchKernelGGL(k_sort_scan_add, dim3(kScanBlocks), dim3(1024), 0, s, cells,
+                       cells + kSortCells);
     hipLaunchKernelGGL(k_sort_place, dim3(blocks), dim3(256), 0, s, pos, n, cells, perm);
     timed_end(ctx, tok, s);
     return hipGetLastError();

@@ -84,7 +84,7 @@ struct npm_ctx {
     int64_t dw_part_elems = 0;
     // spatial order of a training batch (fused path)
     uint32_t *s_perm = nullptr;        // [sort_n]
-    uint32_t *s_cells = nullptr;       // cell counts / offsets
+    uint32_t *s_cells = nullptr;       // 2^18 cell counts / offsets, 256 block totals
     int64_t sort_n = 0;
     // per-tile dG of a fused training batch, for the aggregated scatter
     float *s_dgt = nullptr;            // [dgt_tiles][max(in_p, 32)][32]

@@ -365,7 +365,8 @@ static hipError_t ensure_sort(npm_ctx *ctx, int64_t n)
     ctx->s_perm = nullptr;
     ctx->sort_n = 0;
     e = hipMalloc((void **)&ctx->s_perm, (size_t)n * 4);
-    if (e == hipSuccess && !ctx->s_cells) e = hipMalloc((void **)&ctx->s_cells, (size_t)4 << 18);
+    if (e == hipSuccess && !ctx->s_cells)
+        e = hipMalloc((void **)&ctx->s_cells, ((size_t)1 << 18) * 4 + 256 * 4);  // counts, block totals
     if (e != hipSuccess) return e;
     ctx->sort_n = n;
     return hipSuccess;

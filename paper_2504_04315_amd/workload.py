@@ -69,8 +69,17 @@ CFG5 = replace(CFG2, log2_table=17, precision="bf16", seed=5)
 TINY = NetConfig(n_levels=2, feat=2, base_res=4, max_res=16, log2_table=8, dense_only=False,
                  n_hidden=2, width=8, grid_init="uniform", grid_init_scale=0.3, seed=7)
 
+# The paper's own network (Sec. 5.3): 8 dense levels 8..86 x F=4, three linear
+# layers of width 64 (MLP 32-64-64-32), lr 5e-3; query batch = one 1280x720
+# wavefront, training batch 2^18 (Sec. 6.4).  Grid init is not stated: U(+-1e-4).
+PAPER = NetConfig(n_levels=8, feat=4, base_res=8, max_res=86, log2_table=19, dense_only=True,
+                  n_hidden=2, width=64, lr=5e-3, grid_init="uniform", grid_init_scale=1e-4,
+                  seed=6)
+
 N_CFG1 = 16384
 N_CFG2 = 1 << 20
+N_PAPER_QUERY = 1280 * 720
+N_PAPER_TRAIN = 1 << 18
 
 
 # ----------------------------------------------------------------------------

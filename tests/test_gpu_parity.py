@@ -267,3 +267,21 @@ def test_edge_cases(O, torch, mode):
     torch.cuda.synchronize()
     assert float(g.abs().max()) == 0.0
     model.close()
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_paper_config_parity(O, torch, mode):
+    """The paper's own network (8 dense levels 8..86 x F=4, MLP 32-64-64-32):
+    stages and query on a ragged surface batch, and the gradient of a
+    training batch in spatial order (fused) or as given (staged)."""
+    model = B.NPM(B.make_config(W.PAPER, exec_mode=MODES[mode], batch_order=B.ORDER_SPATIAL))
+    on = oracle_net(O, W.PAPER)
+    rng = np.random.default_rng(12)
+    params = randomize(model, on, rng, grid_sd=0.5)
+    batch = W.make_batch("surface", 8192 + 45, seed=61)
+    msgs = check_stages(O, torch, model, on, params, batch.pos)
+    m2, _ = check_query(O, torch, model, on, params, batch)
+    m3, _, _ = check_backward(O, torch, model, on, params, W.make_batch("surface", 6001, seed=62),
+                              "paper")
+    print("\n".join(msgs + m2 + m3))
+    model.close()
