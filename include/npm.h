@@ -92,7 +92,13 @@ enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
  *   (NPM_INIT_UNIFORM); MLP Xavier-uniform; all from `seed`.
  * Adam (Sec. 5.3): lr, beta1, beta2, eps, bias-corrected, eps outside the
  *   square root.
- * batch_order: one of NPM_ORDER_* (fused training only).                   */
+ * batch_order: one of NPM_ORDER_* (fused training only).
+ * ema_decay: 0 (off) or d in (0, 1).  When on, every optimizer step also
+ *   updates an exponential moving average of the parameters,
+ *   ema <- d * ema + (1 - d) * p (after the step, initialised to the
+ *   initial parameters), and npm_query, npm_encode and npm_forward_raw
+ *   evaluate the network with the averaged weights, as the paper does for
+ *   inference (Sec. 5.3); training always uses the current weights.       */
 typedef struct {
     int32_t grid_kind;
     int32_t n_levels;
@@ -112,6 +118,7 @@ typedef struct {
     float beta2;
     float eps;
     int32_t batch_order;
+    float ema_decay;
     uint64_t seed;
 } npm_config;
 
@@ -168,7 +175,8 @@ npm_status npm_destroy(npm_ctx *ctx);
  *              2*pi*phi).
  *   pdf        [n] out: mixture density at dir (needs dir), or NULL.
  *   sample_dir [3][n] out: one direction drawn from the mixture, or NULL.
- *   sample_pdf [n] out: mixture density at sample_dir, or NULL.          */
+ *   sample_pdf [n] out: mixture density at sample_dir, or NULL.
+ * With ema_decay > 0 the network is evaluated with the averaged weights.   */
 npm_status npm_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                      uint64_t rng_seed, uint32_t rng_stream, float *lobes, float *pdf,
                      float *sample_dir, float *sample_pdf, void *stream);
@@ -219,10 +227,13 @@ npm_status npm_forward_raw(npm_ctx *ctx, int64_t n, const float *pos, float *raw
 
 /* Host copies of the state.  which: NPM_STATE_PARAMS (FP32 master
  * parameters), NPM_STATE_GRADS (the context's gradient buffer),
- * NPM_STATE_ADAM_M, NPM_STATE_ADAM_V.  count must equal n_params.  These
- * calls synchronise the device.  Setting PARAMS also refreshes the
- * low-precision copies used by NPM_PREC_BF16.                              */
-enum { NPM_STATE_PARAMS = 0, NPM_STATE_GRADS = 1, NPM_STATE_ADAM_M = 2, NPM_STATE_ADAM_V = 3 };
+ * NPM_STATE_ADAM_M, NPM_STATE_ADAM_V, NPM_STATE_EMA (the averaged
+ * parameters; NPM_ERR_STATE when ema_decay is 0).  count must equal
+ * n_params.  These calls synchronise the device.  Setting PARAMS also
+ * restarts the average at the new parameters; setting PARAMS or EMA
+ * refreshes the low-precision copies used by NPM_PREC_BF16.                */
+enum { NPM_STATE_PARAMS = 0, NPM_STATE_GRADS = 1, NPM_STATE_ADAM_M = 2, NPM_STATE_ADAM_V = 3,
+       NPM_STATE_EMA = 4 };
 npm_status npm_get_state(npm_ctx *ctx, int which, float *host, int64_t count);
 npm_status npm_set_state(npm_ctx *ctx, int which, const float *host, int64_t count);
 /* Adam step counter (number of optimizer steps taken).                     */

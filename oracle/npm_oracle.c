@@ -744,3 +744,13 @@ void npmo_adam(int64_t np, double *params, const double *grad, double *m, double
         params[i] -= lr * mh / (sqrt(vh) + eps);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Exponential moving average of the weights (Sec. 5.3: inference uses an    */
+/* EMA of the weights of previous training steps).  Called after each        */
+/* optimizer step with that step's parameters: ema <- d ema + (1 - d) p.     */
+/* ------------------------------------------------------------------------ */
+void npmo_ema(int64_t np, double *ema, const double *params, double decay)
+{
+    for (int64_t i = 0; i < np; ++i) ema[i] = decay * ema[i] + (1.0 - decay) * params[i];
+}

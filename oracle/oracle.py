@@ -66,6 +66,7 @@ def lib():
         L.npmo_backward_cond.argtypes = [P, i64, i64, P, P, P, P, P, P]
         L.npmo_adam.argtypes = [i64, P, P, P, P, i64, C.c_double, C.c_double, C.c_double,
                                 C.c_double]
+        L.npmo_ema.argtypes = [i64, P, P, C.c_double]
         _lib = L
     return _lib
 
@@ -258,3 +259,11 @@ def adam(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     for a in (params, grad, m, v):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().npmo_adam(params.size, _p(params), _p(grad), _p(m), _p(v), t, lr, beta1, beta2, eps)
+
+
+def ema(avg, params, decay):
+    """In-place moving average of float64 arrays, after an optimizer step:
+    avg <- decay * avg + (1 - decay) * params."""
+    for a in (avg, params):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().npmo_ema(avg.size, _p(avg), _p(params), decay)

@@ -185,15 +185,22 @@ static PackDesc pack_desc(const Net &net)
     return d;
 }
 
+static void pack_images(const PackDesc &d, const float *src, float *img, void *img16,
+                        hipStream_t s)
+{
+    const int blocks = (int)std::min<int64_t>((d.total + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_pack<false>, dim3(blocks), dim3(256), 0, s, d, src, img,
+                       (__bf16 *)nullptr);
+    if (img16)
+        hipLaunchKernelGGL(k_pack<true>, dim3(blocks), dim3(256), 0, s, d, src, (float *)nullptr,
+                           (__bf16 *)img16);
+}
+
 hipError_t launch_pack_mlp(npm_ctx *ctx, hipStream_t s)
 {
     const PackDesc d = pack_desc(ctx->net);
-    const int blocks = (int)std::min<int64_t>((d.total + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_pack<false>, dim3(blocks), dim3(256), 0, s, d, ctx->params, ctx->mlp_img,
-                       (__bf16 *)nullptr);
-    if (ctx->mlp_img16)
-        hipLaunchKernelGGL(k_pack<true>, dim3(blocks), dim3(256), 0, s, d, ctx->params,
-                           (float *)nullptr, (__bf16 *)ctx->mlp_img16);
+    pack_images(d, ctx->params, ctx->mlp_img, ctx->mlp_img16, s);
+    if (ctx->ema) pack_images(d, ctx->ema, ctx->ema_img, ctx->ema_img16, s);
     return hipGetLastError();
 }
 
@@ -208,23 +215,29 @@ hipError_t launch_refresh_lowp(npm_ctx *ctx, hipStream_t s)
 {
     hipError_t e = launch_pack_mlp(ctx, s);
     if (e != hipSuccess) return e;
-    if (ctx->grid16) {
-        const int64_t n = ctx->net.lay.grid_params;
+    const int64_t n = ctx->net.lay.grid_params;
+    if (ctx->grid16)
         hipLaunchKernelGGL(k_grid_to_half, dim3(2048), dim3(256), 0, s, ctx->params,
                            (__half *)ctx->grid16, n);
-    }
+    if (ctx->ema_grid16)
+        hipLaunchKernelGGL(k_grid_to_half, dim3(2048), dim3(256), 0, s, ctx->ema,
+                           (__half *)ctx->ema_grid16, n);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- Adam
 // m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2; p <- p - lr m^/(sqrt(v^) + eps)
 // with m^ = m / (1 - b1^t), v^ = v / (1 - b2^t); g is zeroed; the FP16 copy of
-// the grid is written in the same pass; sum g^2 is reduced in FP64.
+// the grid is written in the same pass; sum g^2 is reduced in FP64.  With a
+// moving average kept (ema non-null), ema <- d ema + (1 - d) p after the step,
+// and its FP16 grid copy too.
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, float *__restrict__ g,
                                               float *__restrict__ m, float *__restrict__ v,
                                               int64_t np, float lr, float b1, float b2, float eps,
                                               float c1inv, float c2inv, __half *__restrict__ grid16,
-                                              int64_t grid_params, double *__restrict__ partials)
+                                              int64_t grid_params, double *__restrict__ partials,
+                                              float *__restrict__ ema, __half *__restrict__ ema16,
+                                              float decay)
 {
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np;
@@ -238,6 +251,11 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, float *__re
         p[i] = pi;
         g[i] = 0.0f;
         if (grid16 && i < grid_params) grid16[i] = __float2half_rn(pi);
+        if (ema) {
+            const float ei = decay * ema[i] + (1.0f - decay) * pi;
+            ema[i] = ei;
+            if (ema16 && i < grid_params) ema16[i] = __float2half_rn(ei);
+        }
         acc += (double)gi * (double)gi;
     }
     __shared__ double red[256];
@@ -262,7 +280,8 @@ hipError_t launch_adam(npm_ctx *ctx, float *grad, double *gradnorm_out, hipStrea
     timed_begin(ctx, "adam", s, &tok);
     hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, s, ctx->params, grad, ctx->adam_m,
                        ctx->adam_v, np, c.lr, c.beta1, c.beta2, c.eps, c1inv, c2inv,
-                       (__half *)ctx->grid16, ctx->net.lay.grid_params, ctx->partials);
+                       (__half *)ctx->grid16, ctx->net.lay.grid_params, ctx->partials, ctx->ema,
+                       (__half *)ctx->ema_grid16, c.ema_decay);
     timed_end(ctx, tok, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -265,6 +265,10 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *d
                        hipStream_t s)
 {
     FusedArgs a = fused_args(ctx, n, pos);
+    const Weights w = query_weights(ctx);
+    a.grid32 = w.grid32;
+    a.grid16 = (const __half *)w.grid16;
+    a.img = ctx->net.cfg.precision == NPM_PREC_BF16 ? w.img16 : (const void *)w.img;
     a.dir = dir;
     a.seed = seed;
     a.sid = stream_id;

@@ -279,8 +279,9 @@ hipError_t serve_launch_round(RoundBuffers *b, const std::vector<ServeRequest> &
         DevReq &d = hr[j];
         std::memset(&d, 0, sizeof(d));
         d.g = net.grid;
-        d.grid16 = (const __half *)ctx->grid16;
-        d.img = ctx->mlp_img16;
+        const Weights w = q.kind == 0 ? query_weights(ctx) : trained_weights(ctx);
+        d.grid16 = (const __half *)w.grid16;
+        d.img = w.img16;
         d.grad = ctx->grads;
         d.pos = q.pos; d.dir = q.dir; d.rad = q.rad; d.spdf = q.spdf;
         d.lobes = q.lobes; d.pdf = q.pdf; d.sdir = q.sdir; d.spdf_out = q.spdf_out;

@@ -77,16 +77,18 @@ __global__ __launch_bounds__(256) void k_encode(GridDesc g, int64_t n, const flo
     for (int f = 0; f < F; ++f) G[((int64_t)l * F + f) * n + v] = acc[f];
 }
 
-hipError_t staged_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, hipStream_t s)
+hipError_t staged_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, hipStream_t s,
+                         const Weights *w)
 {
     const GridDesc &g = ctx->net.grid;
+    const float *table = w ? w->grid32 : ctx->params;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)g.n_levels);
     int tok;
     timed_begin(ctx, "staged_encode", s, &tok);
     switch (g.feat) {
-    case 1: hipLaunchKernelGGL(k_encode<1>, grid, dim3(256), 0, s, g, n, pos, ctx->params, G); break;
-    case 2: hipLaunchKernelGGL(k_encode<2>, grid, dim3(256), 0, s, g, n, pos, ctx->params, G); break;
-    case 4: hipLaunchKernelGGL(k_encode<4>, grid, dim3(256), 0, s, g, n, pos, ctx->params, G); break;
+    case 1: hipLaunchKernelGGL(k_encode<1>, grid, dim3(256), 0, s, g, n, pos, table, G); break;
+    case 2: hipLaunchKernelGGL(k_encode<2>, grid, dim3(256), 0, s, g, n, pos, table, G); break;
+    case 4: hipLaunchKernelGGL(k_encode<4>, grid, dim3(256), 0, s, g, n, pos, table, G); break;
     default: return hipErrorInvalidValue;
     }
     timed_end(ctx, tok, s);
@@ -479,14 +481,14 @@ __global__ __launch_bounds__(256) void k_scatter(GridDesc g, int64_t n, const fl
 template <int IN_P, int HID_P, int NH>
 struct MlpFwd {
     static void run(npm_ctx *ctx, int blocks, int64_t n, const float *G, float *acts, float *raw,
-                    hipStream_t s)
+                    hipStream_t s, const float *img)
     {
         const MlpDesc &m = ctx->net.mlp;
         const int elems = (int)m.fwd_elems;
         hipFuncSetAttribute((const void *)k_mlp_fwd<IN_P, HID_P, NH>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, elems * sizeof(float));
         hipLaunchKernelGGL((k_mlp_fwd<IN_P, HID_P, NH>), dim3(blocks), dim3(256),
-                           elems * sizeof(float), s, n, m.n_in, m.width, ctx->mlp_img, elems, G,
+                           elems * sizeof(float), s, n, m.n_in, m.width, img, elems, G,
                            acts, raw);
     }
 };
@@ -514,12 +516,13 @@ static int tile_blocks(int64_t n)
 }
 
 hipError_t staged_mlp_fwd(npm_ctx *ctx, int64_t n, const float *G, float *acts, float *raw,
-                          hipStream_t s)
+                          hipStream_t s, const Weights *w)
 {
     const int blocks = tile_blocks(n);
+    const float *img = w ? w->img : ctx->mlp_img;
     int tok;
     timed_begin(ctx, acts ? "staged_mlp_fwd_train" : "staged_mlp_fwd", s, &tok);
-    NPM_MLP_DISPATCH(MlpFwd, ::run(ctx, blocks, n, G, acts, raw, s));
+    NPM_MLP_DISPATCH(MlpFwd, ::run(ctx, blocks, n, G, acts, raw, s, img));
     timed_end(ctx, tok, s);
     return hipGetLastError();
 }

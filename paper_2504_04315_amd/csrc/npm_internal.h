@@ -73,6 +73,10 @@ struct npm_ctx {
     // Packed MLP weight images (forward and backward), FP32 and BF16
     float *mlp_img = nullptr;          // [fwd_elems + bwd_elems] FP32
     void *mlp_img16 = nullptr;         // [fwd_elems + bwd_elems] BF16
+    // Exponential moving average of the parameters (ema_decay > 0): FP32
+    // master, its packed images and (NPM_PREC_BF16) its FP16 grid
+    float *ema = nullptr, *ema_img = nullptr;
+    void *ema_img16 = nullptr, *ema_grid16 = nullptr;
     // FP64 reduction scratch
     double *partials = nullptr;        // kPartials doubles
     double *stats = nullptr;           // 4 doubles: loss, gradnorm, spare
@@ -96,6 +100,23 @@ namespace npm {
 
 constexpr int kPartials = 4096;        // FP64 partial slots per reduction
 
+// The weights a kernel reads: the trained ones, or, for the network npm_query
+// evaluates, their moving average when it is kept.
+struct Weights {
+    const float *grid32;      // FP32 grid (the head of the flat parameters)
+    const void *grid16;       // FP16 grid (precision form) or null
+    const float *img;         // packed FP32 images
+    const void *img16;        // packed BF16 images
+};
+inline Weights trained_weights(const npm_ctx *c)
+{
+    return Weights{c->params, c->grid16, c->mlp_img, c->mlp_img16};
+}
+inline Weights query_weights(const npm_ctx *c)
+{
+    return c->ema ? Weights{c->ema, c->ema_grid16, c->ema_img, c->ema_img16} : trained_weights(c);
+}
+
 // ---------------------------------------------------------------- launchers
 // All return hipSuccess or the first launch error.  `s` is the stream.
 struct Launch {
@@ -109,7 +130,9 @@ void timed_end(npm_ctx *ctx, int token, hipStream_t s);
 
 // common kernels (k_common.hip)
 hipError_t launch_init_params(npm_ctx *ctx, hipStream_t s);
+// packs the MLP images of the parameters (and of their average when kept)
 hipError_t launch_pack_mlp(npm_ctx *ctx, hipStream_t s);
+// repacks the images and rewrites the FP16 grids from the FP32 masters
 hipError_t launch_refresh_lowp(npm_ctx *ctx, hipStream_t s);
 hipError_t launch_adam(npm_ctx *ctx, float *grad, double *gradnorm_out, hipStream_t s);
 hipError_t launch_reduce_partials(npm_ctx *ctx, int nparts, double *out, hipStream_t s);
@@ -120,9 +143,11 @@ hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 // staged path (k_staged.hip)
 hipError_t staged_corner_index(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *idx,
                                hipStream_t s);
-hipError_t staged_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, hipStream_t s);
+// w: the weights to evaluate (the trained ones by default)
+hipError_t staged_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, hipStream_t s,
+                         const Weights *w = nullptr);
 hipError_t staged_mlp_fwd(npm_ctx *ctx, int64_t n, const float *G, float *acts, float *raw,
-                          hipStream_t s);
+                          hipStream_t s, const Weights *w = nullptr);
 hipError_t staged_head(npm_ctx *ctx, int64_t n, const float *raw, const float *dir,
                        uint64_t seed, uint32_t stream_id, float *lobes, float *pdf,
                        float *sdir, float *spdf, hipStream_t s);

@@ -74,6 +74,7 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     if (!(c.beta1 >= 0.0f && c.beta1 < 1.0f && c.beta2 >= 0.0f && c.beta2 < 1.0f))
         return bad("betas must be in [0, 1)");
     if (!(std::isfinite(c.eps) && c.eps > 0.0f)) return bad("eps must be > 0");
+    if (!(c.ema_decay >= 0.0f && c.ema_decay < 1.0f)) return bad("ema_decay must be in [0, 1)");
 
     Net n{};
     n.cfg = c;
@@ -145,8 +146,9 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     }
     m.bwd_elems = bo;
     const int64_t img = m.fwd_elems + m.bwd_elems;
-    L.device_bytes = 16 * L.n_params + 6 * img + (int64_t)kPartials * 8 + 64 +
-                     (c.precision == NPM_PREC_BF16 ? 2 * L.grid_params : 0);
+    const int64_t lowp_grid = c.precision == NPM_PREC_BF16 ? 2 * L.grid_params : 0;
+    L.device_bytes = 16 * L.n_params + 6 * img + (int64_t)kPartials * 8 + 64 + lowp_grid +
+                     (c.ema_decay > 0.0f ? 4 * L.n_params + 6 * img + lowp_grid : 0);
     *net = n;
     return NPM_OK;
 }
@@ -209,7 +211,8 @@ static void free_ctx(npm_ctx *ctx)
     for (void *p : {(void *)ctx->params, (void *)ctx->grads, (void *)ctx->adam_m,
                     (void *)ctx->adam_v, ctx->grid16, (void *)ctx->mlp_img, ctx->mlp_img16,
                     (void *)ctx->partials, (void *)ctx->stats, (void *)ctx->s_dw_part,
-                    (void *)ctx->s_perm, (void *)ctx->s_cells, (void *)ctx->s_dgt})
+                    (void *)ctx->s_perm, (void *)ctx->s_cells, (void *)ctx->s_dgt,
+                    (void *)ctx->ema, (void *)ctx->ema_img, ctx->ema_img16, ctx->ema_grid16})
         if (p) hipFree(p);
     for (auto &p : ctx->timing.pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : ctx->timing.free_events) hipEventDestroy(e);
@@ -260,10 +263,18 @@ npm_status npm_create(const npm_config *cfg, npm_ctx **out)
     const int64_t mlp_w = np - net.lay.grid_params;
     alloc((void **)&ctx->s_dw_part, std::max<int64_t>(256 * max_layer, 1024 * mlp_w) * 4);
     if (net.cfg.precision == NPM_PREC_BF16) alloc(&ctx->grid16, net.lay.grid_params * 2);
+    if (net.cfg.ema_decay > 0.0f) {
+        alloc((void **)&ctx->ema, np * 4);
+        alloc((void **)&ctx->ema_img, img * 4);
+        alloc(&ctx->ema_img16, img * 2);
+        if (net.cfg.precision == NPM_PREC_BF16) alloc(&ctx->ema_grid16, net.lay.grid_params * 2);
+    }
     if (e == hipSuccess) e = hipMemset(ctx->grads, 0, np * 4);
     if (e == hipSuccess) e = hipMemset(ctx->adam_m, 0, np * 4);
     if (e == hipSuccess) e = hipMemset(ctx->adam_v, 0, np * 4);
     if (e == hipSuccess) e = launch_init_params(ctx, nullptr);
+    if (e == hipSuccess && ctx->ema)
+        e = hipMemcpy(ctx->ema, ctx->params, np * 4, hipMemcpyDeviceToDevice);
     if (e == hipSuccess) e = launch_refresh_lowp(ctx, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -332,8 +343,9 @@ npm_status npm_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir
             return NPM_OK;
         }
         NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
-        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");
-        NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s), "mlp forward");
+        const Weights w = query_weights(ctx);
+        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w), "encode");
+        NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s, &w), "mlp forward");
         if (lobes || pdf || sample_dir || sample_pdf)
             NPM_HIP(staged_head(ctx, n, ctx->s_raw, dir, rng_seed, rng_stream, lobes, pdf,
                                 sample_dir, sample_pdf, s), "head");
@@ -508,7 +520,8 @@ npm_status npm_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, void 
     if (st != NPM_OK) return st;
     if (n > 0 && (!G || !aligned4(G))) return fail(NPM_ERR_INVALID_ARG, "G required");
     if (n == 0) return NPM_OK;
-    NPM_HIP(staged_encode(ctx, n, pos, G, (hipStream_t)stream), "encode");
+    const Weights w = query_weights(ctx);
+    NPM_HIP(staged_encode(ctx, n, pos, G, (hipStream_t)stream, &w), "encode");
     return NPM_OK;
 }
 
@@ -520,8 +533,9 @@ npm_status npm_forward_raw(npm_ctx *ctx, int64_t n, const float *pos, float *raw
     if (n == 0) return NPM_OK;
     hipStream_t s = (hipStream_t)stream;
     NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
-    NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");
-    NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, raw, s), "mlp forward");
+    const Weights w = query_weights(ctx);
+    NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w), "encode");
+    NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, raw, s, &w), "mlp forward");
     return NPM_OK;
 }
 
@@ -532,6 +546,7 @@ static float *state_buf(npm_ctx *ctx, int which)
     case NPM_STATE_GRADS: return ctx->grads;
     case NPM_STATE_ADAM_M: return ctx->adam_m;
     case NPM_STATE_ADAM_V: return ctx->adam_v;
+    case NPM_STATE_EMA: return ctx->ema;
     default: return nullptr;
     }
 }
@@ -540,6 +555,7 @@ npm_status npm_get_state(npm_ctx *ctx, int which, float *host, int64_t count)
 {
     if (!ctx || !host) return fail(NPM_ERR_INVALID_ARG, "null argument");
     float *src = state_buf(ctx, which);
+    if (which == NPM_STATE_EMA && !src) return fail(NPM_ERR_STATE, "no moving average is kept");
     if (!src) return fail(NPM_ERR_INVALID_ARG, "unknown state buffer");
     if (count != ctx->net.lay.n_params) return fail(NPM_ERR_INVALID_ARG, "count must equal n_params");
     NPM_HIP(hipDeviceSynchronize(), "synchronize");
@@ -551,11 +567,14 @@ npm_status npm_set_state(npm_ctx *ctx, int which, const float *host, int64_t cou
 {
     if (!ctx || !host) return fail(NPM_ERR_INVALID_ARG, "null argument");
     float *dst = state_buf(ctx, which);
+    if (which == NPM_STATE_EMA && !dst) return fail(NPM_ERR_STATE, "no moving average is kept");
     if (!dst) return fail(NPM_ERR_INVALID_ARG, "unknown state buffer");
     if (count != ctx->net.lay.n_params) return fail(NPM_ERR_INVALID_ARG, "count must equal n_params");
     NPM_HIP(hipDeviceSynchronize(), "synchronize");
     NPM_HIP(hipMemcpy(dst, host, count * 4, hipMemcpyHostToDevice), "copy state");
-    if (which == NPM_STATE_PARAMS) {
+    if (which == NPM_STATE_PARAMS && ctx->ema)      // the average restarts here
+        NPM_HIP(hipMemcpy(ctx->ema, ctx->params, count * 4, hipMemcpyDeviceToDevice), "copy state");
+    if (which == NPM_STATE_PARAMS || which == NPM_STATE_EMA) {
         NPM_HIP(launch_refresh_lowp(ctx, nullptr), "refresh packed weights");
         NPM_HIP(hipDeviceSynchronize(), "synchronize");
     }
@@ -580,6 +599,7 @@ npm_status npm_state_device_ptr(npm_ctx *ctx, int which, void **ptr)
 {
     if (!ctx || !ptr) return fail(NPM_ERR_INVALID_ARG, "null argument");
     float *p = state_buf(ctx, which);
+    if (which == NPM_STATE_EMA && !p) return fail(NPM_ERR_STATE, "no moving average is kept");
     if (!p) return fail(NPM_ERR_INVALID_ARG, "unknown state buffer");
     *ptr = p;
     return NPM_OK;

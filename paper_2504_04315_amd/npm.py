@@ -21,7 +21,7 @@ PREC_FP32, PREC_BF16 = 0, 1
 EXEC_STAGED, EXEC_FUSED = 0, 1
 ORDER_AUTO, ORDER_NONE, ORDER_SPATIAL = 0, 1, 2
 INIT_NORMAL, INIT_UNIFORM = 0, 1
-STATE_PARAMS, STATE_GRADS, STATE_ADAM_M, STATE_ADAM_V = 0, 1, 2, 3
+STATE_PARAMS, STATE_GRADS, STATE_ADAM_M, STATE_ADAM_V, STATE_EMA = 0, 1, 2, 3, 4
 MAX_LEVELS, MAX_LAYERS = 32, 5
 
 
@@ -33,7 +33,7 @@ class npm_config(C.Structure):
         ("mlp_hidden_layers", C.c_int32), ("n_lobes", C.c_int32), ("precision", C.c_int32),
         ("exec_mode", C.c_int32), ("grid_init", C.c_int32), ("grid_init_scale", C.c_float),
         ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-        ("batch_order", C.c_int32), ("seed", C.c_uint64),
+        ("batch_order", C.c_int32), ("ema_decay", C.c_float), ("seed", C.c_uint64),
     ]
 
 
@@ -113,7 +113,7 @@ def check(status):
 
 
 def make_config(net, exec_mode=EXEC_STAGED, precision=None, lr=None, seed=None,
-                batch_order=ORDER_AUTO):
+                batch_order=ORDER_AUTO, ema_decay=0.0):
     """npm_config from a workload.NetConfig (sizes of a workload)."""
     c = npm_config()
     check(lib().npm_config_default(C.byref(c)))
@@ -131,6 +131,7 @@ def make_config(net, exec_mode=EXEC_STAGED, precision=None, lr=None, seed=None,
     c.beta1, c.beta2, c.eps = net.beta1, net.beta2, net.eps
     c.seed = net.seed if seed is None else seed
     c.batch_order = batch_order
+    c.ema_decay = ema_decay
     return c
 
 

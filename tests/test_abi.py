@@ -64,7 +64,8 @@ def test_invalid_configs_rejected_without_device():
     for field, value in [("n_levels", 0), ("n_levels", 33), ("feat_per_level", 3),
                          ("n_lobes", 4), ("mlp_width", 65), ("mlp_hidden_layers", 0),
                          ("log2_table_size", 40), ("precision", 7), ("lr", -1.0),
-                         ("beta1", 1.0), ("max_resolution", 8)]:
+                         ("beta1", 1.0), ("max_resolution", 8), ("batch_order", 3),
+                         ("ema_decay", 1.0), ("ema_decay", -0.5)]:
         c = B.npm_config.from_buffer_copy(base)
         setattr(c, field, value)
         assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1, field
@@ -75,6 +76,19 @@ def test_invalid_configs_rejected_without_device():
     c.precision = B.PREC_BF16
     c.exec_mode = B.EXEC_STAGED
     assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+
+
+def test_moving_average_adds_its_buffers_to_the_layout():
+    """A kept moving average (Sec. 5.3's inference weights) costs an FP32
+    copy of the parameters, its packed images and, in the precision form,
+    its FP16 grid."""
+    for net in (W.CFG2, W.CFG3):
+        off, on = (B.layout_of(B.make_config(net, exec_mode=B.EXEC_FUSED, ema_decay=d))
+                   for d in (0.0, 0.99))
+        extra = on.device_bytes - off.device_bytes
+        lowp = 2 * off.grid_params if net.precision == "bf16" else 0
+        assert extra > 4 * off.n_params + lowp
+        assert extra < 4 * off.n_params + lowp + 6 * 64 * 1024
 
 
 def test_null_context_calls_fail_cleanly():

@@ -180,3 +180,24 @@ def test_condition_scale_dominates_contributions(O):
     cond = O.backward_cond(net, pos, dirs, rad, pdf, params)
     assert np.all(cond >= out["gabs"] * (1 - 1e-12))
     assert np.all((cond > 0) == (out["gabs"] > 0))
+
+
+def test_ema_closed_forms(O):
+    """Moving average of the weights (Sec. 5.3): with the parameters held at p
+    after every step, ema_t = p + d^t (ema_0 - p); d = 0 follows the
+    parameters; a ramp p_t = t gives the weighted sum in closed form."""
+    rng = np.random.default_rng(4)
+    e0, p = rng.normal(size=64), rng.normal(size=64)
+    e = e0.copy()
+    for t in range(1, 11):
+        O.ema(e, p, 0.9)
+        np.testing.assert_allclose(e, p + 0.9 ** t * (e0 - p), rtol=1e-13, atol=1e-14)
+    e = e0.copy()
+    O.ema(e, p, 0.0)
+    assert np.array_equal(e, p)
+    d, T = 0.75, 12
+    e = np.zeros(3)
+    for t in range(1, T + 1):
+        O.ema(e, np.full(3, float(t)), d)
+    ref = sum((1 - d) * d ** (T - t) * t for t in range(1, T + 1))
+    np.testing.assert_allclose(e, ref, rtol=1e-13)
