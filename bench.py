@@ -45,10 +45,13 @@ WORK = {
     # fused: streams + gathers + atomics only, intermediates stay on chip
     # except the tile kernel's dG (32 FP32 per vertex), which the aggregated
     # scatter reads back; the visiting order adds 4 B per vertex to each
-    "fused_query": dict(bytes=24 + GATHER_B + 148, flops=MLP_F),
+    "fused_query": dict(bytes=24 + 4 + GATHER_B + 160, flops=MLP_F),
+    # ordered query: 160-byte staged slot read, inverse order, outputs written
+    "query_unstage": dict(bytes=160 + 4 + 148, flops=0),
     "fused_backward": dict(bytes=32 + 4 + GATHER_B + 32 * 4, flops=3 * MLP_F),
     "fused_scatter": dict(bytes=12 + 4 + 32 * 4 + ATOMIC_B, flops=0),
-    # counting sort: positions read twice, two counter atomics, perm written
+    # counting sort: positions read twice, two counter atomics, perm (and
+    # for queries its inverse) written
     "spatial_sort": dict(bytes=2 * 12 + 2 * 8 + 4, flops=0),
     # staged: each kernel's own streams (feature-major intermediates)
     "staged_encode": dict(bytes=12 + GATHER_B + 32 * 4, flops=0),
@@ -118,6 +121,10 @@ def cpu_baseline(netcfg, batch, params, seconds):
     mq = int(min(batch.n, max(8192, 0.2 * seconds / q0)))
     mb = int(min(batch.n, max(4096, 0.8 * seconds / b0)))
     tq, tb = t_query(mq), t_backward(mb)
+    old = O.set_threads(1)
+    m1 = max(4096, min(mq, int(0.1 * seconds / (q0 * threads))))
+    tq1 = t_query(m1)
+    O.set_threads(old)
     p = params.copy()
     g = np.zeros_like(p)
     m = np.zeros_like(p)
@@ -131,17 +138,18 @@ def cpu_baseline(netcfg, batch, params, seconds):
                       f"backward on {mb} vertices (serial, {tb:.2f} s), Adam over all "
                       f"{p.size} parameters ({ta:.2f} s), of the same 2^20-vertex batch; "
                       f"per-vertex times summed and inverted",
-            "query_vertices_per_s": mq / tq, "train_vertices_per_s": 1.0 / (tb / mb + ta / batch.n)}
+            "query_vertices_per_s": mq / tq, "train_vertices_per_s": 1.0 / (tb / mb + ta / batch.n),
+            "query_vertices_per_s_1_thread": m1 / tq1}
 
 
-def serving_bench(n_sessions=32, per_session=6, load=0.7):
+def serving_bench(n_sessions=32, per_session=6, load=0.7, sweep=(0.3, 0.9)):
     """The serving form on its workload: n_sessions guiding sessions (16-level
     FP16 hash grid, T = 2^17, MLP 32-64-64-64-32), each a Poisson stream of
     query batches with sizes log-uniform in 2^10..2^18 and a training batch
     after every 4 queries.  First the saturation throughput (everything
-    submitted at once), then the same plan offered at `load` times it; both
-    for the shared persistent kernels (BF16) and the per-session plain FP32
-    path."""
+    submitted at once), then the same plan offered at `load` times it (the
+    reported latency) and at the `sweep` loads; both for the shared
+    persistent kernels (BF16) and the per-session plain FP32 path."""
     from paper_2504_04315_amd import npm as B
     from paper_2504_04315_amd import serve as S
     from paper_2504_04315_amd import workload as W
@@ -160,16 +168,24 @@ def serving_bench(n_sessions=32, per_session=6, load=0.7):
             r["t"] = 0.0
         S.run_load(srv, sids, plan[:n_sessions])
         sat = S.run_load(srv, sids, plan)
-        rate = load * sat["vertices_per_s"] / (n_sessions * mean_n * 1.25)
-        plan2 = S.plan_requests(n_sessions, per_session, rate_hz=rate, train_every=4, seed=2)
-        S.make_request_buffers(plan2)
-        res = S.run_load(srv, sids, plan2)
+        def offered(f, seed):
+            rate = f * sat["vertices_per_s"] / (n_sessions * mean_n * 1.25)
+            plan2 = S.plan_requests(n_sessions, per_session, rate_hz=rate, train_every=4,
+                                    seed=seed)
+            S.make_request_buffers(plan2)
+            return S.run_load(srv, sids, plan2)
+        res = offered(load, 2)
         out[name] = {"saturation_vertices_per_s": sat["vertices_per_s"],
                      "saturation_latency_ms": sat["latency_ms"],
                      "offered_vertices_per_s": load * sat["vertices_per_s"],
                      "vertices_per_s": res["vertices_per_s"], "latency_ms": res["latency_ms"],
                      "query_latency_ms": res["query_latency_ms"],
-                     "train_latency_ms": res["train_latency_ms"], "rounds": res["rounds"]}
+                     "train_latency_ms": res["train_latency_ms"], "rounds": res["rounds"],
+                     "sweep": {}}
+        for k, f in enumerate(sweep):
+            r = offered(f, 3 + k)
+            out[name]["sweep"][str(f)] = {"vertices_per_s": r["vertices_per_s"],
+                                          "latency_ms": r["latency_ms"]}
         srv.close()
     return out
 

@@ -66,13 +66,14 @@ enum { NPM_PREC_FP32 = 0, NPM_PREC_BF16 = 1 };
  * grid lookup to the sampled direction (and, in training, to the scatter).  */
 enum { NPM_EXEC_STAGED = 0, NPM_EXEC_FUSED = 1 };
 enum { NPM_INIT_NORMAL = 0, NPM_INIT_UNIFORM = 1 };
-/* Order in which the fused backward visits a training batch.
+/* Order in which the fused path visits a batch.
  * NPM_ORDER_SPATIAL sorts the batch by the Morton code of each vertex's 64^3
  * cell (a counting sort on the device, kept in context scratch) so that a
  * wave's consecutive tiles touch nearby grid entries; NPM_ORDER_NONE keeps
- * the caller's order; NPM_ORDER_AUTO picks the faster of the two for the
- * batch size.  The order changes only the order of the floating-point
- * gradient sums.                                                            */
+ * the caller's order; NPM_ORDER_AUTO sorts batches of 2^15 vertices or more.
+ * A query's outputs do not depend on the order (each vertex keeps its own
+ * uniforms; the outputs are staged and un-permuted); a gradient changes only
+ * in the order of its floating-point sums.                                  */
 enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
 
 /* Network configuration (copied at create).
@@ -92,7 +93,7 @@ enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
  *   (NPM_INIT_UNIFORM); MLP Xavier-uniform; all from `seed`.
  * Adam (Sec. 5.3): lr, beta1, beta2, eps, bias-corrected, eps outside the
  *   square root.
- * batch_order: one of NPM_ORDER_* (fused training only).
+ * batch_order: one of NPM_ORDER_* (fused path: training and queries).
  * ema_decay: 0 (off) or d in (0, 1).  When on, every optimizer step also
  *   updates an exponential moving average of the parameters,
  *   ema <- d * ema + (1 - d) * p (after the step, initialised to the

@@ -63,6 +63,7 @@
  * published known-answer vectors).  The resolution-growth rule and the hash
  * are readings, not results; they are pinned only by their properties.
  */
+#include <omp.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -753,4 +754,13 @@ void npmo_adam(int64_t np, double *params, const double *grad, double *m, double
 void npmo_ema(int64_t np, double *ema, const double *params, double decay)
 {
     for (int64_t i = 0; i < np; ++i) ema[i] = decay * ema[i] + (1.0 - decay) * params[i];
+}
+
+/* Thread count of the OpenMP loops (timing of the oracle on one core);
+ * returns the previous maximum.                                            */
+int npmo_set_threads(int n)
+{
+    int old = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return old;
 }

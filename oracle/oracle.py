@@ -67,6 +67,8 @@ def lib():
         L.npmo_adam.argtypes = [i64, P, P, P, P, i64, C.c_double, C.c_double, C.c_double,
                                 C.c_double]
         L.npmo_ema.argtypes = [i64, P, P, C.c_double]
+        L.npmo_set_threads.argtypes = [C.c_int]
+        L.npmo_set_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -267,3 +269,8 @@ def ema(avg, params, decay):
     for a in (avg, params):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().npmo_ema(avg.size, _p(avg), _p(params), decay)
+
+
+def set_threads(n):
+    """Sets the oracle's OpenMP thread count; returns the previous maximum."""
+    return lib().npmo_set_threads(n)

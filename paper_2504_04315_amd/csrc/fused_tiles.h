@@ -169,10 +169,26 @@ __device__ __forceinline__ float logpdf_half(const Lobe *L, float wx, float wy, 
 struct QueryIO {
     int64_t n;
     const float *pos, *dir;
-    float *lobes, *pdf, *sdir, *spdf;
+    float *lobes, *pdf, *sdir, *spdf;   // requested outputs (null: skipped)
     uint64_t seed;
     uint32_t sid;
+    const uint32_t *perm = nullptr;     // visiting order, or null: 0..n-1
+    float *stage = nullptr;             // with perm: kStageFloats per slot, AoS
+    const float *rec = nullptr;         // with perm: the inputs in visiting order
 };
+
+// A vertex's inputs in visiting order (written by the spatial sort, 32 bytes
+// per slot so that a wave reads its tile coalesced): position, direction,
+// radiance, sampling pdf (zeros where the call has none).
+constexpr int kRecFloats = 8;
+
+// Staged query outputs of one visiting slot (AoS, 160 bytes), laid out so
+// that each half-wave writes whole 16-byte pieces: floats [20 h, 20 h + 16)
+// hold the lobes k = 2 r + h of half h (component q of that lobe at
+// 20 h + 4 r + q); then pdf at 16, the sample direction at 17..19 and the
+// sample pdf at 36.
+constexpr int kStageFloats = 40;
+constexpr int kStagePdf = 16, kStageSdir = 17, kStageSpdf = 36;
 
 // One 32-vertex tile t of a query: encode, MLP, mappings, pdf at dir, one
 // sample per vertex and its pdf.  img: the forward weight image in LDS.
@@ -182,10 +198,20 @@ __device__ __forceinline__ void query_tile(const GridView &gv, const void *img, 
 {
     const int h = lane >> 5;
     const int64_t n = io.n;
-    const int64_t v = t * 32 + (lane & 31);
+    const int64_t v = t * 32 + (lane & 31);   // visiting slot
     const bool valid = v < n;
-    const int64_t vv = valid ? v : n - 1;
-    const float px = io.pos[vv], py = io.pos[n + vv], pz = io.pos[2 * n + vv];
+    // the vertex: its inputs, its uniforms and (unstaged) its outputs
+    const int64_t vv = io.perm ? (int64_t)io.perm[valid ? v : n - 1] : (valid ? v : n - 1);
+    float *st = io.stage ? io.stage + (size_t)(valid ? v : n - 1) * kStageFloats : nullptr;
+    float px, py, pz, wx = 0.0f, wy = 0.0f, wz = 0.0f;
+    if (io.rec) {
+        const f32x4 *r = reinterpret_cast<const f32x4 *>(io.rec + (size_t)(valid ? v : n - 1) * kRecFloats);
+        const f32x4 a = r[0], b = r[1];
+        px = a[0]; py = a[1]; pz = a[2]; wx = a[3]; wy = b[0]; wz = b[1];
+    } else {
+        px = io.pos[vv]; py = io.pos[n + vv]; pz = io.pos[2 * n + vv];
+        if (io.pdf) { wx = io.dir[vv]; wy = io.dir[n + vv]; wz = io.dir[2 * n + vv]; }
+    }
     float x[IN_P / 2];
     encode_tile<IN_P, F, BF>(gv, h, px, py, pz, x);
     float o[16];
@@ -196,17 +222,21 @@ __device__ __forceinline__ void query_tile(const GridView &gv, const void *img, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int k = 2 * r + h;
-            io.lobes[(int64_t)(0 * kLobes + k) * n + v] = L[r].theta;
-            io.lobes[(int64_t)(1 * kLobes + k) * n + v] = L[r].phi;
-            io.lobes[(int64_t)(2 * kLobes + k) * n + v] = L[r].kappa;
-            io.lobes[(int64_t)(3 * kLobes + k) * n + v] = expf(L[r].loglam);
+            const f32x4 c = {L[r].theta, L[r].phi, L[r].kappa, expf(L[r].loglam)};
+            if (st) {
+                *reinterpret_cast<f32x4 *>(st + 20 * h + 4 * r) = c;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) io.lobes[(int64_t)(q * kLobes + k) * n + vv] = c[q];
+            }
         }
     }
+    float pdf_v = 0.0f;
     if (io.pdf) {
-        const float wx = io.dir[vv], wy = io.dir[n + vv], wz = io.dir[2 * n + vv];
         float lt[4];
         const float lv = logpdf_half(L, wx, wy, wz, lt);
-        if (valid && h == 0) io.pdf[v] = expf(lv);
+        pdf_v = expf(lv);
+        if (valid && h == 0 && !st) io.pdf[vv] = pdf_v;
     }
     if (io.sdir || io.spdf) {
         float u[3];
@@ -242,9 +272,16 @@ __device__ __forceinline__ void query_tile(const GridView &gv, const void *img, 
         float lt[4];
         const float lv = logpdf_half(L, w[0], w[1], w[2], lt);
         if (valid && h == 0) {
-            if (io.sdir) { io.sdir[v] = w[0]; io.sdir[n + v] = w[1]; io.sdir[2 * n + v] = w[2]; }
-            if (io.spdf) io.spdf[v] = expf(lv);
+            if (st) {
+                *reinterpret_cast<f32x4 *>(st + kStagePdf) = f32x4{pdf_v, w[0], w[1], w[2]};
+                st[kStageSpdf] = expf(lv);
+            } else {
+                if (io.sdir) { io.sdir[vv] = w[0]; io.sdir[n + vv] = w[1]; io.sdir[2 * n + vv] = w[2]; }
+                if (io.spdf) io.spdf[vv] = expf(lv);
+            }
         }
+    } else if (st && valid && h == 0 && io.pdf) {
+        st[kStagePdf] = pdf_v;
     }
 }
 
@@ -412,6 +449,7 @@ struct TrainIO {
     float *grad;      // flat gradient (grid part scattered here), or null: loss only
     float invN;
     const uint32_t *perm;   // visiting order of the vertices, or null: 0..n-1
+    const float *rec = nullptr;   // with perm: the inputs in visiting order (kRecFloats)
 };
 
 // The vertex at position v of the visiting order.
@@ -442,7 +480,8 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
                                              const float *__restrict__ pos, const uint32_t *perm,
                                              int64_t n, int64_t t, int lane,
                                              float *__restrict__ grad, const float *lo,
-                                             const float *hi, float *win)
+                                             const float *hi, float *win,
+                                             const float *rec = nullptr)
 {
     constexpr int LPV = 8 * F;              // lanes per vertex-level
     constexpr int VPI = 64 / LPV;           // vertex-levels per instruction
@@ -452,8 +491,13 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
 #pragma unroll
     for (int jj = 0; jj < 32 / VPI; ++jj) {
         const int64_t v = t * 32 + jj * VPI + q;
-        const int64_t vv = visit(perm, v < n ? v : n - 1);
-        px[jj] = pos[vv]; py[jj] = pos[n + vv]; pz[jj] = pos[2 * n + vv];
+        if (rec) {
+            const f32x4 a = *reinterpret_cast<const f32x4 *>(rec + (size_t)(v < n ? v : n - 1) * kRecFloats);
+            px[jj] = a[0]; py[jj] = a[1]; pz[jj] = a[2];
+        } else {
+            const int64_t vv = visit(perm, v < n ? v : n - 1);
+            px[jj] = pos[vv]; py[jj] = pos[n + vv]; pz[jj] = pos[2 * n + vv];
+        }
     }
     for (int l = 0; l < gv.n_levels; ++l) {
         const int D = gv.res[l];
@@ -557,8 +601,17 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
     const int64_t n = io.n;
     const int64_t v = t * 32 + (lane & 31);
     const bool valid = v < n;
-    const int64_t vv = visit(io.perm, valid ? v : n - 1);
-    const float px = io.pos[vv], py = io.pos[n + vv], pz = io.pos[2 * n + vv];
+    float px, py, pz, wx, wy, wz, rad, spdf;
+    if (io.rec) {
+        const f32x4 *r = reinterpret_cast<const f32x4 *>(io.rec + (size_t)(valid ? v : n - 1) * kRecFloats);
+        const f32x4 a = r[0], b = r[1];
+        px = a[0]; py = a[1]; pz = a[2]; wx = a[3]; wy = b[0]; wz = b[1]; rad = b[2]; spdf = b[3];
+    } else {
+        const int64_t vv = visit(io.perm, valid ? v : n - 1);
+        px = io.pos[vv]; py = io.pos[n + vv]; pz = io.pos[2 * n + vv];
+        wx = io.dir[vv]; wy = io.dir[n + vv]; wz = io.dir[2 * n + vv];
+        rad = io.rad[vv]; spdf = io.spdf[vv];
+    }
     float x[IN0 / 2];
     encode_tile<IN_P, F, BF>(gv, h, px, py, pz, x);
 #pragma unroll
@@ -567,14 +620,13 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
     float o[16];
     mlp_forward<IN_P, HID_P, NH, BF, true>(fwd, x, acts, o, lane);
     // ---- KL-gradient head
-    const float wgt = valid ? sample_weight(io.rad[vv], io.spdf[vv]) : 0.0f;
+    const float wgt = valid ? sample_weight(rad, spdf) : 0.0f;
     float d[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) d[i] = 0.0f;
     {
         Lobe L[4];
         map_half(o, L);
-        const float wx = io.dir[vv], wy = io.dir[n + vv], wz = io.dir[2 * n + vv];
         float lt[4];
         const float lv = logpdf_half(L, wx, wy, wz, lt);
         if (wgt != 0.0f) {
@@ -623,7 +675,7 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
         t32_to_lds<OUT0 / 2>(tbuf, dG, lane);
         wave_lds_fence();
         scatter_tile<F, WIN_PTS>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad, lo, hi,
-                                 tbuf + OUT0 * kStride);
+                                 tbuf + OUT0 * kStride, io.rec);
     }
 }
 

@@ -39,6 +39,8 @@ struct FusedArgs {
     float invN;
     const uint32_t *perm;    // visiting order of the vertices (backward), or null
     float *dg_tiles;         // per-tile dG for the aggregated scatter (backward)
+    float *qstage;           // staged query outputs in visiting order (with perm)
+    const float *rec;        // inputs in visiting order (with perm), kRecFloats each
 };
 template <int IN_P, int HID_P, int NH, int F, bool BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_query_fused(FusedArgs a)
@@ -54,7 +56,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     }
     __syncthreads();
     const GridView gv = grid_view(a.g, s_off, s_res, a.grid32, a.grid16);
-    const QueryIO io{a.n, a.pos, a.dir, a.lobes, a.pdf, a.sdir, a.spdf_out, a.seed, a.sid};
+    const QueryIO io{a.n, a.pos, a.dir, a.lobes, a.pdf, a.sdir, a.spdf_out, a.seed, a.sid,
+                     a.perm, a.qstage, a.rec};
     const int lane = threadIdx.x & 63;
     const int64_t ntiles = (a.n + 31) / 32;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
@@ -77,7 +80,7 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     stage_levels(a.g, s_off, s_res);
     __syncthreads();
     const GridView gv = grid_view(a.g, s_off, s_res, a.grid32, a.grid16);
-    const TrainIO io{a.n, a.pos, a.dir, a.rad, a.spdf, a.grad, a.invN, a.perm};
+    const TrainIO io{a.n, a.pos, a.dir, a.rad, a.spdf, a.grad, a.invN, a.perm, a.rec};
     const char *fwd = smem;
     const char *bwd = smem + (size_t)a.fwd_elems * ESZ;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -136,6 +139,7 @@ template <int F>
 __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
                                                        const float *__restrict__ pos,
                                                        const uint32_t *perm,
+                                                       const float *__restrict__ rec,
                                                        const float *__restrict__ dgt, int rows,
                                                        float *__restrict__ grad)
 {
@@ -156,18 +160,53 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
     const int64_t t_end = (gwave + 1) * per < ntiles ? (gwave + 1) * per : ntiles;
     for (int64_t t = gwave * per; t < t_end; ++t) {
         const int64_t v = t * 32 + (lane & 31);
-        const int64_t vv = visit(perm, v < n ? v : n - 1);
         float lo[3], hi[3];
-        tile_bbox(pos[vv], pos[n + vv], pos[2 * n + vv], lo, hi);
+        if (rec) {
+            const f32x4 a = *reinterpret_cast<const f32x4 *>(rec + (size_t)(v < n ? v : n - 1) * kRecFloats);
+            tile_bbox(a[0], a[1], a[2], lo, hi);
+        } else {
+            const int64_t vv = visit(perm, v < n ? v : n - 1);
+            tile_bbox(pos[vv], pos[n + vv], pos[2 * n + vv], lo, hi);
+        }
         const float *src = dgt + (size_t)t * rows * 32;
         for (int i = lane; i < lr * 8; i += 64) {
             const f32x4 q = reinterpret_cast<const f32x4 *>(src)[i];
             *reinterpret_cast<f32x4 *>(tb + (i >> 3) * kStride + (i & 7) * 4) = q;
         }
         wave_lds_fence();
-        scatter_tile<F, WIN_PTS>(gv, tb, pos, perm, n, t, lane, grad, lo, hi, tb + 32 * kStride);
+        scatter_tile<F, WIN_PTS>(gv, tb, pos, perm, n, t, lane, grad, lo, hi, tb + 32 * kStride,
+                                 rec);
         wave_lds_fence();
     }
+}
+
+// Moves the staged outputs of a spatially ordered query to the caller's SoA
+// buffers: vertex i (coalesced writes) reads its 160-byte slot inv[i].
+__global__ __launch_bounds__(256) void k_query_unstage(int64_t n, const uint32_t *__restrict__ inv,
+                                                       const float *__restrict__ stage,
+                                                       float *__restrict__ lobes,
+                                                       float *__restrict__ pdf,
+                                                       float *__restrict__ sdir,
+                                                       float *__restrict__ spdf)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const f32x4 *src = reinterpret_cast<const f32x4 *>(stage + (size_t)inv[i] * kStageFloats);
+    f32x4 r[kStageFloats / 4];
+#pragma unroll
+    for (int q = 0; q < kStageFloats / 4; ++q) r[q] = src[q];
+    const float *c = reinterpret_cast<const float *>(r);
+    if (lobes)
+#pragma unroll
+        for (int k = 0; k < kLobes; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                lobes[(int64_t)(q * kLobes + k) * n + i] = c[20 * (k & 1) + 4 * (k >> 1) + q];
+    if (pdf) pdf[i] = c[kStagePdf];
+    if (sdir)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sdir[(int64_t)d * n + i] = c[kStageSdir + d];
+    if (spdf) spdf[i] = c[kStageSpdf];
 }
 
 // Sums the per-block partials of the MLP weight gradient into grad: a block
@@ -262,6 +301,7 @@ static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
 
 hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir, uint64_t seed,
                        uint32_t stream_id, float *lobes, float *pdf, float *sdir, float *spdf,
+                       const uint32_t *perm, const uint32_t *inv, const float *rec, float *stage,
                        hipStream_t s)
 {
     FusedArgs a = fused_args(ctx, n, pos);
@@ -276,21 +316,30 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *d
     a.pdf = pdf;
     a.sdir = sdir;
     a.spdf_out = spdf;
+    a.perm = perm;
+    a.qstage = perm ? stage : nullptr;
+    a.rec = perm ? rec : nullptr;
     hipError_t e = hipSuccess;
     int tok;
     timed_begin(ctx, "fused_query", s, &tok);
     if (ctx->net.cfg.precision == NPM_PREC_BF16) NPM_FUSED_DISPATCH(run_query, true);
     else NPM_FUSED_DISPATCH(run_query, false);
     timed_end(ctx, tok, s);
-    return e;
+    if (e != hipSuccess || !perm) return e;
+    timed_begin(ctx, "query_unstage", s, &tok);
+    hipLaunchKernelGGL(k_query_unstage, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, inv,
+                       stage, lobes, pdf, sdir, spdf);
+    timed_end(ctx, tok, s);
+    return hipGetLastError();
 }
 
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                           const float *rad, const float *spdf, float *grad, double *loss_out,
-                          const uint32_t *perm, float *dg_tiles, hipStream_t s)
+                          const uint32_t *perm, const float *rec, float *dg_tiles, hipStream_t s)
 {
     FusedArgs a = fused_args(ctx, n, pos);
     a.perm = perm;
+    a.rec = perm ? rec : nullptr;
     a.dir = dir;
     a.rad = rad;
     a.spdf = spdf;
@@ -313,11 +362,11 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
         timed_begin(ctx, "fused_scatter", s, &tok);
         switch (ctx->net.grid.feat) {
         case 1: hipLaunchKernelGGL(k_scatter_tiles<1>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                   ctx->net.grid, n, pos, perm, dg_tiles, rows, grad); break;
+                                   ctx->net.grid, n, pos, perm, rec, dg_tiles, rows, grad); break;
         case 2: hipLaunchKernelGGL(k_scatter_tiles<2>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                   ctx->net.grid, n, pos, perm, dg_tiles, rows, grad); break;
+                                   ctx->net.grid, n, pos, perm, rec, dg_tiles, rows, grad); break;
         default: hipLaunchKernelGGL(k_scatter_tiles<4>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                    ctx->net.grid, n, pos, perm, dg_tiles, rows, grad); break;
+                                    ctx->net.grid, n, pos, perm, rec, dg_tiles, rows, grad); break;
         }
         timed_end(ctx, tok, s);
         e = hipGetLastError();

@@ -90,16 +90,37 @@ __global__ __launch_bounds__(1024) void k_sort_scan_add(uint32_t *__restrict__ c
     cnt[blockIdx.x * 1024 + t] += part[0];
 }
 
-__global__ void k_sort_place(const float *__restrict__ pos, int64_t n, uint32_t *__restrict__ off,
-                             uint32_t *__restrict__ perm)
+// Places vertex v at its slot: perm[slot] = v, inv[v] = slot (optional), and
+// its inputs as one 32-byte record rec[slot] = (pos, dir, radiance, pdf), with
+// zeros for the arrays the call does not have.
+__global__ void k_sort_place(const float *__restrict__ pos, const float *__restrict__ dir,
+                             const float *__restrict__ rad, const float *__restrict__ spdf,
+                             int64_t n, uint32_t *__restrict__ off, uint32_t *__restrict__ perm,
+                             uint32_t *__restrict__ inv, float *__restrict__ rec)
 {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v < n) perm[atomicAdd(off + sort_cell(pos, n, v), 1u)] = (uint32_t)v;
+    if (v >= n) return;
+    const uint32_t slot = atomicAdd(off + sort_cell(pos, n, v), 1u);
+    perm[slot] = (uint32_t)v;
+    if (inv) inv[v] = slot;
+    if (rec) {
+        f32x4 a, b;
+        a[0] = pos[v]; a[1] = pos[n + v]; a[2] = pos[2 * n + v];
+        a[3] = dir ? dir[v] : 0.0f;
+        b[0] = dir ? dir[n + v] : 0.0f; b[1] = dir ? dir[2 * n + v] : 0.0f;
+        b[2] = rad ? rad[v] : 0.0f; b[3] = spdf ? spdf[v] : 0.0f;
+        f32x4 *r = reinterpret_cast<f32x4 *>(rec + (size_t)slot * 8);
+        r[0] = a;
+        r[1] = b;
+    }
 }
 
-// cells: kSortCells counters followed by kScanBlocks block totals
-hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *perm,
-                         uint32_t *cells, hipStream_t s)
+// cells: kSortCells counters followed by kScanBlocks block totals; inv
+// (optional) receives the inverse of perm, rec (optional) the inputs in
+// visiting order, 8 floats per slot
+hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                         const float *rad, const float *spdf, uint32_t *perm, uint32_t *inv,
+                         float *rec, uint32_t *cells, hipStream_t s)
 {
     int tok;
     timed_begin(ctx, "spatial_sort", s, &tok);
@@ -110,7 +131,8 @@ hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *pe
                        cells + kSortCells);
     hipLaunchKernelGGL(k_sort_scan_add, dim3(kScanBlocks), dim3(1024), 0, s, cells,
                        cells + kSortCells);
-    hipLaunchKernelGGL(k_sort_place, dim3(blocks), dim3(256), 0, s, pos, n, cells, perm);
+    hipLaunchKernelGGL(k_sort_place, dim3(blocks), dim3(256), 0, s, pos, dir, rad, spdf, n, cells,
+                       perm, inv, rec);
     timed_end(ctx, tok, s);
     return hipGetLastError();
 }

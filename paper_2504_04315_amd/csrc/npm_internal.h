@@ -87,7 +87,11 @@ struct npm_ctx {
     float *s_dw_part = nullptr;        // dW partials
     int64_t dw_part_elems = 0;
     // spatial order of a training batch (fused path)
-    uint32_t *s_perm = nullptr;        // [sort_n]
+    uint32_t *s_perm = nullptr;        // [sort_n] visiting slot -> vertex
+    uint32_t *s_inv = nullptr;         // [sort_n] vertex -> visiting slot
+    float *s_rec = nullptr;            // [sort_n][8] inputs in visiting order
+    float *s_qstage = nullptr;         // [qstage_n][40] staged query outputs
+    int64_t qstage_n = 0;
     uint32_t *s_cells = nullptr;       // 2^18 cell counts / offsets, 256 block totals
     int64_t sort_n = 0;
     // per-tile dG of a fused training batch, for the aggregated scatter
@@ -162,8 +166,9 @@ hipError_t staged_scatter(npm_ctx *ctx, int64_t n, const float *pos, const float
                           float *grad, hipStream_t s);
 
 // spatial order of a batch (k_sort.hip): perm lists the vertices by cell
-hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *perm,
-                         uint32_t *cells, hipStream_t s);
+hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
+                         const float *rad, const float *spdf, uint32_t *perm, uint32_t *inv,
+                         float *rec, uint32_t *cells, hipStream_t s);
 // Smallest batch NPM_ORDER_AUTO sorts.  On the 16-level hash grid at 2^20
 // vertices the sort (0.22 ms) halves the scatter's line requests through the
 // LDS window (4.43 -> 2.42 ms) and speeds the tile kernel's gathers (1.61 ->
@@ -172,13 +177,17 @@ hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *pe
 constexpr int64_t kSortMinBatch = 1 << 15;
 
 // fused path (k_fused.hip)
+// perm/inv (optional): visiting order and its inverse; the outputs then go
+// through `stage` (n slots of 40 floats) and an un-permuting pass
 hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                        uint64_t seed, uint32_t stream_id, float *lobes, float *pdf, float *sdir,
-                       float *spdf, hipStream_t s);
+                       float *spdf, const uint32_t *perm, const uint32_t *inv, const float *rec,
+                       float *stage, hipStream_t s);
 // perm (optional): the order in which to visit the vertices; dg_tiles: the
 // per-tile dG buffer (required when grad is set)
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                           const float *rad, const float *spdf, float *grad, double *loss_out,
-                          const uint32_t *perm, float *dg_tiles, hipStream_t s);
+                          const uint32_t *perm, const float *rec, float *dg_tiles,
+                          hipStream_t s);
 
 }  // namespace npm

@@ -211,7 +211,9 @@ static void free_ctx(npm_ctx *ctx)
     for (void *p : {(void *)ctx->params, (void *)ctx->grads, (void *)ctx->adam_m,
                     (void *)ctx->adam_v, ctx->grid16, (void *)ctx->mlp_img, ctx->mlp_img16,
                     (void *)ctx->partials, (void *)ctx->stats, (void *)ctx->s_dw_part,
-                    (void *)ctx->s_perm, (void *)ctx->s_cells, (void *)ctx->s_dgt,
+                    (void *)ctx->s_perm, (void *)ctx->s_inv, (void *)ctx->s_rec,
+                    (void *)ctx->s_qstage,
+                    (void *)ctx->s_cells, (void *)ctx->s_dgt,
                     (void *)ctx->ema, (void *)ctx->ema_img, ctx->ema_img16, ctx->ema_grid16})
         if (p) hipFree(p);
     for (auto &p : ctx->timing.pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
@@ -324,6 +326,10 @@ static npm_status check_batch(npm_ctx *ctx, int64_t n, const float *pos)
     return NPM_OK;
 }
 
+static bool use_order(const npm_ctx *ctx, int64_t n);
+static hipError_t ensure_sort(npm_ctx *ctx, int64_t n);
+static hipError_t ensure_qstage(npm_ctx *ctx, int64_t n);
+
 npm_status npm_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                      uint64_t rng_seed, uint32_t rng_stream, float *lobes, float *pdf,
                      float *sample_dir, float *sample_pdf, void *stream)
@@ -338,8 +344,17 @@ npm_status npm_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir
     hipStream_t s = (hipStream_t)stream;
     try {
         if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
+            const uint32_t *perm = nullptr;
+            if (use_order(ctx, n) && (lobes || pdf || sample_dir || sample_pdf)) {
+                NPM_HIP(ensure_sort(ctx, n), "order scratch allocation");
+                NPM_HIP(ensure_qstage(ctx, n), "query staging allocation");
+                NPM_HIP(spatial_order(ctx, n, pos, dir, nullptr, nullptr, ctx->s_perm, ctx->s_inv,
+                                      ctx->s_rec, ctx->s_cells, s), "spatial order");
+                perm = ctx->s_perm;
+            }
             NPM_HIP(fused_query(ctx, n, pos, dir, rng_seed, rng_stream, lobes, pdf, sample_dir,
-                                sample_pdf, s), "fused query");
+                                sample_pdf, perm, ctx->s_inv, ctx->s_rec, ctx->s_qstage, s),
+                    "fused query");
             return NPM_OK;
         }
         NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
@@ -368,15 +383,42 @@ static npm_status check_train(npm_ctx *ctx, int64_t n, const float *pos, const f
     return NPM_OK;
 }
 
+// Whether a fused call visits a batch of n vertices in spatial order.
+static bool use_order(const npm_ctx *ctx, int64_t n)
+{
+    const int order = ctx->net.cfg.batch_order;
+    return ctx->net.cfg.exec_mode == NPM_EXEC_FUSED && n > 1 &&
+           (order == NPM_ORDER_SPATIAL || (order == NPM_ORDER_AUTO && n >= kSortMinBatch));
+}
+
+static hipError_t ensure_qstage(npm_ctx *ctx, int64_t n)
+{
+    if (n <= ctx->qstage_n) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    if (ctx->s_qstage) hipFree(ctx->s_qstage);
+    ctx->s_qstage = nullptr;
+    ctx->qstage_n = 0;
+    e = hipMalloc((void **)&ctx->s_qstage, (size_t)n * 40 * sizeof(float));
+    if (e != hipSuccess) return e;
+    ctx->qstage_n = n;
+    return hipSuccess;
+}
+
 static hipError_t ensure_sort(npm_ctx *ctx, int64_t n)
 {
     if (n <= ctx->sort_n) return hipSuccess;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
     if (ctx->s_perm) hipFree(ctx->s_perm);
-    ctx->s_perm = nullptr;
+    if (ctx->s_inv) hipFree(ctx->s_inv);
+    if (ctx->s_rec) hipFree(ctx->s_rec);
+    ctx->s_perm = ctx->s_inv = nullptr;
+    ctx->s_rec = nullptr;
     ctx->sort_n = 0;
     e = hipMalloc((void **)&ctx->s_perm, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->s_inv, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->s_rec, (size_t)n * 32);
     if (e == hipSuccess && !ctx->s_cells)
         e = hipMalloc((void **)&ctx->s_cells, ((size_t)1 << 18) * 4 + 256 * 4);  // counts, block totals
     if (e != hipSuccess) return e;
@@ -406,16 +448,16 @@ static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const
 {
     if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
         const uint32_t *perm = nullptr;
-        const int order = ctx->net.cfg.batch_order;
-        if (grad && n > 1 &&
-            (order == NPM_ORDER_SPATIAL || (order == NPM_ORDER_AUTO && n >= kSortMinBatch))) {
+        if (grad && use_order(ctx, n)) {
             NPM_HIP(ensure_sort(ctx, n), "order scratch allocation");
-            NPM_HIP(spatial_order(ctx, n, pos, ctx->s_perm, ctx->s_cells, s), "spatial order");
+            NPM_HIP(spatial_order(ctx, n, pos, dir, rad, spdf, ctx->s_perm, nullptr, ctx->s_rec,
+                                  ctx->s_cells, s), "spatial order");
             perm = ctx->s_perm;
         }
         if (grad) NPM_HIP(ensure_dgt(ctx, n), "dG scratch allocation");
         NPM_HIP(fused_backward(ctx, n, pos, dir, rad, spdf, grad, loss_out, perm,
-                               grad ? ctx->s_dgt : nullptr, s), "fused backward");
+                               perm ? ctx->s_rec : nullptr, grad ? ctx->s_dgt : nullptr, s),
+                "fused backward");
         return NPM_OK;
     }
     NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
@@ -460,7 +502,7 @@ npm_status npm_loss(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
         if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED && ctx->net.cfg.precision == NPM_PREC_BF16) {
             // the loss of the precision form: the fused kernel with no gradient output
             NPM_HIP(fused_backward(ctx, n, pos, dir, radiance, sampling_pdf, nullptr, loss_out,
-                                   nullptr, nullptr, s), "fused loss");
+                                   nullptr, nullptr, nullptr, s), "fused loss");
             return NPM_OK;
         }
         NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");

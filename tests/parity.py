@@ -94,3 +94,41 @@ def sample_bound(O, net, raw, raw_scale, u, base=2e-5, rtol=RTOL):
 def check_grads(name, got, ref, gabs, rtol=RTOL, atol=1e-12):
     bound = rtol * gabs + atol
     return assert_within(name, got, ref, bound)
+
+
+def fibonacci_sphere(m):
+    i = np.arange(m) + 0.5
+    z = 1 - 2 * i / m
+    a = i * np.pi * (3 - np.sqrt(5))
+    r = np.sqrt(1 - z * z)
+    return np.stack([r * np.cos(a), r * np.sin(a), z], 1)
+
+
+def sample_chi2_pvalue(O, on, raw, samples, nz=8, nphi=8, quad=16):
+    """Chi-square p-value of sampled directions [m][3] against the oracle's
+    mixture pdf for the raw outputs `raw` [4K]: cells of equal width in cos
+    theta and phi, expected counts by Gauss-Legendre quadrature of the pdf,
+    cells expecting fewer than 5 draws dropped."""
+    from scipy import stats
+    m = samples.shape[0]
+    zb = np.linspace(-1, 1, nz + 1)
+    pb = np.linspace(-np.pi, np.pi, nphi + 1)
+    H, _, _ = np.histogram2d(samples[:, 2], np.arctan2(samples[:, 1], samples[:, 0]),
+                             bins=[zb, pb])
+    x, wx = np.polynomial.legendre.leggauss(quad)
+    E = np.zeros((nz, nphi))
+    for i in range(nz):
+        z = 0.5 * (zb[i + 1] - zb[i]) * (x + 1) + zb[i]
+        wz = 0.5 * (zb[i + 1] - zb[i]) * wx
+        for j in range(nphi):
+            ph = 0.5 * (pb[j + 1] - pb[j]) * (x + 1) + pb[j]
+            wp = 0.5 * (pb[j + 1] - pb[j]) * wx
+            Z, PH = np.meshgrid(z, ph, indexing="ij")
+            R = np.sqrt(1 - Z * Z)
+            d = np.stack([R * np.cos(PH), R * np.sin(PH), Z], -1).reshape(-1, 3)
+            lp = O.logpdf(on, np.broadcast_to(raw, (d.shape[0], raw.shape[0])), d)
+            E[i, j] = np.sum(np.exp(lp) * np.outer(wz, wp).reshape(-1))
+    E *= m / E.sum()
+    keep = E > 5
+    chi = float(((H[keep] - E[keep]) ** 2 / E[keep]).sum())
+    return float(stats.chi2.sf(chi, keep.sum() - 1))

@@ -285,3 +285,51 @@ def test_paper_config_parity(O, torch, mode):
                               "paper")
     print("\n".join(msgs + m2 + m3))
     model.close()
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_cfg1_sample_draws(O, torch, mode):
+    """cfg1's 4,096 draws at each of 8 fixed vertices: every draw equals the
+    oracle's with the same uniforms (the query parity bound), and each
+    vertex's draws pass a chi-square test against the oracle's pdf."""
+    model = B.NPM(B.make_config(W.CFG1, exec_mode=MODES[mode]))
+    on = oracle_net(O, W.CFG1)
+    rng = np.random.default_rng(9)
+    params = randomize(model, on, rng)
+    base = W.make_batch("cube", 8, seed=13)
+    rep = base.subset(np.repeat(np.arange(8), 4096))
+    msgs, q = check_query(O, torch, model, on, params, rep, seed=21, sid=1)
+    out = model.query(dev(torch, rep.pos), None, seed=21, stream_id=1, lobes=False)
+    torch.cuda.synchronize()
+    sd = out["sample_dir"].cpu().numpy().T.astype(np.float64)
+    pv = [P.sample_chi2_pvalue(O, on, q["raw"][k * 4096], sd[k * 4096:(k + 1) * 4096])
+          for k in range(8)]
+    print("\n".join(msgs), "\nchi-square p-values:", np.round(pv, 4))
+    assert min(pv) > 1e-4
+    model.close()
+
+
+@pytest.mark.parametrize("net", [W.CFG2, W.CFG3], ids=["fp32", "bf16"])
+def test_query_order_is_invisible(torch, net):
+    """A spatially ordered query (sort, visit in Morton order with each
+    vertex's own uniforms, stage the outputs, un-permute) returns exactly
+    the outputs of the query in the caller's order, whichever outputs are
+    requested."""
+    a = B.NPM(B.make_config(net, exec_mode=B.EXEC_FUSED, batch_order=B.ORDER_NONE))
+    b = B.NPM(B.make_config(net, exec_mode=B.EXEC_FUSED, batch_order=B.ORDER_SPATIAL))
+    for n in (40001, 2, 33):
+        batch = W.make_batch("surface", n, seed=n)
+        pos, d = dev(torch, batch.pos), dev(torch, batch.dir)
+        for kw in (dict(), dict(lobes=False), dict(sample=False)):
+            qa = a.query(pos, d, seed=3, stream_id=4, **kw)
+            qb = b.query(pos, d, seed=3, stream_id=4, **kw)
+            torch.cuda.synchronize()
+            for k, v in qa.items():
+                assert (v is None) == (qb[k] is None), k
+                if v is not None:
+                    assert torch.equal(v, qb[k]), (n, kw, k)
+        qa, qb = a.query(pos, None, seed=1), b.query(pos, None, seed=1)
+        torch.cuda.synchronize()
+        assert torch.equal(qa["sample_dir"], qb["sample_dir"])
+    a.close()
+    b.close()
