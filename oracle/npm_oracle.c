@@ -28,6 +28,10 @@
  *     interpolation over the eight cell corners, level concatenation.
  *   - Sec. 5.3 "Guiding Network": ReLU MLP, K = 8 lobes, Adam, and the
  *     numerically stable vMF sampling strategy of Jakob (2012).
+ *   - Sec. 4.3 "Full Integrand Learning" (NPM-product): the outgoing
+ *     direction and the surface normal, encoded with spherical harmonics, and
+ *     the roughness, as extra inputs after G(x); and the moving average of
+ *     the weights used for inference (Sec. 5.3).
  *
  * Readings where the paper is silent (all of them documented in the design
  * notes of the repository, and fixed identically by the library):
@@ -47,6 +51,9 @@
  *     batch mean divides by N including zero-weight samples;
  *   - Adam: beta1 0.9, beta2 0.999, eps 1e-8 outside the square root, bias
  *     correction with t counted from 1, dense update of every parameter;
+ *   - NPM-product inputs: real orthonormal spherical harmonics of
+ *     sh_degree bands (no Condon-Shortley phase, index l*l + l + m), of
+ *     omega_o then of the normal, then the roughness, all used as given;
  *   - uniforms come from Philox4x32-10 (Salmon et al., SC'11) with counter
  *     (vertex lo, vertex hi, stream, sample) and key (seed lo, seed hi),
  *     u = (word >> 8) * 2^-24; lobe selection takes the first k with
@@ -88,9 +95,25 @@ typedef struct {
     int32_t n_levels, feat, log2_table, dense_only;
     int32_t base_res, max_res;
     int32_t n_in, width, n_hidden, n_lobes, n_layers, n_out;
+    int32_t sh_degree;                /* NPM-product: SH bands of omega_o, n   */
+    int32_t n_aux;                    /* extra inputs after G(x) (0: radiance) */
 } npmo_net;
 
 static const double PI = 3.14159265358979323846264338327950288;
+
+/* MLP shapes and the flat offsets of its matrices (after the grid).        */
+static void oracle_layers(npmo_net *net)
+{
+    net->n_in = net->n_levels * net->feat + net->n_aux;
+    int64_t off = net->grid_params;
+    for (int i = 0; i < net->n_layers; ++i) {
+        net->layer_in[i] = (i == 0) ? net->n_in : net->width;
+        net->layer_out[i] = (i == net->n_hidden) ? net->n_out : net->width;
+        net->layer_offset[i] = off;
+        off += (int64_t)net->layer_in[i] * net->layer_out[i];
+    }
+    net->n_params = off;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Level layout: Sec. 5.1, "D_l grows exponentially".                       */
@@ -128,16 +151,24 @@ int npmo_net_init(npmo_net *net, int L, int F, int base_res, int max_res,
         net->grid_entries += net->size[l];
     }
     net->grid_params = net->grid_entries * F;
-    net->n_in = L * F; net->width = width; net->n_hidden = n_hidden;
+    net->width = width; net->n_hidden = n_hidden;
     net->n_lobes = K; net->n_out = 4 * K; net->n_layers = n_hidden + 1;
-    int64_t off = net->grid_params;
-    for (int i = 0; i < net->n_layers; ++i) {
-        net->layer_in[i] = (i == 0) ? net->n_in : width;
-        net->layer_out[i] = (i == n_hidden) ? net->n_out : width;
-        net->layer_offset[i] = off;
-        off += (int64_t)net->layer_in[i] * net->layer_out[i];
-    }
-    net->n_params = off;
+    oracle_layers(net);
+    return 0;
+}
+
+/* Full integrand learning (Sec. 4.3, NPM-product): the MLP input is G(x)
+ * followed by the spherical-harmonics encoding of the outgoing direction and
+ * of the surface normal (sh_degree bands each, sh_degree^2 values) and the
+ * roughness.  sh_degree 0 restores the radiance-based network.              */
+int npmo_net_set_inputs(npmo_net *net, int sh_degree)
+{
+    if (!net || sh_degree < 0 || sh_degree > 4) return -1;
+    int n_aux = sh_degree ? 2 * sh_degree * sh_degree + 1 : 0;
+    if (net->n_levels * net->feat + n_aux > NPMO_MAX_WIDTH) return -1;
+    net->sh_degree = sh_degree;
+    net->n_aux = n_aux;
+    oracle_layers(net);
     return 0;
 }
 
@@ -230,6 +261,87 @@ void npmo_corners(const npmo_net *net, int64_t n, const float *pos /* [3][n] */,
         oracle_corners_one(net, pos[i], pos[n + i], pos[2 * n + i], idx + i * L * 8, w + i * L * 8);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Real spherical harmonics, orthonormal on the unit sphere, bands l < deg,  */
+/* index l*l + l + m (m = -l..l): m > 0 goes with cos(m phi), m < 0 with    */
+/* sin(|m| phi), written as polynomials in the components of the unit       */
+/* vector.  Each function is a list of monomials c x^a y^b z^e; the value    */
+/* is their sum and the condition scale the sum of their magnitudes.        */
+/* ------------------------------------------------------------------------ */
+typedef struct { double c; int a, b, e; } oracle_mono;
+
+static int oracle_sh_monos(int idx, oracle_mono *m)
+{
+    const double k0 = 0.5 / sqrt(PI);                     /* Y_00            */
+    const double k1 = sqrt(3.0 / (4.0 * PI));             /* band 1          */
+    const double k2 = 0.5 * sqrt(15.0 / PI), k20 = 0.25 * sqrt(5.0 / PI),
+                 k22 = 0.25 * sqrt(15.0 / PI);
+    const double k33 = 0.25 * sqrt(35.0 / (2.0 * PI)), k32 = 0.5 * sqrt(105.0 / PI),
+                 k31 = 0.25 * sqrt(21.0 / (2.0 * PI)), k30 = 0.25 * sqrt(7.0 / PI),
+                 k32c = 0.25 * sqrt(105.0 / PI);
+    switch (idx) {
+    case 0: m[0] = (oracle_mono){k0, 0, 0, 0}; return 1;
+    case 1: m[0] = (oracle_mono){k1, 0, 1, 0}; return 1;                 /* y   */
+    case 2: m[0] = (oracle_mono){k1, 0, 0, 1}; return 1;                 /* z   */
+    case 3: m[0] = (oracle_mono){k1, 1, 0, 0}; return 1;                 /* x   */
+    case 4: m[0] = (oracle_mono){k2, 1, 1, 0}; return 1;                 /* xy  */
+    case 5: m[0] = (oracle_mono){k2, 0, 1, 1}; return 1;                 /* yz  */
+    case 6: m[0] = (oracle_mono){3.0 * k20, 0, 0, 2};                    /* 3z^2-1 */
+            m[1] = (oracle_mono){-k20, 0, 0, 0}; return 2;
+    case 7: m[0] = (oracle_mono){k2, 1, 0, 1}; return 1;                 /* xz  */
+    case 8: m[0] = (oracle_mono){k22, 2, 0, 0};                          /* x^2-y^2 */
+            m[1] = (oracle_mono){-k22, 0, 2, 0}; return 2;
+    case 9: m[0] = (oracle_mono){3.0 * k33, 2, 1, 0};                    /* y(3x^2-y^2) */
+            m[1] = (oracle_mono){-k33, 0, 3, 0}; return 2;
+    case 10: m[0] = (oracle_mono){k32, 1, 1, 1}; return 1;               /* xyz */
+    case 11: m[0] = (oracle_mono){5.0 * k31, 0, 1, 2};                   /* y(5z^2-1) */
+             m[1] = (oracle_mono){-k31, 0, 1, 0}; return 2;
+    case 12: m[0] = (oracle_mono){5.0 * k30, 0, 0, 3};                   /* z(5z^2-3) */
+             m[1] = (oracle_mono){-3.0 * k30, 0, 0, 1}; return 2;
+    case 13: m[0] = (oracle_mono){5.0 * k31, 1, 0, 2};                   /* x(5z^2-1) */
+             m[1] = (oracle_mono){-k31, 1, 0, 0}; return 2;
+    case 14: m[0] = (oracle_mono){k32c, 2, 0, 1};                        /* z(x^2-y^2) */
+             m[1] = (oracle_mono){-k32c, 0, 2, 1}; return 2;
+    case 15: m[0] = (oracle_mono){k33, 3, 0, 0};                         /* x(x^2-3y^2) */
+             m[1] = (oracle_mono){-3.0 * k33, 1, 2, 0}; return 2;
+    default: return 0;
+    }
+}
+
+/* out[i] (and scale[i], or NULL) for i < deg*deg at the vector (x, y, z).   */
+void npmo_sh(int deg, double x, double y, double z, double *out, double *scale)
+{
+    for (int i = 0; i < deg * deg; ++i) {
+        oracle_mono m[2];
+        int k = oracle_sh_monos(i, m);
+        double v = 0.0, a = 0.0;
+        for (int j = 0; j < k; ++j) {
+            double t = m[j].c * pow(x, m[j].a) * pow(y, m[j].b) * pow(z, m[j].e);
+            v += t; a += fabs(t);
+        }
+        out[i] = v;
+        if (scale) scale[i] = a;
+    }
+}
+
+/* The extra inputs of NPM-product for one vertex: aux7 = (omega_o, normal,
+ * roughness), as float values; appended after the net's L*F grid features. */
+static void oracle_aux_one(const npmo_net *net, const float *aux7, double *G, double *gscale)
+{
+    int base = net->n_levels * net->feat, d = net->sh_degree, nb = d * d;
+    if (!net->n_aux) return;
+    npmo_sh(d, aux7[0], aux7[1], aux7[2], G + base, gscale ? gscale + base : NULL);
+    npmo_sh(d, aux7[3], aux7[4], aux7[5], G + base + nb, gscale ? gscale + base + nb : NULL);
+    G[base + 2 * nb] = aux7[6];
+    if (gscale) gscale[base + 2 * nb] = fabs((double)aux7[6]);
+}
+
+/* Vertex i's extra inputs from the SoA array aux [7][n] (zeros if NULL).   */
+static void oracle_aux_fetch(const float *aux, int64_t n, int64_t i, float aux7[7])
+{
+    for (int j = 0; j < 7; ++j) aux7[j] = aux ? aux[j * n + i] : 0.0f;
+}
+
 /* G(x) = concat_l sum_corners w_c V_l[c]  (level-major, index l*F + f).
  * gscale receives sum_c |w_c V_l[c]| per output, the size of the terms.    */
 static void oracle_encode_one(const npmo_net *net, float px, float py, float pz,
@@ -251,14 +363,19 @@ static void oracle_encode_one(const npmo_net *net, float px, float py, float pz,
         }
 }
 
-void npmo_encode(const npmo_net *net, int64_t n, const float *pos, const double *params,
-                 double *G /* [n][n_in] */, double *gscale /* [n][n_in] or NULL */)
+void npmo_encode(const npmo_net *net, int64_t n, const float *pos, const float *aux /* [7][n] or NULL */,
+                 const double *params, double *G /* [n][n_in] */,
+                 double *gscale /* [n][n_in] or NULL */)
 {
     int ni = net->n_in;
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i)
+    for (int64_t i = 0; i < n; ++i) {
+        float a7[7];
+        oracle_aux_fetch(aux, n, i, a7);
         oracle_encode_one(net, pos[i], pos[n + i], pos[2 * n + i], params, G + i * ni,
                           gscale ? gscale + i * ni : NULL);
+        oracle_aux_one(net, a7, G + i * ni, gscale ? gscale + i * ni : NULL);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -448,7 +565,8 @@ static void oracle_sample_one(const npmo_net *net, const oracle_lobe *lob, const
 
 /* Query: lobes, log pdf at dir, one sample and its log pdf, per vertex.
  * vid gives the vertex number used as the random counter (NULL = 0..n-1). */
-void npmo_query(const npmo_net *net, int64_t n, const float *pos, const float *dir /* [3][n] or NULL */,
+void npmo_query(const npmo_net *net, int64_t n, const float *pos, const float *aux /* [7][n] or NULL */,
+                const float *dir /* [3][n] or NULL */,
                 const int64_t *vid, uint64_t seed, uint32_t stream, const double *params,
                 double *G_out /* [n][n_in] or NULL */, double *raw_out /* [n][4K] or NULL */,
                 double *lobes /* [n][K][4] or NULL */, double *logpdf /* [n] or NULL */,
@@ -461,7 +579,10 @@ void npmo_query(const npmo_net *net, int64_t n, const float *pos, const float *d
         double G[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES];
         double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
         oracle_lobe lob[NPMO_MAX_LOBES];
+        float a7[7];
+        oracle_aux_fetch(aux, n, i, a7);
         oracle_encode_one(net, pos[i], pos[n + i], pos[2 * n + i], params, G, NULL);
+        oracle_aux_one(net, a7, G, NULL);
         oracle_mlp_one(net, G, params, acts, raw, NULL);
         oracle_map(net, raw, lob);
         if (G_out) for (int j = 0; j < net->n_in; ++j) G_out[i * net->n_in + j] = G[j];
@@ -618,9 +739,9 @@ double npmo_loss_grad(const npmo_net *net, int64_t n, int64_t n_total, const dou
  * cond(dz) = cond(dh) where z > 0; cond(dh_k) = sum_o |W_ok| cond(dz_o);
  * cond(dW_ok) += cond(dz_o) |h_k| + |dz_o| cond(h_k); the grid entry of a
  * corner gets w_c cond(dG).                                               */
-static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, const double w3[3],
-                                     double wgt, double invN, const double *params,
-                                     double *gcond)
+static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, const float *aux7,
+                                     const double w3[3], double wgt, double invN,
+                                     const double *params, double *gcond)
 {
     int L = net->n_levels, F = net->feat;
     double G[NPMO_MAX_WIDTH], Gc[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES], rawc[4 * NPMO_MAX_LOBES];
@@ -631,6 +752,7 @@ static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, con
     double cw[NPMO_MAX_LEVELS * 8];
     if (wgt == 0.0) return;
     oracle_encode_one(net, pos3[0], pos3[1], pos3[2], params, G, Gc);
+    oracle_aux_one(net, aux7, G, Gc);
     oracle_mlp_cond_one(net, G, Gc, params, acts, cacts, raw, rawc);
     oracle_loss_grad_one(net, raw, w3, wgt, invN, draw);
     oracle_head_cond(net, raw, rawc, w3, wgt, invN, cdraw);
@@ -663,19 +785,23 @@ static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, con
 }
 
 void npmo_backward_cond(const npmo_net *net, int64_t n, int64_t n_total, const float *pos,
-                        const float *dir, const float *rad, const float *spdf, const double *params,
+                        const float *aux /* [7][n] or NULL */, const float *dir, const float *rad,
+                        const float *spdf, const double *params,
                         double *gcond /* [n_params], accumulated */)
 {
     double invN = 1.0 / (double)n_total;
     for (int64_t i = 0; i < n; ++i) {
-        float p3[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+        float p3[3] = {pos[i], pos[n + i], pos[2 * n + i]}, a7[7];
         double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
-        oracle_backward_cond_one(net, p3, w3, oracle_weight(rad[i], spdf[i]), invN, params, gcond);
+        oracle_aux_fetch(aux, n, i, a7);
+        oracle_backward_cond_one(net, p3, a7, w3, oracle_weight(rad[i], spdf[i]), invN, params,
+                                 gcond);
     }
 }
 
 double npmo_backward(const npmo_net *net, int64_t n, int64_t n_total, const float *pos,
-                     const float *dir, const float *rad, const float *spdf, const double *params,
+                     const float *aux /* [7][n] or NULL */, const float *dir, const float *rad,
+                     const float *spdf, const double *params,
                      double *grad /* [n_params] */, double *gabs /* [n_params] or NULL */,
                      double *draw_out /* [n][4K] or NULL */, double *dG_out /* [n][n_in] or NULL */)
 {
@@ -687,8 +813,10 @@ double npmo_backward(const npmo_net *net, int64_t n, int64_t n_total, const floa
         double delta[NPMO_MAX_WIDTH], prev[NPMO_MAX_WIDTH];
         int64_t idx[NPMO_MAX_LEVELS * 8];
         double cw[NPMO_MAX_LEVELS * 8];
-        float px = pos[i], py = pos[n + i], pz = pos[2 * n + i];
+        float px = pos[i], py = pos[n + i], pz = pos[2 * n + i], a7[7];
+        oracle_aux_fetch(aux, n, i, a7);
         oracle_encode_one(net, px, py, pz, params, G, NULL);
+        oracle_aux_one(net, a7, G, NULL);
         oracle_mlp_one(net, G, params, acts, raw, NULL);
         double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
         loss += oracle_loss_grad_one(net, raw, w3, oracle_weight(rad[i], spdf[i]), invN, draw);

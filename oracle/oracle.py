@@ -35,6 +35,7 @@ class NpmoNet(C.Structure):
         ("dense_only", C.c_int32), ("base_res", C.c_int32), ("max_res", C.c_int32),
         ("n_in", C.c_int32), ("width", C.c_int32), ("n_hidden", C.c_int32),
         ("n_lobes", C.c_int32), ("n_layers", C.c_int32), ("n_out", C.c_int32),
+        ("sh_degree", C.c_int32), ("n_aux", C.c_int32),
     ]
 
 
@@ -53,17 +54,20 @@ def lib():
         L.npmo_philox.argtypes = [P, P, P]
         L.npmo_uniforms.argtypes = [i64, P, u64, u32, u32, P]
         L.npmo_corners.argtypes = [P, i64, P, P, P]
-        L.npmo_encode.argtypes = [P, i64, P, P, P, P]
+        L.npmo_net_set_inputs.argtypes = [P, i32]
+        L.npmo_net_set_inputs.restype = i32
+        L.npmo_sh.argtypes = [i32, C.c_double, C.c_double, C.c_double, P, P]
+        L.npmo_encode.argtypes = [P, i64, P, P, P, P, P]
         L.npmo_mlp_forward.argtypes = [P, i64, P, P, P, P]
         L.npmo_head.argtypes = [P, i64, P, P]
         L.npmo_logpdf.argtypes = [P, i64, P, P, P]
-        L.npmo_query.argtypes = [P, i64, P, P, P, u64, u32, P, P, P, P, P, P, P, P, P]
+        L.npmo_query.argtypes = [P, i64, P, P, P, P, u64, u32, P, P, P, P, P, P, P, P, P]
         L.npmo_sample_raw.argtypes = [P, i64, P, P, P, P]
         L.npmo_loss_grad.argtypes = [P, i64, i64, P, P, P, P, P]
         L.npmo_loss_grad.restype = C.c_double
-        L.npmo_backward.argtypes = [P, i64, i64, P, P, P, P, P, P, P, P, P]
+        L.npmo_backward.argtypes = [P, i64, i64, P, P, P, P, P, P, P, P, P, P]
         L.npmo_backward.restype = C.c_double
-        L.npmo_backward_cond.argtypes = [P, i64, i64, P, P, P, P, P, P]
+        L.npmo_backward_cond.argtypes = [P, i64, i64, P, P, P, P, P, P, P]
         L.npmo_adam.argtypes = [i64, P, P, P, P, i64, C.c_double, C.c_double, C.c_double,
                                 C.c_double]
         L.npmo_ema.argtypes = [i64, P, P, C.c_double]
@@ -83,17 +87,44 @@ def _f32soa(a, n):
     return a
 
 
+def _aux(net, aux, n):
+    """The NPM-product inputs [7][n] float32 (omega_o, normal, roughness)."""
+    if not net.n_aux:
+        return None
+    assert aux is not None, "this network takes omega_o, normal and roughness"
+    a = np.ascontiguousarray(aux, dtype=np.float32)
+    assert a.shape == (7, n), a.shape
+    return a
+
+
+def sh(degree, v):
+    """Real orthonormal spherical harmonics of `degree` bands at the vectors
+    v [m][3]: values [m][degree^2] and their condition scales."""
+    v = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((v.shape[0], degree * degree))
+    sc = np.zeros_like(out)
+    for i in range(v.shape[0]):
+        o = np.zeros(degree * degree)
+        c = np.zeros(degree * degree)
+        lib().npmo_sh(degree, v[i, 0], v[i, 1], v[i, 2], _p(o), _p(c))
+        out[i], sc[i] = o, c
+    return out, sc
+
+
 class Net:
     """Network shape and grid layout, computed by the oracle from the paper's
     rules (Sec. 5.1 level resolutions; Sec. 5.3 MLP)."""
 
     def __init__(self, n_levels, feat, base_res, max_res, log2_table, dense_only,
-                 n_hidden, width, n_lobes=8):
+                 n_hidden, width, n_lobes=8, sh_degree=0):
         self.s = NpmoNet()
         rc = lib().npmo_net_init(C.byref(self.s), n_levels, feat, base_res, max_res,
                                  log2_table, int(dense_only), n_hidden, width, n_lobes)
+        if rc == 0 and sh_degree:
+            rc = lib().npmo_net_set_inputs(C.byref(self.s), sh_degree)
         if rc != 0:
             raise ValueError("oracle: invalid network shape")
+        self.sh_degree, self.n_aux = self.s.sh_degree, self.s.n_aux
         s = self.s
         self.n_levels, self.feat, self.n_in = s.n_levels, s.feat, s.n_in
         self.n_out, self.n_lobes, self.n_params = s.n_out, s.n_lobes, s.n_params
@@ -139,13 +170,14 @@ def corners(net, pos):
     return idx, w
 
 
-def encode(net, pos, params, with_scale=False):
+def encode(net, pos, params, with_scale=False, aux=None):
     n = pos.shape[1]
     pos = _f32soa(pos, n)
+    ax = _aux(net, aux, n)
     params = np.ascontiguousarray(params, dtype=np.float64)
     G = np.zeros((n, net.n_in))
     S = np.zeros((n, net.n_in)) if with_scale else None
-    lib().npmo_encode(net.ref, n, _p(pos), _p(params), _p(G), _p(S))
+    lib().npmo_encode(net.ref, n, _p(pos), _p(ax), _p(params), _p(G), _p(S))
     return (G, S) if with_scale else G
 
 
@@ -187,11 +219,12 @@ def sample_raw(net, raw, u):
     return d, lobe
 
 
-def query(net, pos, params, dirs=None, seed=0, stream=0, vid=None):
+def query(net, pos, params, dirs=None, seed=0, stream=0, vid=None, aux=None):
     """Full query: returns a dict of G, raw, lobes [n][K][4], logpdf (if dirs),
     sample dir [n][3], sample logpdf, sampled lobe and CDF margin."""
     n = pos.shape[1]
     pos = _f32soa(pos, n)
+    ax = _aux(net, aux, n)
     d = None if dirs is None else _f32soa(dirs, n)
     params = np.ascontiguousarray(params, dtype=np.float64)
     v = None if vid is None else np.ascontiguousarray(vid, dtype=np.int64)
@@ -200,7 +233,7 @@ def query(net, pos, params, dirs=None, seed=0, stream=0, vid=None):
                logpdf=np.zeros(n) if d is not None else None,
                sdir=np.zeros((n, 3)), slogpdf=np.zeros(n), slobe=np.zeros(n, dtype=np.int32),
                margin=np.zeros(n))
-    lib().npmo_query(net.ref, n, _p(pos), _p(d), _p(v), seed, stream, _p(params),
+    lib().npmo_query(net.ref, n, _p(pos), _p(ax), _p(d), _p(v), seed, stream, _p(params),
                      _p(out["G"]), _p(out["raw"]), _p(out["lobes"]), _p(out["logpdf"]),
                      _p(out["sdir"]), _p(out["slogpdf"]), _p(out["slobe"]), _p(out["margin"]))
     return out
@@ -218,11 +251,13 @@ def loss_grad(net, raw, dirs, rad, spdf, n_total=None):
     return loss, draw
 
 
-def backward(net, pos, dirs, rad, spdf, params, n_total=None, with_abs=True, with_vertex=False):
+def backward(net, pos, dirs, rad, spdf, params, n_total=None, with_abs=True, with_vertex=False,
+             aux=None):
     """Gradient of the surrogate loss w.r.t. the flat parameters (float64),
     the sum of |contributions| per parameter, and the loss value."""
     n = pos.shape[1]
     pos = _f32soa(pos, n)
+    ax = _aux(net, aux, n)
     dirs = _f32soa(dirs, n)
     rad = np.ascontiguousarray(rad, dtype=np.float32)
     spdf = np.ascontiguousarray(spdf, dtype=np.float32)
@@ -231,7 +266,7 @@ def backward(net, pos, dirs, rad, spdf, params, n_total=None, with_abs=True, wit
     gabs = np.zeros(net.n_params) if with_abs else None
     draw = np.zeros((n, net.n_out)) if with_vertex else None
     dG = np.zeros((n, net.n_in)) if with_vertex else None
-    loss = lib().npmo_backward(net.ref, n, n if n_total is None else n_total, _p(pos), _p(dirs),
+    loss = lib().npmo_backward(net.ref, n, n if n_total is None else n_total, _p(pos), _p(ax), _p(dirs),
                                _p(rad), _p(spdf), _p(params), _p(grad), _p(gabs), _p(draw), _p(dG))
     out = dict(grad=grad, gabs=gabs, loss=loss)
     if with_vertex:
@@ -239,19 +274,20 @@ def backward(net, pos, dirs, rad, spdf, params, n_total=None, with_abs=True, wit
     return out
 
 
-def backward_cond(net, pos, dirs, rad, spdf, params, n_total=None):
+def backward_cond(net, pos, dirs, rad, spdf, params, n_total=None, aux=None):
     """Condition scale of every gradient entry (float64): the sum of the
     absolute sizes of the terms an FP32 evaluation of the backward rounds,
     propagated from the KL-gradient head through the MLP and the scatter.
     Parity tolerances are relative to it."""
     n = pos.shape[1]
     pos = _f32soa(pos, n)
+    ax = _aux(net, aux, n)
     dirs = _f32soa(dirs, n)
     rad = np.ascontiguousarray(rad, dtype=np.float32)
     spdf = np.ascontiguousarray(spdf, dtype=np.float32)
     params = np.ascontiguousarray(params, dtype=np.float64)
     out = np.zeros(net.n_params)
-    lib().npmo_backward_cond(net.ref, n, n if n_total is None else n_total, _p(pos), _p(dirs),
+    lib().npmo_backward_cond(net.ref, n, n if n_total is None else n_total, _p(pos), _p(ax), _p(dirs),
                              _p(rad), _p(spdf), _p(params), _p(out))
     return out
 
