@@ -94,6 +94,15 @@ enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
  * Adam (Sec. 5.3): lr, beta1, beta2, eps, bias-corrected, eps outside the
  *   square root.
  * batch_order: one of NPM_ORDER_* (fused path: training and queries).
+ * sh_degree: 0 for the radiance-based network (Sec. 4.1), or 1..4 for
+ *   NPM-product (Sec. 4.3, Full Integrand Learning): the MLP input is G(x)
+ *   followed by the real orthonormal spherical harmonics of sh_degree bands
+ *   (sh_degree^2 values, index l*l + l + m, no Condon-Shortley phase) of the
+ *   outgoing direction omega_o, the same of the surface normal, and the
+ *   roughness; such a context takes these per vertex through the *_aux
+ *   entry points.  The fused path is built for sh_degree 4 with
+ *   n_levels * feat_per_level = 32 (65 inputs) and sh_degree 2 with
+ *   n_levels * feat_per_level = 4; the staged path takes any.
  * ema_decay: 0 (off) or d in (0, 1).  When on, every optimizer step also
  *   updates an exponential moving average of the parameters,
  *   ema <- d * ema + (1 - d) * p (after the step, initialised to the
@@ -120,6 +129,8 @@ typedef struct {
     float eps;
     int32_t batch_order;
     float ema_decay;
+    int32_t sh_degree;
+    int32_t reserved;
     uint64_t seed;
 } npm_config;
 
@@ -216,10 +227,34 @@ npm_status npm_train_step(npm_ctx *ctx, int64_t n, const float *pos, const float
                           const float *radiance, const float *sampling_pdf, double *stats_out,
                           void *stream);
 
+/* NPM-product (sh_degree > 0): the same calls with the extra per-vertex
+ * inputs aux [7][n] float32 SoA on the device: omega_o (3 rows, unit
+ * outgoing direction), the surface normal (3 rows, unit), the roughness
+ * (1 row); used as given.  The calls without aux fail with
+ * NPM_ERR_INVALID_ARG on such a context, and these calls with aux == NULL
+ * are the plain ones on a radiance-based context.                          */
+npm_status npm_query_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                         const float *dir, uint64_t rng_seed, uint32_t rng_stream, float *lobes,
+                         float *pdf, float *sample_dir, float *sample_pdf, void *stream);
+npm_status npm_backward_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                            const float *dir, const float *radiance, const float *sampling_pdf,
+                            float *grad_out, double *loss_out, void *stream);
+npm_status npm_loss_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                        const float *dir, const float *radiance, const float *sampling_pdf,
+                        double *loss_out, void *stream);
+npm_status npm_train_step_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                              const float *dir, const float *radiance, const float *sampling_pdf,
+                              double *stats_out, void *stream);
+npm_status npm_encode_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux, float *G,
+                          void *stream);
+npm_status npm_forward_raw_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                               float *raw, void *stream);
+
 /* Stage outputs, for checking each step of the path on its own.
  *   npm_corner_index: idx [L][8][n] global table entry of corner b of level
  *     l (corner b has offsets (b&1, b>>1&1, b>>2&1) in x, y, z).
- *   npm_encode: G [n_levels*feat][n], the concatenated embedding (Sec. 5.1).
+ *   npm_encode: G [n_in][n], the MLP input: the concatenated embedding
+ *     (Sec. 5.1), then the NPM-product inputs when sh_degree > 0.
  *   npm_forward_raw: raw [4K][n], the MLP output before the mappings.      */
 npm_status npm_corner_index(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *idx,
                             void *stream);

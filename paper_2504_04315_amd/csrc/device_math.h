@@ -284,6 +284,35 @@ __device__ __forceinline__ void mfma_layer_bf16(const __bf16 *__restrict__ img, 
         for (int v = 0; v < 16; ++v) y[16 * b + v] = acc[b][v];
 }
 
+// ------------------------------------------------------------------ NPM-product
+// Real orthonormal spherical harmonics of the first four bands at the vector
+// (x, y, z) (Sec. 4.3 encodes the outgoing direction and the normal with
+// them): y[l*l + l + m], m > 0 with cos(m phi), m < 0 with sin(|m| phi), no
+// Condon-Shortley phase.  Constants: band 0 1/(2 sqrt(pi)); band 1
+// sqrt(3/(4 pi)); band 2 sqrt(15/pi)/2, sqrt(5/pi)/4, sqrt(15/pi)/4; band 3
+// sqrt(35/(2 pi))/4, sqrt(105/pi)/2, sqrt(21/(2 pi))/4, sqrt(7/pi)/4,
+// sqrt(105/pi)/4.
+__device__ __forceinline__ void sh_bands4(float x, float y, float z, float *o)
+{
+    const float xx = x * x, yy = y * y, zz = z * z;
+    o[0] = 0.28209479177387814f;
+    o[1] = 0.48860251190291992f * y;
+    o[2] = 0.48860251190291992f * z;
+    o[3] = 0.48860251190291992f * x;
+    o[4] = 1.0925484305920792f * x * y;
+    o[5] = 1.0925484305920792f * y * z;
+    o[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+    o[7] = 1.0925484305920792f * x * z;
+    o[8] = 0.54627421529603959f * (xx - yy);
+    o[9] = 0.59004358992664352f * y * (3.0f * xx - yy);
+    o[10] = 2.8906114426405538f * x * y * z;
+    o[11] = 0.45704579946446572f * y * (5.0f * zz - 1.0f);
+    o[12] = 0.37317633259011540f * z * (5.0f * zz - 3.0f);
+    o[13] = 0.45704579946446572f * x * (5.0f * zz - 1.0f);
+    o[14] = 1.4453057213202769f * z * (xx - yy);
+    o[15] = 0.59004358992664352f * x * (xx - 3.0f * yy);
+}
+
 // Wave-wide helpers for the two half-waves of a tile.
 __device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); }
 

@@ -94,6 +94,32 @@ __device__ __forceinline__ void encode_tile(const GridView &gv, int h, float px,
     }
 }
 
+// NPM-product inputs (Sec. 4.3) of the tile vertex into the feature
+// registers: features GF .. GF + 2 SHD^2 hold the spherical harmonics of the
+// outgoing direction, then of the normal, then the roughness (a7 = omega_o,
+// normal, roughness).  Which register holds which input is fixed at compile
+// time for each half-wave, so the fill is one select per register.
+template <int NB>
+__device__ __forceinline__ float aux_value(int k, const float *yo, const float *yn, float r)
+{
+    return k < NB ? yo[k] : (k < 2 * NB ? yn[k - NB] : r);
+}
+
+template <int IN_P, int GF, int SHD>
+__device__ __forceinline__ void aux_fill(int h, const float *a7, float *x)
+{
+    constexpr int NB = SHD * SHD, NA = 2 * NB + 1;
+    float yo[16], yn[16];
+    sh_bands4(a7[0], a7[1], a7[2], yo);
+    sh_bands4(a7[3], a7[4], a7[5], yn);
+#pragma unroll
+    for (int a = 0; a < IN_P / 2; ++a) {
+        const int k0 = 8 * (a / 4) + (a & 3) - GF, k1 = k0 + 4;   // inputs of half 0 / half 1
+        if (k0 >= 0 && k0 < NA && h == 0) x[a] = aux_value<NB>(k0, yo, yn, a7[6]);
+        if (k1 >= 0 && k1 < NA && h == 1) x[a] = aux_value<NB>(k1, yo, yn, a7[6]);
+    }
+}
+
 // ------------------------------------------------------------------ MLP
 template <bool BF, int IN_P, int OUT_P>
 __device__ __forceinline__ void layer(const void *img, const float *x, float *y, int lane)
@@ -175,12 +201,36 @@ struct QueryIO {
     const uint32_t *perm = nullptr;     // visiting order, or null: 0..n-1
     float *stage = nullptr;             // with perm: kStageFloats per slot, AoS
     const float *rec = nullptr;         // with perm: the inputs in visiting order
+    const float *aux = nullptr;         // NPM-product inputs [7][n]
+    int rec_stride = 8;                 // floats per record (16 with NPM-product)
 };
 
 // A vertex's inputs in visiting order (written by the spatial sort, 32 bytes
 // per slot so that a wave reads its tile coalesced): position, direction,
-// radiance, sampling pdf (zeros where the call has none).
+// radiance, sampling pdf (zeros where the call has none); with NPM-product 64
+// bytes, followed by omega_o, the normal and the roughness.
 constexpr int kRecFloats = 8;
+
+// The NPM-product inputs of slot v (vertex vv) from the record or the SoA array.
+__device__ __forceinline__ void load_aux(const float *rec, int rec_stride, const float *aux,
+                                         int64_t n, int64_t v, int64_t vv, float *a7)
+{
+    if (rec) {
+        const f32x4 *r = reinterpret_cast<const f32x4 *>(rec + (size_t)v * rec_stride + 8);
+        const f32x4 p = r[0], q = r[1];
+        a7[0] = p[0]; a7[1] = p[1]; a7[2] = p[2]; a7[3] = p[3];
+        a7[4] = q[0]; a7[5] = q[1]; a7[6] = q[2];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) a7[j] = aux[j * n + vv];
+    }
+}
+
+// Compile-time shape of the NPM-product inputs (PG: 0 none; 1: 32 grid
+// features and 4 SH bands; 2: 4 grid features and 2 bands).
+template <int PG> struct ProductShape { static constexpr int GF = 0, SHD = 0; };
+template <> struct ProductShape<1> { static constexpr int GF = 32, SHD = 4; };
+template <> struct ProductShape<2> { static constexpr int GF = 4, SHD = 2; };
 
 // Staged query outputs of one visiting slot (AoS, 160 bytes), laid out so
 // that each half-wave writes whole 16-byte pieces: floats [20 h, 20 h + 16)
@@ -192,7 +242,7 @@ constexpr int kStagePdf = 16, kStageSdir = 17, kStageSpdf = 36;
 
 // One 32-vertex tile t of a query: encode, MLP, mappings, pdf at dir, one
 // sample per vertex and its pdf.  img: the forward weight image in LDS.
-template <int IN_P, int HID_P, int NH, int F, bool BF>
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0>
 __device__ __forceinline__ void query_tile(const GridView &gv, const void *img, const QueryIO &io,
                                            int64_t t, int lane)
 {
@@ -205,7 +255,7 @@ __device__ __forceinline__ void query_tile(const GridView &gv, const void *img, 
     float *st = io.stage ? io.stage + (size_t)(valid ? v : n - 1) * kStageFloats : nullptr;
     float px, py, pz, wx = 0.0f, wy = 0.0f, wz = 0.0f;
     if (io.rec) {
-        const f32x4 *r = reinterpret_cast<const f32x4 *>(io.rec + (size_t)(valid ? v : n - 1) * kRecFloats);
+        const f32x4 *r = reinterpret_cast<const f32x4 *>(io.rec + (size_t)(valid ? v : n - 1) * io.rec_stride);
         const f32x4 a = r[0], b = r[1];
         px = a[0]; py = a[1]; pz = a[2]; wx = a[3]; wy = b[0]; wz = b[1];
     } else {
@@ -214,6 +264,11 @@ __device__ __forceinline__ void query_tile(const GridView &gv, const void *img, 
     }
     float x[IN_P / 2];
     encode_tile<IN_P, F, BF>(gv, h, px, py, pz, x);
+    if constexpr (PG > 0) {
+        float a7[7];
+        load_aux(io.rec, io.rec_stride, io.aux, n, valid ? v : n - 1, vv, a7);
+        aux_fill<IN_P, ProductShape<PG>::GF, ProductShape<PG>::SHD>(h, a7, x);
+    }
     float o[16];
     mlp_forward<IN_P, HID_P, NH, BF, false>(img, x, nullptr, o, lane);
     Lobe L[4];
@@ -449,7 +504,9 @@ struct TrainIO {
     float *grad;      // flat gradient (grid part scattered here), or null: loss only
     float invN;
     const uint32_t *perm;   // visiting order of the vertices, or null: 0..n-1
-    const float *rec = nullptr;   // with perm: the inputs in visiting order (kRecFloats)
+    const float *rec = nullptr;   // with perm: the inputs in visiting order
+    const float *aux = nullptr;   // NPM-product inputs [7][n]
+    int rec_stride = 8;           // floats per record (16 with NPM-product)
 };
 
 // The vertex at position v of the visiting order.
@@ -481,7 +538,7 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
                                              int64_t n, int64_t t, int lane,
                                              float *__restrict__ grad, const float *lo,
                                              const float *hi, float *win,
-                                             const float *rec = nullptr)
+                                             const float *rec = nullptr, int rec_stride = 8)
 {
     constexpr int LPV = 8 * F;              // lanes per vertex-level
     constexpr int VPI = 64 / LPV;           // vertex-levels per instruction
@@ -492,7 +549,7 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
     for (int jj = 0; jj < 32 / VPI; ++jj) {
         const int64_t v = t * 32 + jj * VPI + q;
         if (rec) {
-            const f32x4 a = *reinterpret_cast<const f32x4 *>(rec + (size_t)(v < n ? v : n - 1) * kRecFloats);
+            const f32x4 a = *reinterpret_cast<const f32x4 *>(rec + (size_t)(v < n ? v : n - 1) * rec_stride);
             px[jj] = a[0]; py[jj] = a[1]; pz[jj] = a[2];
         } else {
             const int64_t vv = visit(perm, v < n ? v : n - 1);
@@ -588,7 +645,7 @@ __device__ __forceinline__ void tile_bbox(float px, float py, float pz, float *l
 // STORE_DG: the tile's dG is stored at dg_tiles + t * OUT0 * 32 (row r =
 // feature r, 32 vertices of the visiting order) for the aggregated scatter
 // kernel; otherwise it is scattered into the grid here.
-template <int IN_P, int HID_P, int NH, int F, bool BF, bool STORE_DG = false>
+template <int IN_P, int HID_P, int NH, int F, bool BF, bool STORE_DG = false, int PG = 0>
 __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fwd, const char *bwd,
                                               float *tbuf, const TrainIO &io, int64_t t, int lane,
                                               DwAcc<IN_P, HID_P, NH> &dw, double &lacc,
@@ -602,12 +659,12 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
     const int64_t v = t * 32 + (lane & 31);
     const bool valid = v < n;
     float px, py, pz, wx, wy, wz, rad, spdf;
+    const int64_t vv = visit(io.perm, valid ? v : n - 1);
     if (io.rec) {
-        const f32x4 *r = reinterpret_cast<const f32x4 *>(io.rec + (size_t)(valid ? v : n - 1) * kRecFloats);
+        const f32x4 *r = reinterpret_cast<const f32x4 *>(io.rec + (size_t)(valid ? v : n - 1) * io.rec_stride);
         const f32x4 a = r[0], b = r[1];
         px = a[0]; py = a[1]; pz = a[2]; wx = a[3]; wy = b[0]; wz = b[1]; rad = b[2]; spdf = b[3];
     } else {
-        const int64_t vv = visit(io.perm, valid ? v : n - 1);
         px = io.pos[vv]; py = io.pos[n + vv]; pz = io.pos[2 * n + vv];
         wx = io.dir[vv]; wy = io.dir[n + vv]; wz = io.dir[2 * n + vv];
         rad = io.rad[vv]; spdf = io.spdf[vv];
@@ -616,6 +673,11 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
     encode_tile<IN_P, F, BF>(gv, h, px, py, pz, x);
 #pragma unroll
     for (int i = IN_P / 2; i < IN0 / 2; ++i) x[i] = 0.0f;
+    if constexpr (PG > 0) {
+        float a7[7];
+        load_aux(io.rec, io.rec_stride, io.aux, n, valid ? v : n - 1, vv, a7);
+        aux_fill<IN_P, ProductShape<PG>::GF, ProductShape<PG>::SHD>(h, a7, x);
+    }
     float acts[NH][HID_P / 2];
     float o[16];
     mlp_forward<IN_P, HID_P, NH, BF, true>(fwd, x, acts, o, lane);
@@ -675,7 +737,7 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
         t32_to_lds<OUT0 / 2>(tbuf, dG, lane);
         wave_lds_fence();
         scatter_tile<F, WIN_PTS>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad, lo, hi,
-                                 tbuf + OUT0 * kStride, io.rec);
+                                 tbuf + OUT0 * kStride, io.rec, io.rec_stride);
     }
 }
 

@@ -40,9 +40,11 @@ struct FusedArgs {
     const uint32_t *perm;    // visiting order of the vertices (backward), or null
     float *dg_tiles;         // per-tile dG for the aggregated scatter (backward)
     float *qstage;           // staged query outputs in visiting order (with perm)
-    const float *rec;        // inputs in visiting order (with perm), kRecFloats each
+    const float *rec;        // inputs in visiting order (with perm), rec_stride floats each
+    const float *aux;        // NPM-product inputs [7][n]
+    int rec_stride;
 };
-template <int IN_P, int HID_P, int NH, int F, bool BF>
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_query_fused(FusedArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -57,16 +59,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     __syncthreads();
     const GridView gv = grid_view(a.g, s_off, s_res, a.grid32, a.grid16);
     const QueryIO io{a.n, a.pos, a.dir, a.lobes, a.pdf, a.sdir, a.spdf_out, a.seed, a.sid,
-                     a.perm, a.qstage, a.rec};
+                     a.perm, a.qstage, a.rec, a.aux, a.rec_stride};
     const int lane = threadIdx.x & 63;
     const int64_t ntiles = (a.n + 31) / 32;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     for (int64_t t = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6); t < ntiles;
          t += nwaves)
-        query_tile<IN_P, HID_P, NH, F, BF>(gv, smem, io, t, lane);
+        query_tile<IN_P, HID_P, NH, F, BF, PG>(gv, smem, io, t, lane);
 }
 
-template <int IN_P, int HID_P, int NH, int F, bool BF>
+// Rows of a wave's transpose buffer: the widest matrix side the weight
+// gradients transpose (hidden width, or a first-layer input wider than it).
+constexpr int trans_rows(int in_p, int hid_p)
+{
+    return (in_p < 32 ? 32 : in_p) > hid_p ? (in_p < 32 ? 32 : in_p) : hid_p;
+}
+
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG>
 __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_weights)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -80,12 +89,13 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     stage_levels(a.g, s_off, s_res);
     __syncthreads();
     const GridView gv = grid_view(a.g, s_off, s_res, a.grid32, a.grid16);
-    const TrainIO io{a.n, a.pos, a.dir, a.rad, a.spdf, a.grad, a.invN, a.perm, a.rec};
+    const TrainIO io{a.n, a.pos, a.dir, a.rad, a.spdf, a.grad, a.invN, a.perm, a.rec, a.aux,
+                     a.rec_stride};
     const char *fwd = smem;
     const char *bwd = smem + (size_t)a.fwd_elems * ESZ;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float *tbuf = reinterpret_cast<float *>(smem + (((size_t)img_bytes + 15) / 16) * 16) +
-                  wave * HID_P * kStride;
+                  wave * trans_rows(IN_P, HID_P) * kStride;
     DwAcc<IN_P, HID_P, NH> dw;
     dw.zero();
     double lacc = 0.0;
@@ -99,22 +109,21 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     const int64_t per = (ntiles + nwaves - 1) / nwaves;
     const int64_t t_end = (gwave + 1) * per < ntiles ? (gwave + 1) * per : ntiles;
     for (int64_t t = gwave * per; t < t_end; ++t)
-        backward_tile<IN_P, HID_P, NH, F, BF, true>(gv, fwd, bwd, tbuf, io, t, lane, dw, lacc,
-                                                    a.dg_tiles);
+        backward_tile<IN_P, HID_P, NH, F, BF, true, PG>(gv, fwd, bwd, tbuf, io, t, lane, dw,
+                                                        lacc, a.dg_tiles);
     // ---- loss partial of the block (FP64)
     red[threadIdx.x] = lacc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = (int)blockDim.x / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
     if (!a.grad) return;
-    // ---- the block's weight-gradient partial: the four waves add theirs in
-    // turn into LDS (the weight images are no longer needed), then one store
+    // ---- the block's weight-gradient partial: the waves add theirs in turn
+    // into LDS (the weight images are no longer needed), then one store
     float *acc = reinterpret_cast<float *>(smem);
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
         if (wave == w) {
             if (w == 0) dw_flush<IN_P, HID_P, NH, DW_STORE>(acc, a.n_in, a.width, dw, lane);
             else dw_flush<IN_P, HID_P, NH, DW_ADD>(acc, a.n_in, a.width, dw, lane);
@@ -140,6 +149,7 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
                                                        const float *__restrict__ pos,
                                                        const uint32_t *perm,
                                                        const float *__restrict__ rec,
+                                                       int rec_stride,
                                                        const float *__restrict__ dgt, int rows,
                                                        float *__restrict__ grad)
 {
@@ -162,7 +172,7 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
         const int64_t v = t * 32 + (lane & 31);
         float lo[3], hi[3];
         if (rec) {
-            const f32x4 a = *reinterpret_cast<const f32x4 *>(rec + (size_t)(v < n ? v : n - 1) * kRecFloats);
+            const f32x4 a = *reinterpret_cast<const f32x4 *>(rec + (size_t)(v < n ? v : n - 1) * rec_stride);
             tile_bbox(a[0], a[1], a[2], lo, hi);
         } else {
             const int64_t vv = visit(perm, v < n ? v : n - 1);
@@ -175,7 +185,7 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
         }
         wave_lds_fence();
         scatter_tile<F, WIN_PTS>(gv, tb, pos, perm, n, t, lane, grad, lo, hi, tb + 32 * kStride,
-                                 rec);
+                                 rec, rec_stride);
         wave_lds_fence();
     }
 }
@@ -242,16 +252,17 @@ static FusedArgs fused_args(npm_ctx *ctx, int64_t n, const float *pos)
     a.bwd_elems = (int)net.mlp.bwd_elems;
     a.n_in = net.mlp.n_in;
     a.width = net.mlp.width;
+    a.rec_stride = net.cfg.sh_degree ? 16 : 8;
     return a;
 }
 
-template <int IN_P, int HID_P, int NH, int F, bool BF>
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0>
 static hipError_t run_query(npm_ctx *ctx, FusedArgs a, hipStream_t s)
 {
     const int64_t tiles = (a.n + 31) / 32;
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2048));
     const size_t lds = (size_t)a.fwd_elems * (BF ? 2 : 4);
-    auto k = k_query_fused<IN_P, HID_P, NH, F, BF>;
+    auto k = k_query_fused<IN_P, HID_P, NH, F, BF, PG>;
     hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, s, a);
     return hipGetLastError();
@@ -264,17 +275,32 @@ static int backward_waves(int64_t n)
     return (int)std::max<int64_t>(4, std::min<int64_t>(((tiles + 3) / 4) * 4, 1024));
 }
 
-template <int IN_P, int HID_P, int NH, int F, bool BF>
+// Dynamic LDS a backward block may take: gfx950's 160 KB per workgroup less
+// room for the kernel's static arrays (level table, FP64 loss partials).
+constexpr size_t kLdsBytes = 160 * 1024 - 4096;
+
+// Waves per block of the backward kernel: four, or two when the weight images
+// and four waves' transpose buffers exceed the LDS (the FP32 images of a
+// 96-wide first layer).
+static int backward_wpb(const FusedArgs &a, int in_p, int hid_p, bool bf)
+{
+    const size_t img = ((size_t)(a.fwd_elems + a.bwd_elems) * (bf ? 2 : 4) + 15) / 16 * 16;
+    return img + (size_t)4 * trans_rows(in_p, hid_p) * kStride * sizeof(float) <= kLdsBytes ? 4 : 2;
+}
+
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0>
 static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
 {
     const int waves = backward_waves(a.n);
-    const int blocks = waves / 4;
+    const int wpb = backward_wpb(a, IN_P, HID_P, BF);
+    const int blocks = waves / wpb;
     const size_t img = ((size_t)(a.fwd_elems + a.bwd_elems) * (BF ? 2 : 4) + 15) / 16 * 16;
-    const size_t lds = img + (size_t)4 * HID_P * kStride * sizeof(float);
+    const size_t lds = img + (size_t)wpb * trans_rows(IN_P, HID_P) * kStride * sizeof(float);
     const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
-    auto k = k_backward_fused<IN_P, HID_P, NH, F, BF>;
+    if (lds > kLdsBytes || (size_t)count * sizeof(float) > lds) return hipErrorInvalidValue;
+    auto k = k_backward_fused<IN_P, HID_P, NH, F, BF, PG>;
     hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, s, a, count);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * wpb), lds, s, a, count);
     return hipGetLastError();
 }
 
@@ -299,12 +325,43 @@ static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
         }                                                                                         \
     } while (0)
 
-hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir, uint64_t seed,
-                       uint32_t stream_id, float *lobes, float *pdf, float *sdir, float *spdf,
-                       const uint32_t *perm, const uint32_t *inv, const float *rec, float *stage,
-                       hipStream_t s)
+// NPM-product shapes (sh_degree 4 on 32 grid features, 65 inputs in a 96-wide
+// first layer; sh_degree 2 on 4 grid features, 13 inputs).
+#define NPM_FUSED_PRODUCT_DISPATCH(RUN, BFV)                                                      \
+    do {                                                                                          \
+        const MlpDesc &m_ = ctx->net.mlp;                                                         \
+        const int F_ = ctx->net.grid.feat;                                                        \
+        const int key_ = m_.sh_degree * 100000 + F_ * 10000 + m_.in_p * 100 +                    \
+                         (m_.hid_p == 64) * 10 + m_.n_hidden;                                     \
+        switch (key_) {                                                                           \
+        case 429612: e = RUN<96, 64, 2, 2, BFV, 1>(ctx, a, s); break;                             \
+        case 429613: e = RUN<96, 64, 3, 2, BFV, 1>(ctx, a, s); break;                             \
+        case 449612: e = RUN<96, 64, 2, 4, BFV, 1>(ctx, a, s); break;                             \
+        case 449613: e = RUN<96, 64, 3, 4, BFV, 1>(ctx, a, s); break;                             \
+        case 221602: e = RUN<16, 32, 2, 2, BFV, 2>(ctx, a, s); break;                             \
+        default: return hipErrorNotSupported;                                                     \
+        }                                                                                         \
+    } while (0)
+
+#define NPM_FUSED_RUN(RUN)                                                                        \
+    do {                                                                                          \
+        const bool bf_ = ctx->net.cfg.precision == NPM_PREC_BF16;                                 \
+        if (ctx->net.mlp.sh_degree > 0) {                                                         \
+            if (bf_) NPM_FUSED_PRODUCT_DISPATCH(RUN, true);                                       \
+            else NPM_FUSED_PRODUCT_DISPATCH(RUN, false);                                          \
+        } else {                                                                                  \
+            if (bf_) NPM_FUSED_DISPATCH(RUN, true);                                               \
+            else NPM_FUSED_DISPATCH(RUN, false);                                                  \
+        }                                                                                         \
+    } while (0)
+
+hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                       const float *dir, uint64_t seed, uint32_t stream_id, float *lobes,
+                       float *pdf, float *sdir, float *spdf, const uint32_t *perm,
+                       const uint32_t *inv, const float *rec, float *stage, hipStream_t s)
 {
     FusedArgs a = fused_args(ctx, n, pos);
+    a.aux = aux;
     const Weights w = query_weights(ctx);
     a.grid32 = w.grid32;
     a.grid16 = (const __half *)w.grid16;
@@ -322,8 +379,7 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *d
     hipError_t e = hipSuccess;
     int tok;
     timed_begin(ctx, "fused_query", s, &tok);
-    if (ctx->net.cfg.precision == NPM_PREC_BF16) NPM_FUSED_DISPATCH(run_query, true);
-    else NPM_FUSED_DISPATCH(run_query, false);
+    NPM_FUSED_RUN(run_query);
     timed_end(ctx, tok, s);
     if (e != hipSuccess || !perm) return e;
     timed_begin(ctx, "query_unstage", s, &tok);
@@ -333,11 +389,13 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *d
     return hipGetLastError();
 }
 
-hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
-                          const float *rad, const float *spdf, float *grad, double *loss_out,
-                          const uint32_t *perm, const float *rec, float *dg_tiles, hipStream_t s)
+hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                          const float *dir, const float *rad, const float *spdf, float *grad,
+                          double *loss_out, const uint32_t *perm, const float *rec,
+                          float *dg_tiles, hipStream_t s)
 {
     FusedArgs a = fused_args(ctx, n, pos);
+    a.aux = aux;
     a.perm = perm;
     a.rec = perm ? rec : nullptr;
     a.dir = dir;
@@ -351,8 +409,7 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
     hipError_t e = hipSuccess;
     int tok;
     timed_begin(ctx, "fused_backward", s, &tok);
-    if (ctx->net.cfg.precision == NPM_PREC_BF16) NPM_FUSED_DISPATCH(run_backward, true);
-    else NPM_FUSED_DISPATCH(run_backward, false);
+    NPM_FUSED_RUN(run_backward);
     timed_end(ctx, tok, s);
     if (e != hipSuccess) return e;
     if (grad) {
@@ -362,27 +419,31 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
         timed_begin(ctx, "fused_scatter", s, &tok);
         switch (ctx->net.grid.feat) {
         case 1: hipLaunchKernelGGL(k_scatter_tiles<1>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                   ctx->net.grid, n, pos, perm, rec, dg_tiles, rows, grad); break;
+                                   ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
+                                   grad); break;
         case 2: hipLaunchKernelGGL(k_scatter_tiles<2>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                   ctx->net.grid, n, pos, perm, rec, dg_tiles, rows, grad); break;
+                                   ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
+                                   grad); break;
         default: hipLaunchKernelGGL(k_scatter_tiles<4>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                    ctx->net.grid, n, pos, perm, rec, dg_tiles, rows, grad); break;
+                                    ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
+                                   grad); break;
         }
         timed_end(ctx, tok, s);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const int waves = backward_waves(n);
+    const int blocks = backward_waves(n) / backward_wpb(a, ctx->net.mlp.in_p, ctx->net.mlp.hid_p,
+                                                        ctx->net.cfg.precision == NPM_PREC_BF16);
     if (grad) {
         const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
         timed_begin(ctx, "fused_dw_sum", s, &tok);
         hipLaunchKernelGGL(k_dw_sum, dim3((count + 63) / 64), dim3(256), 0, s, ctx->s_dw_part,
-                           waves / 4, count, grad + ctx->net.lay.grid_params);
+                           blocks, count, grad + ctx->net.lay.grid_params);
         timed_end(ctx, tok, s);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (loss_out) return launch_reduce_scaled(ctx->partials, waves / 4, 1.0 / (double)n, loss_out, s);
+    if (loss_out) return launch_reduce_scaled(ctx->partials, blocks, 1.0 / (double)n, loss_out, s);
     return hipSuccess;
 }
 

@@ -203,6 +203,7 @@ bool serve_supports(const npm_config *cfg)
     Net net;
     std::string err;
     if (describe(cfg, &net, &err) != NPM_OK) return false;
+    if (cfg->sh_degree != 0) return false;
     const int k = shape_key(net);
     return k == 2113 || k == 4012 || k == 2002 || k == 2112;
 }

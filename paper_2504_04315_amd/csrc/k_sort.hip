@@ -91,12 +91,14 @@ __global__ __launch_bounds__(1024) void k_sort_scan_add(uint32_t *__restrict__ c
 }
 
 // Places vertex v at its slot: perm[slot] = v, inv[v] = slot (optional), and
-// its inputs as one 32-byte record rec[slot] = (pos, dir, radiance, pdf), with
-// zeros for the arrays the call does not have.
-__global__ void k_sort_place(const float *__restrict__ pos, const float *__restrict__ dir,
-                             const float *__restrict__ rad, const float *__restrict__ spdf,
-                             int64_t n, uint32_t *__restrict__ off, uint32_t *__restrict__ perm,
-                             uint32_t *__restrict__ inv, float *__restrict__ rec)
+// its inputs as one record rec[slot] = (pos, dir, radiance, pdf), with zeros
+// for the arrays the call does not have; with the NPM-product inputs aux
+// [7][n] the record is 16 floats, followed by (omega_o, normal, roughness, 0).
+__global__ void k_sort_place(const float *__restrict__ pos, const float *__restrict__ aux,
+                             const float *__restrict__ dir, const float *__restrict__ rad,
+                             const float *__restrict__ spdf, int64_t n, uint32_t *__restrict__ off,
+                             uint32_t *__restrict__ perm, uint32_t *__restrict__ inv,
+                             float *__restrict__ rec)
 {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= n) return;
@@ -109,18 +111,25 @@ __global__ void k_sort_place(const float *__restrict__ pos, const float *__restr
         a[3] = dir ? dir[v] : 0.0f;
         b[0] = dir ? dir[n + v] : 0.0f; b[1] = dir ? dir[2 * n + v] : 0.0f;
         b[2] = rad ? rad[v] : 0.0f; b[3] = spdf ? spdf[v] : 0.0f;
-        f32x4 *r = reinterpret_cast<f32x4 *>(rec + (size_t)slot * 8);
+        f32x4 *r = reinterpret_cast<f32x4 *>(rec + (size_t)slot * (aux ? 16 : 8));
         r[0] = a;
         r[1] = b;
+        if (aux) {
+            f32x4 c, d;
+            c[0] = aux[v]; c[1] = aux[n + v]; c[2] = aux[2 * n + v]; c[3] = aux[3 * n + v];
+            d[0] = aux[4 * n + v]; d[1] = aux[5 * n + v]; d[2] = aux[6 * n + v]; d[3] = 0.0f;
+            r[2] = c;
+            r[3] = d;
+        }
     }
 }
 
 // cells: kSortCells counters followed by kScanBlocks block totals; inv
 // (optional) receives the inverse of perm, rec (optional) the inputs in
 // visiting order, 8 floats per slot
-hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
-                         const float *rad, const float *spdf, uint32_t *perm, uint32_t *inv,
-                         float *rec, uint32_t *cells, hipStream_t s)
+hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                         const float *dir, const float *rad, const float *spdf, uint32_t *perm,
+                         uint32_t *inv, float *rec, uint32_t *cells, hipStream_t s)
 {
     int tok;
     timed_begin(ctx, "spatial_sort", s, &tok);
@@ -131,8 +140,8 @@ hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float 
                        cells + kSortCells);
     hipLaunchKernelGGL(k_sort_scan_add, dim3(kScanBlocks), dim3(1024), 0, s, cells,
                        cells + kSortCells);
-    hipLaunchKernelGGL(k_sort_place, dim3(blocks), dim3(256), 0, s, pos, dir, rad, spdf, n, cells,
-                       perm, inv, rec);
+    hipLaunchKernelGGL(k_sort_place, dim3(blocks), dim3(256), 0, s, pos, aux, dir, rad, spdf, n,
+                       cells, perm, inv, rec);
     timed_end(ctx, tok, s);
     return hipGetLastError();
 }

@@ -77,8 +77,24 @@ __global__ __launch_bounds__(256) void k_encode(GridDesc g, int64_t n, const flo
     for (int f = 0; f < F; ++f) G[((int64_t)l * F + f) * n + v] = acc[f];
 }
 
+// NPM-product rows of the MLP input: G[gf + k][v] for the SH of omega_o
+// (d^2 values), of the normal (d^2), and the roughness; aux is [7][n].
+__global__ void k_aux_rows(int64_t n, int gf, int deg, const float *__restrict__ aux,
+                           float *__restrict__ G)
+{
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int nb = deg * deg;
+    float y[16];
+    sh_bands4(aux[v], aux[n + v], aux[2 * n + v], y);
+    for (int k = 0; k < nb; ++k) G[(int64_t)(gf + k) * n + v] = y[k];
+    sh_bands4(aux[3 * n + v], aux[4 * n + v], aux[5 * n + v], y);
+    for (int k = 0; k < nb; ++k) G[(int64_t)(gf + nb + k) * n + v] = y[k];
+    G[(int64_t)(gf + 2 * nb) * n + v] = aux[6 * n + v];
+}
+
 hipError_t staged_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, hipStream_t s,
-                         const Weights *w)
+                         const Weights *w, const float *aux)
 {
     const GridDesc &g = ctx->net.grid;
     const float *table = w ? w->grid32 : ctx->params;
@@ -91,6 +107,9 @@ hipError_t staged_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, hi
     case 4: hipLaunchKernelGGL(k_encode<4>, grid, dim3(256), 0, s, g, n, pos, table, G); break;
     default: return hipErrorInvalidValue;
     }
+    if (ctx->net.mlp.sh_degree > 0)
+        hipLaunchKernelGGL(k_aux_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                           ctx->net.mlp.gf, ctx->net.mlp.sh_degree, aux, G);
     timed_end(ctx, tok, s);
     return hipGetLastError();
 }
@@ -456,24 +475,40 @@ __global__ __launch_bounds__(256) void k_scatter(GridDesc g, int64_t n, const fl
 #define NPM_MLP_DISPATCH(KERNEL, ...)                                                             \
     do {                                                                                          \
         const MlpDesc &m_ = ctx->net.mlp;                                                         \
-        const int key_ = (m_.in_p == 32) * 100 + (m_.hid_p == 64) * 10 + m_.n_hidden;            \
+        const int key_ = (m_.in_p / 16) * 100 + (m_.hid_p == 64) * 10 + m_.n_hidden;              \
         switch (key_) {                                                                           \
-        case 1: KERNEL<16, 32, 1> __VA_ARGS__; break;                                             \
-        case 2: KERNEL<16, 32, 2> __VA_ARGS__; break;                                             \
-        case 3: KERNEL<16, 32, 3> __VA_ARGS__; break;                                             \
-        case 4: KERNEL<16, 32, 4> __VA_ARGS__; break;                                             \
-        case 11: KERNEL<16, 64, 1> __VA_ARGS__; break;                                            \
-        case 12: KERNEL<16, 64, 2> __VA_ARGS__; break;                                            \
-        case 13: KERNEL<16, 64, 3> __VA_ARGS__; break;                                            \
-        case 14: KERNEL<16, 64, 4> __VA_ARGS__; break;                                            \
-        case 101: KERNEL<32, 32, 1> __VA_ARGS__; break;                                           \
-        case 102: KERNEL<32, 32, 2> __VA_ARGS__; break;                                           \
-        case 103: KERNEL<32, 32, 3> __VA_ARGS__; break;                                           \
-        case 104: KERNEL<32, 32, 4> __VA_ARGS__; break;                                           \
-        case 111: KERNEL<32, 64, 1> __VA_ARGS__; break;                                           \
-        case 112: KERNEL<32, 64, 2> __VA_ARGS__; break;                                           \
-        case 113: KERNEL<32, 64, 3> __VA_ARGS__; break;                                           \
-        case 114: KERNEL<32, 64, 4> __VA_ARGS__; break;                                           \
+        case 101: KERNEL<16, 32, 1> __VA_ARGS__; break;                                               \
+        case 102: KERNEL<16, 32, 2> __VA_ARGS__; break;                                               \
+        case 103: KERNEL<16, 32, 3> __VA_ARGS__; break;                                               \
+        case 104: KERNEL<16, 32, 4> __VA_ARGS__; break;                                               \
+        case 111: KERNEL<16, 64, 1> __VA_ARGS__; break;                                               \
+        case 112: KERNEL<16, 64, 2> __VA_ARGS__; break;                                               \
+        case 113: KERNEL<16, 64, 3> __VA_ARGS__; break;                                               \
+        case 114: KERNEL<16, 64, 4> __VA_ARGS__; break;                                               \
+        case 201: KERNEL<32, 32, 1> __VA_ARGS__; break;                                               \
+        case 202: KERNEL<32, 32, 2> __VA_ARGS__; break;                                               \
+        case 203: KERNEL<32, 32, 3> __VA_ARGS__; break;                                               \
+        case 204: KERNEL<32, 32, 4> __VA_ARGS__; break;                                               \
+        case 211: KERNEL<32, 64, 1> __VA_ARGS__; break;                                               \
+        case 212: KERNEL<32, 64, 2> __VA_ARGS__; break;                                               \
+        case 213: KERNEL<32, 64, 3> __VA_ARGS__; break;                                               \
+        case 214: KERNEL<32, 64, 4> __VA_ARGS__; break;                                               \
+        case 401: KERNEL<64, 32, 1> __VA_ARGS__; break;                                               \
+        case 402: KERNEL<64, 32, 2> __VA_ARGS__; break;                                               \
+        case 403: KERNEL<64, 32, 3> __VA_ARGS__; break;                                               \
+        case 404: KERNEL<64, 32, 4> __VA_ARGS__; break;                                               \
+        case 411: KERNEL<64, 64, 1> __VA_ARGS__; break;                                               \
+        case 412: KERNEL<64, 64, 2> __VA_ARGS__; break;                                               \
+        case 413: KERNEL<64, 64, 3> __VA_ARGS__; break;                                               \
+        case 414: KERNEL<64, 64, 4> __VA_ARGS__; break;                                               \
+        case 601: KERNEL<96, 32, 1> __VA_ARGS__; break;                                               \
+        case 602: KERNEL<96, 32, 2> __VA_ARGS__; break;                                               \
+        case 603: KERNEL<96, 32, 3> __VA_ARGS__; break;                                               \
+        case 604: KERNEL<96, 32, 4> __VA_ARGS__; break;                                               \
+        case 611: KERNEL<96, 64, 1> __VA_ARGS__; break;                                               \
+        case 612: KERNEL<96, 64, 2> __VA_ARGS__; break;                                               \
+        case 613: KERNEL<96, 64, 3> __VA_ARGS__; break;                                               \
+        case 614: KERNEL<96, 64, 4> __VA_ARGS__; break;                                               \
         default: return hipErrorInvalidValue;                                                     \
         }                                                                                         \
     } while (0)
@@ -553,12 +588,14 @@ hipError_t staged_mlp_dw(npm_ctx *ctx, int64_t n, const float *G, const float *a
         const float *dz = (i == L.n_layers - 1) ? draw : delta + (int64_t)i * m.width * n;
         const float *x = (i == 0) ? G : acts + (int64_t)(i - 1) * m.width * n;
         const int out_p = (i == L.n_layers - 1) ? 32 : m.hid_p;
-        const int in_p = (i == 0) ? 32 : m.hid_p;   // inputs padded to one 32 block at least
+        const int in_p = (i == 0) ? std::max(m.in_p, 32) : m.hid_p;   // at least one 32 block
         float *part = ctx->s_dw_part;
 #define NPM_DW(OP, IP) hipLaunchKernelGGL((k_dw<OP, IP>), dim3(blocks), dim3(256), 0, s, n, out_r, in_r, dz, x, part)
         if (out_p == 32 && in_p == 32) NPM_DW(32, 32);
         else if (out_p == 32 && in_p == 64) NPM_DW(32, 64);
+        else if (out_p == 32 && in_p == 96) NPM_DW(32, 96);
         else if (out_p == 64 && in_p == 32) NPM_DW(64, 32);
+        else if (out_p == 64 && in_p == 96) NPM_DW(64, 96);
         else NPM_DW(64, 64);
 #undef NPM_DW
         const int count = out_r * in_r;

@@ -30,7 +30,9 @@ struct GridDesc {
 // MLP shape as the kernels see it: widths padded to MFMA tiles.
 struct MlpDesc {
     int n_in, width, n_hidden;        // real sizes
-    int in_p, hid_p;                  // padded: in_p in {16, 32}, hid_p in {32, 64}
+    int in_p, hid_p;                  // padded: in_p in {16, 32, 64, 96}, hid_p in {32, 64}
+    int gf;                           // grid features (n_levels * feat), the first inputs
+    int sh_degree;                    // NPM-product: SH bands of omega_o and the normal
     int64_t fwd_off[NPM_MAX_LAYERS];  // offset of each layer's image in the packed
     int64_t bwd_off[NPM_MAX_LAYERS];  //   forward / backward weight images (elements)
     int64_t fwd_elems, bwd_elems;
@@ -148,8 +150,9 @@ hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 hipError_t staged_corner_index(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *idx,
                                hipStream_t s);
 // w: the weights to evaluate (the trained ones by default)
+// aux: the NPM-product inputs [7][n] (required when the network takes them)
 hipError_t staged_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, hipStream_t s,
-                         const Weights *w = nullptr);
+                         const Weights *w = nullptr, const float *aux = nullptr);
 hipError_t staged_mlp_fwd(npm_ctx *ctx, int64_t n, const float *G, float *acts, float *raw,
                           hipStream_t s, const Weights *w = nullptr);
 hipError_t staged_head(npm_ctx *ctx, int64_t n, const float *raw, const float *dir,
@@ -166,9 +169,9 @@ hipError_t staged_scatter(npm_ctx *ctx, int64_t n, const float *pos, const float
                           float *grad, hipStream_t s);
 
 // spatial order of a batch (k_sort.hip): perm lists the vertices by cell
-hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
-                         const float *rad, const float *spdf, uint32_t *perm, uint32_t *inv,
-                         float *rec, uint32_t *cells, hipStream_t s);
+hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                         const float *dir, const float *rad, const float *spdf, uint32_t *perm,
+                         uint32_t *inv, float *rec, uint32_t *cells, hipStream_t s);
 // Smallest batch NPM_ORDER_AUTO sorts.  On the 16-level hash grid at 2^20
 // vertices the sort (0.22 ms) halves the scatter's line requests through the
 // LDS window (4.43 -> 2.42 ms) and speeds the tile kernel's gathers (1.61 ->
@@ -179,15 +182,15 @@ constexpr int64_t kSortMinBatch = 1 << 15;
 // fused path (k_fused.hip)
 // perm/inv (optional): visiting order and its inverse; the outputs then go
 // through `stage` (n slots of 40 floats) and an un-permuting pass
-hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
-                       uint64_t seed, uint32_t stream_id, float *lobes, float *pdf, float *sdir,
-                       float *spdf, const uint32_t *perm, const uint32_t *inv, const float *rec,
-                       float *stage, hipStream_t s);
+hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                       const float *dir, uint64_t seed, uint32_t stream_id, float *lobes,
+                       float *pdf, float *sdir, float *spdf, const uint32_t *perm,
+                       const uint32_t *inv, const float *rec, float *stage, hipStream_t s);
 // perm (optional): the order in which to visit the vertices; dg_tiles: the
 // per-tile dG buffer (required when grad is set)
-hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
-                          const float *rad, const float *spdf, float *grad, double *loss_out,
-                          const uint32_t *perm, const float *rec, float *dg_tiles,
-                          hipStream_t s);
+hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                          const float *dir, const float *rad, const float *spdf, float *grad,
+                          double *loss_out, const uint32_t *perm, const float *rec,
+                          float *dg_tiles, hipStream_t s);
 
 }  // namespace npm

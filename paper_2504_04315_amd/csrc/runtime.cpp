@@ -75,6 +75,12 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
         return bad("betas must be in [0, 1)");
     if (!(std::isfinite(c.eps) && c.eps > 0.0f)) return bad("eps must be > 0");
     if (!(c.ema_decay >= 0.0f && c.ema_decay < 1.0f)) return bad("ema_decay must be in [0, 1)");
+    if (c.sh_degree < 0 || c.sh_degree > 4) return bad("sh_degree must be 0..4");
+    if (c.sh_degree > 0 && c.exec_mode == NPM_EXEC_FUSED &&
+        !((c.sh_degree == 4 && c.n_levels * c.feat_per_level == 32) ||
+          (c.sh_degree == 2 && c.n_levels * c.feat_per_level == 4)))
+        return bad("fused NPM-product: sh_degree 4 with 32 grid features or 2 with 4; "
+                   "the staged path takes other shapes");
 
     Net n{};
     n.cfg = c;
@@ -101,7 +107,8 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     }
     L.grid_entries = entries;
     L.grid_params = entries * c.feat_per_level;
-    L.n_in = nl * c.feat_per_level;
+    const int n_aux = c.sh_degree ? 2 * c.sh_degree * c.sh_degree + 1 : 0;
+    L.n_in = nl * c.feat_per_level + n_aux;
     L.n_out = 4 * kLobes;
     L.n_layers = c.mlp_hidden_layers + 1;
     int64_t off = L.grid_params;
@@ -127,7 +134,9 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     m.n_in = L.n_in;
     m.width = c.mlp_width;
     m.n_hidden = c.mlp_hidden_layers;
-    m.in_p = L.n_in <= 16 ? 16 : 32;
+    m.in_p = L.n_in <= 16 ? 16 : L.n_in <= 32 ? 32 : L.n_in <= 64 ? 64 : 96;
+    m.gf = nl * c.feat_per_level;
+    m.sh_degree = c.sh_degree;
     m.hid_p = c.mlp_width <= 32 ? 32 : 64;
     int64_t fo = 0;
     for (int i = 0; i < L.n_layers; ++i) {
@@ -326,6 +335,19 @@ static npm_status check_batch(npm_ctx *ctx, int64_t n, const float *pos)
     return NPM_OK;
 }
 
+// The NPM-product inputs: required exactly when the network takes them.
+static npm_status check_aux(npm_ctx *ctx, int64_t n, const float *aux)
+{
+    if (ctx->net.cfg.sh_degree > 0) {
+        if (n > 0 && (!aux || !aligned4(aux)))
+            return fail(NPM_ERR_INVALID_ARG, "this network takes omega_o, normal and roughness: "
+                                             "use the *_aux calls with aux [7][n]");
+    } else if (aux) {
+        return fail(NPM_ERR_INVALID_ARG, "aux inputs given to a radiance-based network");
+    }
+    return NPM_OK;
+}
+
 static bool use_order(const npm_ctx *ctx, int64_t n);
 static hipError_t ensure_sort(npm_ctx *ctx, int64_t n);
 static hipError_t ensure_qstage(npm_ctx *ctx, int64_t n);
@@ -334,8 +356,17 @@ npm_status npm_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir
                      uint64_t rng_seed, uint32_t rng_stream, float *lobes, float *pdf,
                      float *sample_dir, float *sample_pdf, void *stream)
 {
+    return npm_query_aux(ctx, n, pos, nullptr, dir, rng_seed, rng_stream, lobes, pdf, sample_dir,
+                         sample_pdf, stream);
+}
+
+npm_status npm_query_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                         const float *dir, uint64_t rng_seed, uint32_t rng_stream, float *lobes,
+                         float *pdf, float *sample_dir, float *sample_pdf, void *stream)
+{
     npm_status st = check_batch(ctx, n, pos);
     if (st != NPM_OK) return st;
+    if ((st = check_aux(ctx, n, aux)) != NPM_OK) return st;
     if (pdf && !dir) return fail(NPM_ERR_INVALID_ARG, "pdf needs dir");
     for (const void *p : {(const void *)dir, (const void *)lobes, (const void *)pdf,
                           (const void *)sample_dir, (const void *)sample_pdf})
@@ -348,18 +379,18 @@ npm_status npm_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir
             if (use_order(ctx, n) && (lobes || pdf || sample_dir || sample_pdf)) {
                 NPM_HIP(ensure_sort(ctx, n), "order scratch allocation");
                 NPM_HIP(ensure_qstage(ctx, n), "query staging allocation");
-                NPM_HIP(spatial_order(ctx, n, pos, dir, nullptr, nullptr, ctx->s_perm, ctx->s_inv,
-                                      ctx->s_rec, ctx->s_cells, s), "spatial order");
+                NPM_HIP(spatial_order(ctx, n, pos, aux, dir, nullptr, nullptr, ctx->s_perm,
+                                      ctx->s_inv, ctx->s_rec, ctx->s_cells, s), "spatial order");
                 perm = ctx->s_perm;
             }
-            NPM_HIP(fused_query(ctx, n, pos, dir, rng_seed, rng_stream, lobes, pdf, sample_dir,
-                                sample_pdf, perm, ctx->s_inv, ctx->s_rec, ctx->s_qstage, s),
-                    "fused query");
+            NPM_HIP(fused_query(ctx, n, pos, aux, dir, rng_seed, rng_stream, lobes, pdf,
+                                sample_dir, sample_pdf, perm, ctx->s_inv, ctx->s_rec,
+                                ctx->s_qstage, s), "fused query");
             return NPM_OK;
         }
         NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
         const Weights w = query_weights(ctx);
-        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w), "encode");
+        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w, aux), "encode");
         NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s, &w), "mlp forward");
         if (lobes || pdf || sample_dir || sample_pdf)
             NPM_HIP(staged_head(ctx, n, ctx->s_raw, dir, rng_seed, rng_stream, lobes, pdf,
@@ -418,7 +449,8 @@ static hipError_t ensure_sort(npm_ctx *ctx, int64_t n)
     ctx->sort_n = 0;
     e = hipMalloc((void **)&ctx->s_perm, (size_t)n * 4);
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->s_inv, (size_t)n * 4);
-    if (e == hipSuccess) e = hipMalloc((void **)&ctx->s_rec, (size_t)n * 32);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&ctx->s_rec, (size_t)n * (ctx->net.cfg.sh_degree ? 64 : 32));
     if (e == hipSuccess && !ctx->s_cells)
         e = hipMalloc((void **)&ctx->s_cells, ((size_t)1 << 18) * 4 + 256 * 4);  // counts, block totals
     if (e != hipSuccess) return e;
@@ -442,26 +474,26 @@ static hipError_t ensure_dgt(npm_ctx *ctx, int64_t n)
     return hipSuccess;
 }
 
-static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
-                                const float *rad, const float *spdf, float *grad, double *loss_out,
-                                hipStream_t s)
+static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                                const float *dir, const float *rad, const float *spdf, float *grad,
+                                double *loss_out, hipStream_t s)
 {
     if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
         const uint32_t *perm = nullptr;
         if (grad && use_order(ctx, n)) {
             NPM_HIP(ensure_sort(ctx, n), "order scratch allocation");
-            NPM_HIP(spatial_order(ctx, n, pos, dir, rad, spdf, ctx->s_perm, nullptr, ctx->s_rec,
-                                  ctx->s_cells, s), "spatial order");
+            NPM_HIP(spatial_order(ctx, n, pos, aux, dir, rad, spdf, ctx->s_perm, nullptr,
+                                  ctx->s_rec, ctx->s_cells, s), "spatial order");
             perm = ctx->s_perm;
         }
         if (grad) NPM_HIP(ensure_dgt(ctx, n), "dG scratch allocation");
-        NPM_HIP(fused_backward(ctx, n, pos, dir, rad, spdf, grad, loss_out, perm,
+        NPM_HIP(fused_backward(ctx, n, pos, aux, dir, rad, spdf, grad, loss_out, perm,
                                perm ? ctx->s_rec : nullptr, grad ? ctx->s_dgt : nullptr, s),
                 "fused backward");
         return NPM_OK;
     }
     NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
-    NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");
+    NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, nullptr, aux), "encode");
     NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, ctx->s_acts, ctx->s_raw, s), "mlp forward");
     NPM_HIP(staged_loss_grad(ctx, n, ctx->s_raw, dir, rad, spdf, ctx->s_draw, loss_out, s),
             "loss gradient");
@@ -477,12 +509,21 @@ npm_status npm_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *
                         const float *radiance, const float *sampling_pdf, float *grad_out,
                         double *loss_out, void *stream)
 {
+    return npm_backward_aux(ctx, n, pos, nullptr, dir, radiance, sampling_pdf, grad_out, loss_out,
+                            stream);
+}
+
+npm_status npm_backward_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                            const float *dir, const float *radiance, const float *sampling_pdf,
+                            float *grad_out, double *loss_out, void *stream)
+{
     npm_status st = check_train(ctx, n, pos, dir, radiance, sampling_pdf);
     if (st != NPM_OK) return st;
+    if ((st = check_aux(ctx, n, aux)) != NPM_OK) return st;
     if (grad_out && !aligned4(grad_out)) return fail(NPM_ERR_INVALID_ARG, "misaligned grad_out");
     if (n == 0) return NPM_OK;
     try {
-        return backward_impl(ctx, n, pos, dir, radiance, sampling_pdf,
+        return backward_impl(ctx, n, pos, aux, dir, radiance, sampling_pdf,
                              grad_out ? grad_out : ctx->grads, loss_out, (hipStream_t)stream);
     } catch (...) {
         return fail(NPM_ERR_HIP, "unexpected exception");
@@ -493,19 +534,27 @@ npm_status npm_loss(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
                     const float *radiance, const float *sampling_pdf, double *loss_out,
                     void *stream)
 {
+    return npm_loss_aux(ctx, n, pos, nullptr, dir, radiance, sampling_pdf, loss_out, stream);
+}
+
+npm_status npm_loss_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                        const float *dir, const float *radiance, const float *sampling_pdf,
+                        double *loss_out, void *stream)
+{
     npm_status st = check_train(ctx, n, pos, dir, radiance, sampling_pdf);
     if (st != NPM_OK) return st;
+    if ((st = check_aux(ctx, n, aux)) != NPM_OK) return st;
     if (n == 0) return NPM_OK;
     hipStream_t s = (hipStream_t)stream;
     try {
         NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
         if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED && ctx->net.cfg.precision == NPM_PREC_BF16) {
             // the loss of the precision form: the fused kernel with no gradient output
-            NPM_HIP(fused_backward(ctx, n, pos, dir, radiance, sampling_pdf, nullptr, loss_out,
-                                   nullptr, nullptr, nullptr, s), "fused loss");
+            NPM_HIP(fused_backward(ctx, n, pos, aux, dir, radiance, sampling_pdf, nullptr,
+                                   loss_out, nullptr, nullptr, nullptr, s), "fused loss");
             return NPM_OK;
         }
-        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s), "encode");
+        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, nullptr, aux), "encode");
         NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s), "mlp forward");
         NPM_HIP(staged_loss_grad(ctx, n, ctx->s_raw, dir, radiance, sampling_pdf, ctx->s_draw,
                                  loss_out, s), "loss");
@@ -532,11 +581,20 @@ npm_status npm_train_step(npm_ctx *ctx, int64_t n, const float *pos, const float
                           const float *radiance, const float *sampling_pdf, double *stats_out,
                           void *stream)
 {
+    return npm_train_step_aux(ctx, n, pos, nullptr, dir, radiance, sampling_pdf, stats_out,
+                              stream);
+}
+
+npm_status npm_train_step_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                              const float *dir, const float *radiance, const float *sampling_pdf,
+                              double *stats_out, void *stream)
+{
     npm_status st = check_train(ctx, n, pos, dir, radiance, sampling_pdf);
     if (st != NPM_OK) return st;
+    if ((st = check_aux(ctx, n, aux)) != NPM_OK) return st;
     if (n > 0) {
         try {
-            st = backward_impl(ctx, n, pos, dir, radiance, sampling_pdf, ctx->grads,
+            st = backward_impl(ctx, n, pos, aux, dir, radiance, sampling_pdf, ctx->grads,
                                stats_out, (hipStream_t)stream);
         } catch (...) {
             return fail(NPM_ERR_HIP, "unexpected exception");
@@ -558,25 +616,39 @@ npm_status npm_corner_index(npm_ctx *ctx, int64_t n, const float *pos, uint32_t 
 
 npm_status npm_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, void *stream)
 {
+    return npm_encode_aux(ctx, n, pos, nullptr, G, stream);
+}
+
+npm_status npm_encode_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux, float *G,
+                          void *stream)
+{
     npm_status st = check_batch(ctx, n, pos);
     if (st != NPM_OK) return st;
+    if ((st = check_aux(ctx, n, aux)) != NPM_OK) return st;
     if (n > 0 && (!G || !aligned4(G))) return fail(NPM_ERR_INVALID_ARG, "G required");
     if (n == 0) return NPM_OK;
     const Weights w = query_weights(ctx);
-    NPM_HIP(staged_encode(ctx, n, pos, G, (hipStream_t)stream, &w), "encode");
+    NPM_HIP(staged_encode(ctx, n, pos, G, (hipStream_t)stream, &w, aux), "encode");
     return NPM_OK;
 }
 
 npm_status npm_forward_raw(npm_ctx *ctx, int64_t n, const float *pos, float *raw, void *stream)
 {
+    return npm_forward_raw_aux(ctx, n, pos, nullptr, raw, stream);
+}
+
+npm_status npm_forward_raw_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                               float *raw, void *stream)
+{
     npm_status st = check_batch(ctx, n, pos);
     if (st != NPM_OK) return st;
+    if ((st = check_aux(ctx, n, aux)) != NPM_OK) return st;
     if (n > 0 && (!raw || !aligned4(raw))) return fail(NPM_ERR_INVALID_ARG, "raw required");
     if (n == 0) return NPM_OK;
     hipStream_t s = (hipStream_t)stream;
     NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
     const Weights w = query_weights(ctx);
-    NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w), "encode");
+    NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w, aux), "encode");
     NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, raw, s, &w), "mlp forward");
     return NPM_OK;
 }

@@ -33,7 +33,8 @@ class npm_config(C.Structure):
         ("mlp_hidden_layers", C.c_int32), ("n_lobes", C.c_int32), ("precision", C.c_int32),
         ("exec_mode", C.c_int32), ("grid_init", C.c_int32), ("grid_init_scale", C.c_float),
         ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-        ("batch_order", C.c_int32), ("ema_decay", C.c_float), ("seed", C.c_uint64),
+        ("batch_order", C.c_int32), ("ema_decay", C.c_float), ("sh_degree", C.c_int32),
+        ("reserved", C.c_int32), ("seed", C.c_uint64),
     ]
 
 
@@ -75,6 +76,12 @@ SIGNATURES = {
     "npm_set_timing": [_P, _i32],
     "npm_kernel_times": [_P, _P, C.c_int32, _P],
     "npm_reset_timing": [_P],
+    "npm_query_aux": [_P, _i64, _P, _P, _P, _u64, _u32, _P, _P, _P, _P, _P],
+    "npm_backward_aux": [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _P],
+    "npm_loss_aux": [_P, _i64, _P, _P, _P, _P, _P, _P, _P],
+    "npm_train_step_aux": [_P, _i64, _P, _P, _P, _P, _P, _P, _P],
+    "npm_encode_aux": [_P, _i64, _P, _P, _P, _P],
+    "npm_forward_raw_aux": [_P, _i64, _P, _P, _P, _P],
 }
 
 _lib = None
@@ -113,7 +120,7 @@ def check(status):
 
 
 def make_config(net, exec_mode=EXEC_STAGED, precision=None, lr=None, seed=None,
-                batch_order=ORDER_AUTO, ema_decay=0.0):
+                batch_order=ORDER_AUTO, ema_decay=0.0, sh_degree=None):
     """npm_config from a workload.NetConfig (sizes of a workload)."""
     c = npm_config()
     check(lib().npm_config_default(C.byref(c)))
@@ -132,6 +139,7 @@ def make_config(net, exec_mode=EXEC_STAGED, precision=None, lr=None, seed=None,
     c.seed = net.seed if seed is None else seed
     c.batch_order = batch_order
     c.ema_decay = ema_decay
+    c.sh_degree = getattr(net, "sh_degree", 0) if sh_degree is None else sh_degree
     return c
 
 
@@ -188,8 +196,9 @@ class NPM:
 
     # -- hot path
     def query(self, pos, dir=None, seed=0, stream_id=0, lobes=True, pdf=None, sample=True,
-              stream=None):
-        """Returns dict with lobes [4][8][n], pdf [n], sample_dir [3][n], sample_pdf [n]."""
+              stream=None, aux=None):
+        """Returns dict with lobes [4][8][n], pdf [n], sample_dir [3][n], sample_pdf [n].
+        aux: the NPM-product inputs [7][n] (omega_o, normal, roughness)."""
         import torch
         n = pos.shape[1]
         dev = pos.device
@@ -199,28 +208,29 @@ class NPM:
         out["pdf"] = torch.empty(n, device=dev) if want_pdf else None
         out["sample_dir"] = torch.empty((3, n), device=dev) if sample else None
         out["sample_pdf"] = torch.empty(n, device=dev) if sample else None
-        check(lib().npm_query(self._ctx, n, _ptr(pos), _ptr(dir), seed, stream_id,
-                              _ptr(out["lobes"]), _ptr(out["pdf"]), _ptr(out["sample_dir"]),
-                              _ptr(out["sample_pdf"]), _stream(stream)))
+        check(lib().npm_query_aux(self._ctx, n, _ptr(pos), _ptr(aux), _ptr(dir), seed, stream_id,
+                                  _ptr(out["lobes"]), _ptr(out["pdf"]), _ptr(out["sample_dir"]),
+                                  _ptr(out["sample_pdf"]), _stream(stream)))
         return out
 
-    def backward(self, pos, dir, radiance, pdf, grad=None, loss=None, stream=None):
-        check(lib().npm_backward(self._ctx, pos.shape[1], _ptr(pos), _ptr(dir), _ptr(radiance),
-                                 _ptr(pdf), _ptr(grad), _ptr(loss), _stream(stream)))
+    def backward(self, pos, dir, radiance, pdf, grad=None, loss=None, stream=None, aux=None):
+        check(lib().npm_backward_aux(self._ctx, pos.shape[1], _ptr(pos), _ptr(aux), _ptr(dir),
+                                     _ptr(radiance), _ptr(pdf), _ptr(grad), _ptr(loss),
+                                     _stream(stream)))
 
-    def loss(self, pos, dir, radiance, pdf, out=None, stream=None):
+    def loss(self, pos, dir, radiance, pdf, out=None, stream=None, aux=None):
         import torch
         out = torch.zeros(1, dtype=torch.float64, device=pos.device) if out is None else out
-        check(lib().npm_loss(self._ctx, pos.shape[1], _ptr(pos), _ptr(dir), _ptr(radiance),
-                             _ptr(pdf), _ptr(out), _stream(stream)))
+        check(lib().npm_loss_aux(self._ctx, pos.shape[1], _ptr(pos), _ptr(aux), _ptr(dir),
+                                 _ptr(radiance), _ptr(pdf), _ptr(out), _stream(stream)))
         return out
 
     def optimizer_step(self, grad=None, gradnorm=None, stream=None):
         check(lib().npm_optimizer_step(self._ctx, _ptr(grad), _ptr(gradnorm), _stream(stream)))
 
-    def train_step(self, pos, dir, radiance, pdf, stats=None, stream=None):
-        check(lib().npm_train_step(self._ctx, pos.shape[1], _ptr(pos), _ptr(dir),
-                                   _ptr(radiance), _ptr(pdf), _ptr(stats), _stream(stream)))
+    def train_step(self, pos, dir, radiance, pdf, stats=None, stream=None, aux=None):
+        check(lib().npm_train_step_aux(self._ctx, pos.shape[1], _ptr(pos), _ptr(aux), _ptr(dir),
+                                       _ptr(radiance), _ptr(pdf), _ptr(stats), _stream(stream)))
 
     # -- stage outputs
     def corner_index(self, pos, stream=None):
@@ -230,18 +240,19 @@ class NPM:
         check(lib().npm_corner_index(self._ctx, n, _ptr(pos), _ptr(idx), _stream(stream)))
         return idx
 
-    def encode(self, pos, stream=None):
+    def encode(self, pos, stream=None, aux=None):
         import torch
         n = pos.shape[1]
         G = torch.empty((self.layout.n_in, n), device=pos.device)
-        check(lib().npm_encode(self._ctx, n, _ptr(pos), _ptr(G), _stream(stream)))
+        check(lib().npm_encode_aux(self._ctx, n, _ptr(pos), _ptr(aux), _ptr(G), _stream(stream)))
         return G
 
-    def forward_raw(self, pos, stream=None):
+    def forward_raw(self, pos, stream=None, aux=None):
         import torch
         n = pos.shape[1]
         raw = torch.empty((32, n), device=pos.device)
-        check(lib().npm_forward_raw(self._ctx, n, _ptr(pos), _ptr(raw), _stream(stream)))
+        check(lib().npm_forward_raw_aux(self._ctx, n, _ptr(pos), _ptr(aux), _ptr(raw),
+                                        _stream(stream)))
         return raw
 
     # -- state

@@ -47,6 +47,7 @@ class NetConfig:
     grid_init_scale: float = 1e-4
     precision: str = "fp32"      # "fp32" or "bf16" (BF16 MLP + FP16 grid)
     seed: int = 1
+    sh_degree: int = 0           # NPM-product: SH bands of omega_o and the normal
 
     @property
     def n_in(self):
@@ -75,6 +76,12 @@ TINY = NetConfig(n_levels=2, feat=2, base_res=4, max_res=16, log2_table=8, dense
 PAPER = NetConfig(n_levels=8, feat=4, base_res=8, max_res=86, log2_table=19, dense_only=True,
                   n_hidden=2, width=64, lr=5e-3, grid_init="uniform", grid_init_scale=1e-4,
                   seed=6)
+
+# NPM-product (Sec. 4.3) forms: omega_o, normal and roughness after G(x), four
+# SH bands each (65 inputs on the 32 grid features); two bands on TINY.
+CFG2P = replace(CFG2, sh_degree=4, seed=8)
+PAPERP = replace(PAPER, sh_degree=4, seed=9)
+TINYP = replace(TINY, sh_degree=2, seed=10)
 
 N_CFG1 = 16384
 N_CFG2 = 1 << 20
@@ -165,7 +172,7 @@ def triangle_soup(rng, n_tri=4096):
     return c + rng.uniform(-0.08, 0.08, size=(n_tri, 3, 3))
 
 
-def surface_points(rng, n, tris):
+def surface_points(rng, n, tris, return_tri=False):
     e1 = tris[:, 1] - tris[:, 0]
     e2 = tris[:, 2] - tris[:, 0]
     area = 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1)
@@ -173,7 +180,13 @@ def surface_points(rng, n, tris):
     r1 = np.sqrt(rng.random(n))[:, None]
     r2 = rng.random(n)[:, None]
     # uniform barycentrics (Osada et al. 2002)
-    return (1 - r1) * tris[t, 0] + r1 * (1 - r2) * tris[t, 1] + r1 * r2 * tris[t, 2]
+    x = (1 - r1) * tris[t, 0] + r1 * (1 - r2) * tris[t, 1] + r1 * r2 * tris[t, 2]
+    return (x, t) if return_tri else x
+
+
+def triangle_normals(tris):
+    nrm = np.cross(tris[:, 1] - tris[:, 0], tris[:, 2] - tris[:, 0])
+    return nrm / np.linalg.norm(nrm, axis=1, keepdims=True)
 
 
 def uniform_sphere(rng, n):
@@ -216,7 +229,9 @@ def make_batch(kind, n, seed, phase=0.0, tris_seed=None):
         p = np.full(n, 1.0 / (4 * math.pi))
     elif kind == "surface":
         trng = np.random.default_rng(1000 + (seed if tris_seed is None else tris_seed))
-        x = surface_points(rng, n, triangle_soup(trng))
+        tris = triangle_soup(trng)
+        x, tri = surface_points(rng, n, tris, return_tri=True)
+        normal = triangle_normals(tris)[tri]
         w = field_sample(rng, x, phase)
         p = None
     else:
@@ -227,8 +242,35 @@ def make_batch(kind, n, seed, phase=0.0, tris_seed=None):
     if p is None:
         p = f
     e = rng.exponential(1.0, n)
-    return Batch(_soa(x), _soa(w), (f * e).astype(np.float32), p.astype(np.float32),
-                 dict(kind=kind, seed=seed, phase=phase))
+    meta = dict(kind=kind, seed=seed, phase=phase)
+    if kind == "surface":
+        meta["normal"] = normal
+    return Batch(_soa(x), _soa(w), (f * e).astype(np.float32), p.astype(np.float32), meta)
+
+
+def make_aux(batch, seed):
+    """NPM-product inputs [7][n] float32 for a batch: the outgoing direction
+    omega_o (cosine-distributed about the normal, the direction a path
+    arrives from), the surface normal (the triangle's, facing omega_o; a
+    random unit vector for cube batches), and a roughness U(0.05, 1)."""
+    rng = np.random.default_rng(50000 + seed)
+    n = batch.n
+    nrm = batch.meta.get("normal")
+    if nrm is None:
+        nrm = uniform_sphere(rng, n)
+    # cosine-weighted direction about nrm (Malley's method in a local frame)
+    r = np.sqrt(rng.random(n))
+    phi = 2 * math.pi * rng.random(n)
+    local = np.stack([r * np.cos(phi), r * np.sin(phi), np.sqrt(np.maximum(0.0, 1 - r * r))], 1)
+    a = np.where(np.abs(nrm[:, 2:3]) < 0.9, np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]]))
+    t1 = np.cross(a, nrm)
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(nrm, t1)
+    wo = local[:, :1] * t1 + local[:, 1:2] * t2 + local[:, 2:3] * nrm
+    wo /= np.linalg.norm(wo, axis=1, keepdims=True)
+    rough = rng.uniform(0.05, 1.0, n)
+    out = np.concatenate([wo.T, nrm.T, rough[None, :]], 0)
+    return np.ascontiguousarray(out.astype(np.float32))
 
 
 def edge_positions(rng, n, res_list):

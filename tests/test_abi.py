@@ -57,6 +57,32 @@ def test_layout_matches_oracle(O, net):
         assert (L.layer_out[i], L.layer_in[i]) == on.layer_shape[i]
 
 
+@pytest.mark.parametrize("net", ["CFG2P", "TINYP", "PAPERP"])
+def test_product_layout_matches_oracle(O, net):
+    """NPM-product (Sec. 4.3): G(x) then 2 * sh_degree^2 + 1 extra inputs;
+    the flat layout of the library equals the oracle's."""
+    cfg = getattr(W, net)
+    L = B.layout_of(B.make_config(cfg, exec_mode=B.EXEC_FUSED))
+    on = O.Net(cfg.n_levels, cfg.feat, cfg.base_res, cfg.max_res, cfg.log2_table, cfg.dense_only,
+               cfg.n_hidden, cfg.width, cfg.n_lobes, sh_degree=cfg.sh_degree)
+    assert L.n_in == on.n_in == cfg.n_levels * cfg.feat + 2 * cfg.sh_degree ** 2 + 1
+    assert L.n_params == on.n_params and L.grid_params == on.grid_params
+    for i in range(L.n_layers):
+        assert L.layer_offset[i] == on.layer_offset[i]
+        assert (L.layer_out[i], L.layer_in[i]) == on.layer_shape[i]
+
+
+def test_product_shapes():
+    lib = B.lib()
+    out = B.npm_layout()
+    c = B.make_config(W.CFG1, exec_mode=B.EXEC_FUSED, sh_degree=4)   # 16 grid features
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1        # no fused kernels
+    c = B.make_config(W.CFG1, exec_mode=B.EXEC_STAGED, sh_degree=4)
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == 0 and out.n_in == 16 + 33
+    c = B.make_config(W.CFG2, sh_degree=5)
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+
+
 def test_invalid_configs_rejected_without_device():
     lib = B.lib()
     base = B.make_config(W.CFG2)

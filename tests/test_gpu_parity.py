@@ -43,7 +43,7 @@ def adam_hp(net):
 
 def oracle_net(O, net):
     return O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table,
-                 net.dense_only, net.n_hidden, net.width, net.n_lobes)
+                 net.dense_only, net.n_hidden, net.width, net.n_lobes, sh_degree=net.sh_degree)
 
 
 def randomize(model, on, rng, grid_sd=1.0, mlp_gain=2.0):
@@ -59,15 +59,18 @@ def randomize(model, on, rng, grid_sd=1.0, mlp_gain=2.0):
     return p.astype(np.float64)
 
 
-def check_query(O, torch, model, on, params, batch, idx=None, seed=11, sid=3):
-    """Runs npm_query on the whole batch and checks it (at idx if given)."""
+def check_query(O, torch, model, on, params, batch, idx=None, seed=11, sid=3, aux=None):
+    """Runs npm_query on the whole batch and checks it (at idx if given);
+    aux: the NPM-product inputs [7][n] of the batch."""
     n = batch.n
     pos, dirs = dev(torch, batch.pos), dev(torch, batch.dir)
-    out = model.query(pos, dirs, seed=seed, stream_id=sid)
+    out = model.query(pos, dirs, seed=seed, stream_id=sid,
+                      aux=None if aux is None else dev(torch, aux))
     torch.cuda.synchronize()
     sel = np.arange(n) if idx is None else idx
     sub = batch.subset(sel)
-    q = O.query(on, sub.pos, params, dirs=sub.dir, seed=seed, stream=sid, vid=sel)
+    q = O.query(on, sub.pos, params, dirs=sub.dir, seed=seed, stream=sid, vid=sel,
+                aux=None if aux is None else aux[:, sel])
     raw_ref, raw_scale = O.mlp_forward(on, q["G"], params, with_scale=True)
     msgs = []
     lob = out["lobes"].cpu().numpy()[:, :, sel].transpose(2, 1, 0)
@@ -94,16 +97,17 @@ def check_query(O, torch, model, on, params, batch, idx=None, seed=11, sid=3):
     return msgs, q
 
 
-def check_stages(O, torch, model, on, params, pos_np):
+def check_stages(O, torch, model, on, params, pos_np, aux=None):
     n = pos_np.shape[1]
     pos = dev(torch, pos_np)
+    ax = None if aux is None else dev(torch, aux)
     idx = model.corner_index(pos).cpu().numpy().astype(np.uint32)
     oidx, _ = O.corners(on, pos_np)
     assert np.array_equal(idx.transpose(2, 0, 1).astype(np.int64), oidx), "corner indices differ"
-    G = model.encode(pos).cpu().numpy().T
-    Gr, Gs = O.encode(on, pos_np, params, with_scale=True)
+    G = model.encode(pos, aux=ax).cpu().numpy().T
+    Gr, Gs = O.encode(on, pos_np, params, with_scale=True, aux=aux)
     msgs = [P.check_scaled("encode", G, Gr, Gs)]
-    raw = model.forward_raw(pos).cpu().numpy().T
+    raw = model.forward_raw(pos, aux=ax).cpu().numpy().T
     rr, rs = O.mlp_forward(on, Gr, params, with_scale=True)
     msgs.append(P.check_scaled("raw", raw, rr, rs))
     return msgs
@@ -141,15 +145,17 @@ def test_cfg2_query_parity_full_batch(O, torch, mode):
     model.close()
 
 
-def check_backward(O, torch, model, on, params, batch, tag):
+def check_backward(O, torch, model, on, params, batch, tag, aux=None):
     pos, dirs = dev(torch, batch.pos), dev(torch, batch.dir)
     rad, pdf = dev(torch, batch.radiance), dev(torch, batch.pdf)
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     grad = torch.zeros(on.n_params, dtype=torch.float32, device="cuda")
-    model.backward(pos, dirs, rad, pdf, grad=grad, loss=loss)
+    model.backward(pos, dirs, rad, pdf, grad=grad, loss=loss,
+                   aux=None if aux is None else dev(torch, aux))
     torch.cuda.synchronize()
-    ref = O.backward(on, batch.pos, batch.dir, batch.radiance, batch.pdf, params)
-    ref["cond"] = O.backward_cond(on, batch.pos, batch.dir, batch.radiance, batch.pdf, params)
+    ref = O.backward(on, batch.pos, batch.dir, batch.radiance, batch.pdf, params, aux=aux)
+    ref["cond"] = O.backward_cond(on, batch.pos, batch.dir, batch.radiance, batch.pdf, params,
+                                  aux=aux)
     g = grad.cpu().numpy().astype(np.float64)
     gp = on.grid_params
     msgs = [P.check_grads(f"{tag} grad(grid)", g[:gp], ref["grad"][:gp], ref["cond"][:gp]),

@@ -70,3 +70,18 @@ def test_device_batch_generator_matches_numpy_field():
         se = math.sqrt(got.var() / n + exp.var() / n)
         assert abs(got.mean() - exp.mean()) < 5 * se, (got.mean(), exp.mean(), se)
     assert np.allclose(pos.mean(axis=1), ref.pos.mean(axis=1), atol=0.01)
+
+
+def test_product_inputs():
+    """omega_o is a unit vector cosine-distributed about the unit normal
+    (E[cos] = 2/3), on the triangle's side; roughness in [0.05, 1]."""
+    b = W.make_batch("surface", 20000, seed=4)
+    a = W.make_aux(b, 4).astype(np.float64)
+    wo, nrm, r = a[0:3], a[3:6], a[6]
+    assert np.abs(np.linalg.norm(wo, axis=0) - 1).max() < 1e-6
+    assert np.abs(np.linalg.norm(nrm, axis=0) - 1).max() < 1e-6
+    c = np.sum(wo * nrm, axis=0)
+    assert c.min() >= -1e-6
+    assert abs(c.mean() - 2 / 3) < 5 * math.sqrt((0.5 - 4 / 9) / c.size)
+    assert r.min() >= 0.05 and r.max() <= 1.0
+    assert np.array_equal(W.make_aux(b, 4), W.make_aux(b, 4))
