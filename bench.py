@@ -190,30 +190,27 @@ def serving_bench(n_sessions=32, per_session=6, load=0.7, sweep=(0.3, 0.9)):
     return out
 
 
-def paper_config_bench(reps=20, warm=5):
-    """The paper's own network (8 dense levels 8..86 x F=4, MLP 32-64-64-32,
-    lr 5e-3) on its own batch sizes: queries of one 1280x720 wavefront
-    (921,600 vertices; dir given, lobes + pdf + sample + sample pdf) and
-    training steps of 2^18 vertices, fused FP32 and precision form; median of
-    `reps` HIP-event timings after `warm` warm-ups.  The paper's figures
-    (about 3 ms and 10 ms on an RTX 3070) are context: another GPU."""
+def _time_forms(net, nq, nt, seeds, reps, warm, product=False):
+    """Median HIP-event times of fused queries of nq vertices (dir given;
+    lobes, pdf, sample, sample pdf) and training steps of nt vertices, FP32
+    and the precision form, on surface batches of the workload."""
     import torch
     from paper_2504_04315_amd import npm as B
     from paper_2504_04315_amd import workload as W
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    nq, nt = W.N_PAPER_QUERY, W.N_PAPER_TRAIN
-    qb = W.make_batch("surface", nq, seed=71)
-    tb = W.make_batch("surface", nt, seed=72)
+    qb = W.make_batch("surface", nq, seed=seeds[0])
+    tb = W.make_batch("surface", nt, seed=seeds[1])
     qa = [t(qb.pos), t(qb.dir)]
     ta = [t(tb.pos), t(tb.dir), t(tb.radiance), t(tb.pdf)]
-    out = {"network": "8 dense levels 8..86 x F=4, MLP 32-64-64-32, K=8",
-           "query_batch": nq, "train_batch": nt,
-           "paper": {"query_ms": 3.0, "train_ms": 10.0, "hardware": "RTX 3070"}}
+    qx = t(W.make_aux(qb, seeds[0])) if product else None
+    tx = t(W.make_aux(tb, seeds[1])) if product else None
+    out = {}
     for prec in ("fp32", "bf16"):
-        m = B.NPM(B.make_config(W.PAPER, exec_mode=B.EXEC_FUSED, precision=prec))
+        m = B.NPM(B.make_config(net, exec_mode=B.EXEC_FUSED, precision=prec))
         o = dict(lobes=torch.empty((4, 8, nq), device="cuda"), pdf=torch.empty(nq, device="cuda"),
                  sample_dir=torch.empty((3, nq), device="cuda"),
                  sample_pdf=torch.empty(nq, device="cuda"))
+
         def timed(fn):
             for i in range(warm):
                 fn(i)
@@ -227,14 +224,38 @@ def paper_config_bench(reps=20, warm=5):
                 ms.append(a.elapsed_time(b))
             return float(np.median(ms))
         lib = B.lib()
-        q_ms = timed(lambda i: B.check(lib.npm_query(
-            m.handle, nq, B._ptr(qa[0]), B._ptr(qa[1]), i, 0, B._ptr(o["lobes"]),
+        q_ms = timed(lambda i: B.check(lib.npm_query_aux(
+            m.handle, nq, B._ptr(qa[0]), B._ptr(qx), B._ptr(qa[1]), i, 0, B._ptr(o["lobes"]),
             B._ptr(o["pdf"]), B._ptr(o["sample_dir"]), B._ptr(o["sample_pdf"]), B._stream())))
-        t_ms = timed(lambda i: m.train_step(*ta))
+        t_ms = timed(lambda i: m.train_step(*ta, aux=tx))
         out[prec] = {"query_ms": q_ms, "train_ms": t_ms,
                      "query_vertices_per_s": nq / (q_ms / 1e3),
                      "train_vertices_per_s": nt / (t_ms / 1e3)}
         m.close()
+    return out
+
+
+def paper_config_bench(reps=20, warm=5):
+    """The paper's own network (8 dense levels 8..86 x F=4, MLP 32-64-64-32,
+    lr 5e-3) on its own batch sizes: queries of one 1280x720 wavefront
+    (921,600 vertices) and training steps of 2^18 vertices.  The paper's
+    figures (about 3 ms and 10 ms on an RTX 3070) are context: another GPU."""
+    from paper_2504_04315_amd import workload as W
+    out = {"network": "8 dense levels 8..86 x F=4, MLP 32-64-64-32, K=8",
+           "query_batch": W.N_PAPER_QUERY, "train_batch": W.N_PAPER_TRAIN,
+           "paper": {"query_ms": 3.0, "train_ms": 10.0, "hardware": "RTX 3070"}}
+    out.update(_time_forms(W.PAPER, W.N_PAPER_QUERY, W.N_PAPER_TRAIN, (71, 72), reps, warm))
+    return out
+
+
+def product_bench(reps=20, warm=5):
+    """NPM-product (Sec. 4.3) at the production size: the 16-level hash grid
+    with omega_o, normal (4 SH bands each) and roughness after G(x) -- 65
+    inputs -- on 2^20-vertex queries and training steps."""
+    from paper_2504_04315_amd import workload as W
+    out = {"network": "16-level hash grid T=2^19 F=2 + SH4(omega_o) + SH4(normal) + roughness, "
+                      "MLP 65-64-64-64-32, K=8", "query_batch": 1 << 20, "train_batch": 1 << 20}
+    out.update(_time_forms(W.CFG2P, 1 << 20, 1 << 20, (81, 82), reps, warm, product=True))
     return out
 
 
@@ -391,6 +412,8 @@ def main():
     if not (args.no_serving or args.profile):
         print("paper configuration ...", file=sys.stderr, flush=True)
         line["paper_config"] = paper_config_bench()
+        print("NPM-product ...", file=sys.stderr, flush=True)
+        line["product"] = product_bench()
     if not (args.no_cpu_baseline or args.profile):
         print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(netcfg, batch, params0, args.cpu_seconds)

@@ -70,7 +70,9 @@ enum { NPM_INIT_NORMAL = 0, NPM_INIT_UNIFORM = 1 };
  * NPM_ORDER_SPATIAL sorts the batch by the Morton code of each vertex's 64^3
  * cell (a counting sort on the device, kept in context scratch) so that a
  * wave's consecutive tiles touch nearby grid entries; NPM_ORDER_NONE keeps
- * the caller's order; NPM_ORDER_AUTO sorts batches of 2^15 vertices or more.
+ * the caller's order; NPM_ORDER_AUTO sorts training batches of 2^15
+ * vertices or more, and queries of that size on grids with hashed levels
+ * (on a small dense grid the gathers already hit the cache).
  * A query's outputs do not depend on the order (each vertex keeps its own
  * uniforms; the outputs are staged and un-permuted); a gradient changes only
  * in the order of its floating-point sums.                                  */

@@ -1,6 +1,6 @@
 """Differentiation form: the hot path behind torch.autograd.
 
-`NPMFunction.apply(params, pos, dir, radiance, pdf, model)` returns the
+`NPMFunction.apply(params, pos, dir, radiance, pdf, model, aux)` returns the
 surrogate KL loss of the batch (Sec. 4.2: -(1/N) sum w log V, whose gradient
 is eq. mcgradients) as a float64 device scalar.  Its backward runs the
 library's hand-written backward kernels -- KL-gradient head, MLP backward,
@@ -8,7 +8,9 @@ weight gradients on MFMA, FP32 atomic scatter into the grid -- with the
 grid encoding recomputed from the saved positions rather than stored.
 `params` is a tensor aliasing the library's own FP32 parameter buffer, so
 autograd accumulates its gradient into `params.grad`, and `NPMAdam.step()`
-applies the library's fused Adam to that gradient (and zeroes it).
+applies the library's fused Adam to that gradient (and zeroes it).  aux: the
+NPM-product inputs [7][n] (omega_o, normal, roughness) of a network that
+takes them (Sec. 4.3), else None.
 
 Only argument marshalling happens here; every step runs in libnpm.
 """
@@ -19,10 +21,11 @@ from . import npm as B
 
 class NPMFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, params, pos, dir, radiance, pdf, model):
+    def forward(ctx, params, pos, dir, radiance, pdf, model, aux=None):
         loss = torch.zeros(1, dtype=torch.float64, device=pos.device)
-        model.loss(pos, dir, radiance, pdf, out=loss)
+        model.loss(pos, dir, radiance, pdf, out=loss, aux=aux)
         ctx.model = model
+        ctx.aux = aux
         ctx.save_for_backward(pos, dir, radiance, pdf)
         return loss
 
@@ -31,10 +34,10 @@ class NPMFunction(torch.autograd.Function):
         pos, dir, radiance, pdf = ctx.saved_tensors
         model = ctx.model
         g = torch.zeros(model.n_params, dtype=torch.float32, device=pos.device)
-        model.backward(pos, dir, radiance, pdf, grad=g)
+        model.backward(pos, dir, radiance, pdf, grad=g, aux=ctx.aux)
         if grad_out is not None:
             g.mul_(grad_out.to(torch.float32))
-        return g, None, None, None, None, None
+        return g, None, None, None, None, None, None
 
 
 class NPM(torch.nn.Module):
@@ -46,8 +49,8 @@ class NPM(torch.nn.Module):
         p = self.model.state_tensor(B.STATE_PARAMS)
         self.params = torch.nn.Parameter(p, requires_grad=True)
 
-    def forward(self, pos, dir, radiance, pdf):
-        return NPMFunction.apply(self.params, pos, dir, radiance, pdf, self.model)
+    def forward(self, pos, dir, radiance, pdf, aux=None):
+        return NPMFunction.apply(self.params, pos, dir, radiance, pdf, self.model, aux)
 
     def query(self, pos, dir=None, **kw):
         return self.model.query(pos, dir, **kw)

@@ -142,3 +142,36 @@ def test_product_calls_need_the_extra_inputs(torch):
         plain.query(dev(torch, b.pos), dev(torch, b.dir), aux=dev(torch, W.make_aux(b, 1)))
     model.close()
     plain.close()
+
+
+def test_product_autograd_matches_finite_differences(O, torch):
+    """The differentiation form on the product network: the autograd
+    gradient equals the oracle's and central differences of the FP64 loss
+    (first-layer columns of the extra inputs included)."""
+    from paper_2504_04315_amd.autograd import NPM
+    net = W.TINYP
+    mod = NPM(B.make_config(net, exec_mode=B.EXEC_FUSED))
+    on = oracle_net(O, net)
+    params = mod.model.get_state().astype(np.float64)
+    b = W.make_batch("cube", 2003, seed=71)
+    aux = W.make_aux(b, 71)
+    loss = mod(*(dev(torch, a) for a in (b.pos, b.dir, b.radiance, b.pdf)), aux=dev(torch, aux))
+    loss.backward()
+    g = mod.params.grad.detach().cpu().numpy().astype(np.float64)
+    ref = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, params, aux=aux)
+    cond = O.backward_cond(on, b.pos, b.dir, b.radiance, b.pdf, params, aux=aux)
+    print(P.check_grads("product autograd vs oracle", g, ref["grad"], cond))
+    assert float(loss.item()) == pytest.approx(ref["loss"], rel=1e-5)
+    w0 = on.layer_offset[0]
+    pick = [w0 + o * on.n_in + k for o in range(0, net.width, 3) for k in range(4, on.n_in)]
+    for j in pick:
+        def f(h):
+            p = params.copy(); p[j] += h
+            a = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, p, with_abs=False, aux=aux)["loss"]
+            p[j] -= 2 * h
+            c = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, p, with_abs=False, aux=aux)["loss"]
+            return (a - c) / (2 * h)
+        f1, f2 = f(1e-6), f(5e-7)
+        fd_err = abs(f1 - f2) * 4.0 / 3.0 + 1e-16 * abs(ref["loss"]) / 5e-7
+        assert abs(g[j] - f2) <= 1e-5 * cond[j] + fd_err + 1e-12, (j, g[j], f2)
+    mod.model.close()
