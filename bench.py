@@ -64,6 +64,9 @@ WORK = {
     "staged_scatter": dict(bytes=12 + 32 * 4 + ATOMIC_B, flops=0),
 }
 ADAM_BYTES_PER_PARAM = 32      # read p, g, m, v; write p, m, v, g
+# FP32 global atomics with random addresses, one 64-byte line per request,
+# measured on the MI355X by a probe kernel: 21.1 G requests/s for the chip
+ATOMIC_REQ_CEILING = 21.1e9
 
 
 def kernel_sources_sha():
@@ -374,6 +377,14 @@ def main():
             # (copy-calibrated), null when the kernels changed since
             "traffic": None if tr is None else tr["fetch_bytes"] + tr["write_bytes"],
             "traffic_fetch_write": (None if tr is None else [tr["fetch_bytes"], tr["write_bytes"]])}
+    if tr is not None and tr.get("atomic_requests"):
+        # the FP32 grid-gradient atomics are executed at the memory side, one
+        # request per 64-byte line and wave instruction; their rate, not the
+        # bytes, bounds the scatter (ceiling from a random-address probe)
+        rate = tr["atomic_requests"] / (r["avg_ms"] / 1e3)
+        roof["atomics"] = {"requests_per_launch": tr["atomic_requests"],
+                           "requests_per_s": round(rate), "ceiling_per_s": ATOMIC_REQ_CEILING,
+                           "frac": round(rate / ATOMIC_REQ_CEILING, 4)}
     line = {
         "metric": METRIC,
         "value": n / (ms_per_step / 1e3),
