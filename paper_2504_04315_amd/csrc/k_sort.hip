@@ -40,10 +40,14 @@ __global__ void k_sort_zero(uint32_t *__restrict__ cnt)
         cnt[i] = 0u;
 }
 
-__global__ void k_sort_count(const float *__restrict__ pos, int64_t n, uint32_t *__restrict__ cnt)
+// Counts the vertices of each cell; the count a vertex's increment returns
+// is its rank within the cell, kept in rank[v] so that placement needs no
+// second atomic.
+__global__ void k_sort_count(const float *__restrict__ pos, int64_t n, uint32_t *__restrict__ cnt,
+                             uint32_t *__restrict__ rank)
 {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v < n) atomicAdd(cnt + sort_cell(pos, n, v), 1u);
+    if (v < n) rank[v] = atomicAdd(cnt + sort_cell(pos, n, v), 1u);
 }
 
 // Exclusive prefix sum of the 2^18 counts in two coalesced passes: each block
@@ -90,7 +94,8 @@ __global__ __launch_bounds__(1024) void k_sort_scan_add(uint32_t *__restrict__ c
     cnt[blockIdx.x * 1024 + t] += part[0];
 }
 
-// Places vertex v at its slot: perm[slot] = v, inv[v] = slot (optional), and
+// Places vertex v at its slot, the cell's offset plus its rank (read from
+// inv[v], then replaced by the slot): perm[slot] = v, inv[v] = slot, and
 // its inputs as one record rec[slot] = (pos, dir, radiance, pdf), with zeros
 // for the arrays the call does not have; with the NPM-product inputs aux
 // [7][n] the record is 16 floats, followed by (omega_o, normal, roughness, 0).
@@ -102,9 +107,9 @@ __global__ void k_sort_place(const float *__restrict__ pos, const float *__restr
 {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= n) return;
-    const uint32_t slot = atomicAdd(off + sort_cell(pos, n, v), 1u);
+    const uint32_t slot = off[sort_cell(pos, n, v)] + inv[v];
     perm[slot] = (uint32_t)v;
-    if (inv) inv[v] = slot;
+    inv[v] = slot;
     if (rec) {
         f32x4 a, b;
         a[0] = pos[v]; a[1] = pos[n + v]; a[2] = pos[2 * n + v];
@@ -125,8 +130,8 @@ __global__ void k_sort_place(const float *__restrict__ pos, const float *__restr
 }
 
 // cells: kSortCells counters followed by kScanBlocks block totals; inv
-// (optional) receives the inverse of perm, rec (optional) the inputs in
-// visiting order, 8 floats per slot
+// receives the inverse of perm, rec (optional) the inputs in visiting order,
+// 8 floats per slot (16 with aux)
 hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                          const float *dir, const float *rad, const float *spdf, uint32_t *perm,
                          uint32_t *inv, float *rec, uint32_t *cells, hipStream_t s)
@@ -135,7 +140,7 @@ hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float 
     timed_begin(ctx, "spatial_sort", s, &tok);
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_sort_zero, dim3(256), dim3(256), 0, s, cells);
-    hipLaunchKernelGGL(k_sort_count, dim3(blocks), dim3(256), 0, s, pos, n, cells);
+    hipLaunchKernelGGL(k_sort_count, dim3(blocks), dim3(256), 0, s, pos, n, cells, inv);
     hipLaunchKernelGGL(k_sort_scan_local, dim3(kScanBlocks), dim3(1024), 0, s, cells,
                        cells + kSortCells);
     hipLaunchKernelGGL(k_sort_scan_add, dim3(kScanBlocks), dim3(1024), 0, s, cells,

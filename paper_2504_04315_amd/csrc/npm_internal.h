@@ -168,7 +168,8 @@ hipError_t staged_mlp_dw(npm_ctx *ctx, int64_t n, const float *G, const float *a
 hipError_t staged_scatter(npm_ctx *ctx, int64_t n, const float *pos, const float *dG,
                           float *grad, hipStream_t s);
 
-// spatial order of a batch (k_sort.hip): perm lists the vertices by cell
+// spatial order of a batch (k_sort.hip): perm lists the vertices by cell,
+// inv (required, n entries) receives its inverse
 hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                          const float *dir, const float *rad, const float *spdf, uint32_t *perm,
                          uint32_t *inv, float *rec, uint32_t *cells, hipStream_t s);

@@ -488,7 +488,7 @@ static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const
         const uint32_t *perm = nullptr;
         if (grad && use_order(ctx, n)) {
             NPM_HIP(ensure_sort(ctx, n), "order scratch allocation");
-            NPM_HIP(spatial_order(ctx, n, pos, aux, dir, rad, spdf, ctx->s_perm, nullptr,
+            NPM_HIP(spatial_order(ctx, n, pos, aux, dir, rad, spdf, ctx->s_perm, ctx->s_inv,
                                   ctx->s_rec, ctx->s_cells, s), "spatial order");
             perm = ctx->s_perm;
         }
