@@ -7,7 +7,9 @@ synthetic triangle set with directions and Exp(1)-noisy radiance from an
 analytic 8-lobe vMF field.  One step is one pass of the whole hot path over
 the batch: npm_query (encode + MLP + mappings + pdf at dir + one sample and
 its pdf per vertex) followed by npm_train_step (forward, KL gradient,
-backward, grid scatter, weight gradients, Adam over all parameters).
+backward, grid scatter, weight gradients, Adam over all parameters).  The
+default run also reports the serving form, the paper's own network on its
+batch sizes, NPM-product, and the FP64 oracle on the host cores.
 
 Prints one JSON line.  `value` is vertices per second through a full step
 (query + train on the same batch), inputs resident in HBM.  The roofline
@@ -273,8 +275,8 @@ def load_traffic(workload, sha):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path: the hot path's sharding is described in DESIGN.md.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library runs "
+              "the hot path on one GPU and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2504_04315_amd import npm as B

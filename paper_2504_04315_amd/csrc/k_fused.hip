@@ -5,9 +5,15 @@
 //              -> mixture pdf at dir -> lobe selection and vMF sample (Jakob
 //              2012) -> pdf at the sample.
 //   backward:  encode -> MLP forward (activations in registers) -> KL-gradient
-//              head (Sec. 4.2, eq. mcgradients) -> delta chain -> grid scatter
-//              (FP32 atomics) and weight gradients (MFMA with the tile's
-//              vertices as the reduction dimension, accumulated per wave).
+//              head (Sec. 4.2, eq. mcgradients) -> delta chain -> weight
+//              gradients (MFMA with the tile's vertices as the reduction
+//              dimension, accumulated per wave) -> the tile's dG stored;
+//              then the aggregated grid scatter (FP32 atomics) in a kernel of
+//              its own.
+// Batches of 2^15 vertices or more are visited in a spatial order (k_sort.hip)
+// with their inputs read from one record per slot; a query's outputs are
+// staged per slot and un-permuted.  NPM-product kernels (PG > 0) also take
+// the outgoing direction, normal and roughness (Sec. 4.3).
 //
 // Tile layout (device_math.h): lane l holds vertex l % 32; of a feature vector
 // the half-wave h = l / 32 holds the features nf(h, a).  After the output layer

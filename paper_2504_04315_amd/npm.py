@@ -99,7 +99,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2504_04315_amd/build.py "
-                              "(or __graft_entry__.build()); there is no fallback path")
+                              "(python -m paper_2504_04315_amd.build); there is no fallback path")
         L = C.CDLL(LIB_PATH)
         for name, args in SIGNATURES.items():
             f = getattr(L, name)

@@ -105,7 +105,8 @@ def test_training_curve_with_evaluation_parity(O, torch):
     memorised by the fine hash levels and the held-out loss then rises).
     Every 10 steps the loss of a fixed 1,024-vertex held-out set is computed
     by the GPU and by the oracle from the GPU's parameters (evaluation
-    parity); the curve is written to gpurun_out/ when that directory exists."""
+    parity); the curve is written to $NPM_TEST_OUTPUT when that names a
+    directory."""
     import json
     import os
     import field_torch as FT
@@ -131,8 +132,9 @@ def test_training_curve_with_evaluation_parity(O, torch):
         mod(*gen.next(1 << 20)).backward()
         opt.step()
     print("step, GPU held-out loss, oracle held-out loss:", curve)
-    if os.path.isdir("gpurun_out"):
-        json.dump(curve, open("gpurun_out/cfg4_curve.json", "w"))
+    out = os.environ.get("NPM_TEST_OUTPUT")
+    if out and os.path.isdir(out):
+        json.dump(curve, open(os.path.join(out, "cfg4_curve.json"), "w"))
     assert curve[-1][1] < curve[0][1] - 0.1
     assert curve[-1][1] < curve[10][1]
 
@@ -184,8 +186,9 @@ def test_twin_training_run(O, torch):
     dev_max = float(np.max(np.abs(dev_losses - ref_losses)))
     print(f"twin run: max |loss_gpu - loss_oracle| over 200 steps = {dev_max:.3e}; "
           f"first {ref_losses[0]:.4f}, last {ref_losses[-1]:.4f}")
-    if os.path.isdir("gpurun_out"):
+    out = os.environ.get("NPM_TEST_OUTPUT")
+    if out and os.path.isdir(out):
         json.dump(dict(gpu=dev_losses.tolist(), oracle=ref_losses.tolist()),
-                  open("gpurun_out/cfg4_twin.json", "w"))
+                  open(os.path.join(out, "cfg4_twin.json"), "w"))
     assert dev_losses[0] == pytest.approx(ref_losses[0], rel=1e-5)
     assert dev_max < 0.05 * abs(ref_losses[0])

@@ -8,8 +8,8 @@ them compared) it reports, and bounds:
   Fibonacci sphere;
 * cosine between the precision form's gradient and the oracle's, grid and MLP;
 * a chi-square test of the precision form's samples against the oracle pdf.
-The figures are also written to gpurun_out/precision_metrics.json when that
-directory exists.
+The figures are also written to $NPM_TEST_OUTPUT/precision_metrics.json when
+that variable names a directory.
 """
 import json
 import math
@@ -125,8 +125,9 @@ def test_precision_form_metrics(O, torch):
         pvals.append(float(stats.chi2.sf(chi, keep.sum() - 1)))
     metrics["sample_chi2_pvalues"] = pvals
     print(json.dumps(metrics, indent=1))
-    if os.path.isdir("gpurun_out"):
-        json.dump(metrics, open("gpurun_out/precision_metrics.json", "w"), indent=1)
+    out = os.environ.get("NPM_TEST_OUTPUT")
+    if out and os.path.isdir(out):
+        json.dump(metrics, open(os.path.join(out, "precision_metrics.json"), "w"), indent=1)
     assert metrics["pdf_rel_err"]["p99"] <= 1e-2
     assert metrics["kl_oracle_to_bf16"]["median"] < 1e-3
     assert metrics["grad_cosine"]["grid"] > 0.99 and metrics["grad_cosine"]["mlp"] > 0.99
