@@ -139,3 +139,38 @@ def test_every_request_completes_once(torch):
             p = r["pdf"].cpu().numpy()
             assert np.all(np.isfinite(p)) and np.all(p > 0)
     srv.close()
+
+
+def test_sessions_with_a_moving_average(torch):
+    """A session that keeps a moving average (ema_decay > 0) answers queries
+    with it in the shared kernels, as its own context does."""
+    srv = S.Server(budget_bytes=4 << 30, max_sessions=2)
+    cfg = small_cfg(21)
+    cfg.ema_decay = 0.9
+    sid = srv.create_session(cfg)
+    tb = W.make_batch("surface", 4096, seed=22)
+    targs = [dev(torch, a) for a in (tb.pos, tb.dir, tb.radiance, tb.pdf)]
+    for _ in range(2):
+        srv.wait(srv.submit_train(sid, *targs))
+    b = W.make_batch("surface", 3000, seed=23)
+    pos, dirs = dev(torch, b.pos), dev(torch, b.dir)
+    o = dict(lobes=torch.empty((4, 8, b.n), device="cuda"), pdf=torch.empty(b.n, device="cuda"),
+             sdir=torch.empty((3, b.n), device="cuda"), spdf=torch.empty(b.n, device="cuda"))
+    srv.wait(srv.submit_query(sid, pos, dirs, seed=4, **o))
+    # the session's average, evaluated by a context holding it as parameters
+    twin = B.NPM(small_cfg(21))
+    avg = srv.session_state(sid, twin.n_params, B.STATE_EMA)
+    assert not np.array_equal(avg, srv.session_state(sid, twin.n_params, B.STATE_PARAMS))
+    twin.set_state(avg)
+    ref = twin.query(pos, dirs, seed=4)
+    torch.cuda.synchronize()
+    assert torch.equal(o["pdf"], ref["pdf"]) and torch.equal(o["sdir"], ref["sample_dir"])
+    twin.close()
+    srv.close()
+
+
+def test_product_sessions_are_refused(torch):
+    srv = S.Server(budget_bytes=4 << 30, max_sessions=2)
+    with pytest.raises(B.NPMError):
+        srv.create_session(B.make_config(W.TINYP, exec_mode=B.EXEC_FUSED))
+    srv.close()
