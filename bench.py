@@ -65,6 +65,26 @@ WORK = {
     "staged_mlp_dw": dict(bytes=2 * (ACT_B + 32 * 4 + 32 * 4), flops=MLP_F),
     "staged_scatter": dict(bytes=12 + 32 * 4 + ATOMIC_B, flops=0),
 }
+# Binned scatter of the hashed levels (levels 5-15 of the production grid,
+# 2^19 entries x F = 2 each, in slices of 8,192 entries: 704 bins; chunks of
+# 256 vertices): one 12-byte item (slice entry, 2 FP32) per corner and level.
+L_HASHED, L_DENSE, T_HASH = 11, 5, 1 << 19
+BIN_ITEM_B = 12
+BIN_ITEMS_B = L_HASHED * 8 * BIN_ITEM_B           # 1,056 B per vertex
+BIN_COUNTERS_B = 4 * 704 / 256                    # one counter per bin and chunk
+BIN_WORK = {
+    # positions, dG of the binned levels; counters written
+    "bin_count": dict(bytes=16 + L_HASHED * 2 * 4 + BIN_COUNTERS_B, flops=0),
+    # two read + write passes over the counters
+    "bin_scan": dict(bytes=4 * BIN_COUNTERS_B, flops=0),
+    # positions, dG, the chunk's counter pairs, items written
+    "bin_place": dict(bytes=16 + L_HASHED * 2 * 4 + 2 * BIN_COUNTERS_B + BIN_ITEMS_B, flops=0),
+    # items read; the hashed tables' gradient read and written once per batch
+    # (its per-vertex share at 2^20 vertices is added in main)
+    "bin_reduce": dict(bytes=BIN_ITEMS_B, flops=0),
+}
+# with the hashed levels binned the atomic scatter covers the dense levels
+FUSED_SCATTER_DENSE_B = 12 + 4 + 32 * 4 + 2 * 8 * 2 * 4 * L_DENSE
 ADAM_BYTES_PER_PARAM = 32      # read p, g, m, v; write p, m, v, g
 # FP32 global atomics with random addresses, one 64-byte line per request,
 # measured on the MI355X by a probe kernel: 21.1 G requests/s for the chip
@@ -345,13 +365,18 @@ def main():
     sha = kernel_sources_sha()
     traffic = load_traffic(f"cfg2_{args.precision}_{args.mode}", sha)
     np_params = model.n_params
+    work = dict(WORK)
+    if "bin_reduce" in kt:
+        work.update(BIN_WORK)
+        work["bin_reduce"] = dict(bytes=BIN_ITEMS_B + 2 * L_HASHED * T_HASH * 2 * 4 / n, flops=0)
+        work["fused_scatter"] = dict(bytes=FUSED_SCATTER_DENSE_B, flops=0)
     rows = {}
     for name, (launches, tot) in kt.items():
         if launches == 0:
             continue
         avg_s = tot / launches / 1e3
-        if name in WORK:
-            w = WORK[name]
+        if name in work:
+            w = work[name]
             rows[name] = dict(avg_ms=avg_s * 1e3, launches=launches,
                               gbs=w["bytes"] * n / avg_s / 1e9,
                               tflops=w["flops"] * n / avg_s / 1e12)
@@ -360,17 +385,17 @@ def main():
                               gbs=ADAM_BYTES_PER_PARAM * np_params / avg_s / 1e9, tflops=0.0)
         else:
             rows[name] = dict(avg_ms=avg_s * 1e3, launches=launches, gbs=None, tflops=None)
-    known = [k for k in kt if k in WORK or k == "adam"]
+    known = [k for k in kt if k in work or k == "adam"]
     dom = max(known, key=lambda k: kt[k][1])
     r = rows[dom]
     dtype = args.precision if args.precision == "bf16" else "f32"
     peak_tf = PEAK_TFLOPS[dtype]
-    if dom == "adam" or dom not in WORK or r["tflops"] / peak_tf < r["gbs"] / HBM_PEAK_GBS:
+    if dom == "adam" or dom not in work or r["tflops"] / peak_tf < r["gbs"] / HBM_PEAK_GBS:
         bound, achieved, peak, unit = "hbm", r["gbs"], HBM_PEAK_GBS, "GB/s"
-        per_launch = (WORK[dom]["bytes"] * n if dom in WORK else ADAM_BYTES_PER_PARAM * np_params)
+        per_launch = (work[dom]["bytes"] * n if dom in work else ADAM_BYTES_PER_PARAM * np_params)
     else:
         bound, achieved, peak, unit = "mfma", r["tflops"], peak_tf, "TFLOP/s"
-        per_launch = WORK[dom]["flops"] * n
+        per_launch = work[dom]["flops"] * n
     tr = traffic.get("kernels", {}).get(dom)
     roof = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "kernel": dom,

@@ -77,6 +77,18 @@ enum { NPM_INIT_NORMAL = 0, NPM_INIT_UNIFORM = 1 };
  * uniforms; the outputs are staged and un-permuted); a gradient changes only
  * in the order of its floating-point sums.                                  */
 enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
+/* How the fused training path adds the gradient into the grid's hashed
+ * levels (Sec. 4.2 gradient through the interpolation of Sec. 5.1).
+ * NPM_SCATTER_ATOMIC adds each corner's contribution with an FP32 atomic
+ * (through a tile's LDS window where its corners fall together);
+ * NPM_SCATTER_BINNED first bins the contributions of the hashed levels by
+ * table slice and sums each slice in one block, then adds it to the gradient
+ * (device scratch of about 12 n bytes per hashed level for F = 2, kept in the
+ * context; dense levels keep the atomic path); NPM_SCATTER_AUTO bins
+ * training batches of 2^15 vertices or more whose hashed levels split into
+ * at least 256 slices (8192 / F table entries each).  Either way the gradient
+ * changes only in the order of its floating-point sums.                    */
+enum { NPM_SCATTER_AUTO = 0, NPM_SCATTER_ATOMIC = 1, NPM_SCATTER_BINNED = 2 };
 
 /* Network configuration (copied at create).
  * Grid (Sec. 5.1): n_levels uniform grids over the unit cube with
@@ -96,6 +108,7 @@ enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
  * Adam (Sec. 5.3): lr, beta1, beta2, eps, bias-corrected, eps outside the
  *   square root.
  * batch_order: one of NPM_ORDER_* (fused path: training and queries).
+ * scatter_mode: one of NPM_SCATTER_* (fused path: training).
  * sh_degree: 0 for the radiance-based network (Sec. 4.1), or 1..4 for
  *   NPM-product (Sec. 4.3, Full Integrand Learning): the MLP input is G(x)
  *   followed by the real orthonormal spherical harmonics of sh_degree bands
@@ -132,7 +145,7 @@ typedef struct {
     int32_t batch_order;
     float ema_decay;
     int32_t sh_degree;
-    int32_t reserved;
+    int32_t scatter_mode;
     uint64_t seed;
 } npm_config;
 

@@ -538,7 +538,8 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
                                              int64_t n, int64_t t, int lane,
                                              float *__restrict__ grad, const float *lo,
                                              const float *hi, float *win,
-                                             const float *rec = nullptr, int rec_stride = 8)
+                                             const float *rec = nullptr, int rec_stride = 8,
+                                             uint32_t skip_mask = 0u)
 {
     constexpr int LPV = 8 * F;              // lanes per vertex-level
     constexpr int VPI = 64 / LPV;           // vertex-levels per instruction
@@ -557,6 +558,7 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
         }
     }
     for (int l = 0; l < gv.n_levels; ++l) {
+        if ((skip_mask >> l) & 1u) continue;      // scattered by the binned pass
         const int D = gv.res[l];
         const uint32_t d1 = (uint32_t)D + 1u;
         const bool hashed = (gv.hashed_mask >> l) & 1u;

@@ -1,0 +1,462 @@
+// Binned grid scatter (the gradient of Sec. 4.2 pushed through the
+// trilinear interpolation of Sec. 5.1 into the hashed levels).
+//
+// On a hashed level neighbouring vertices land on unrelated table entries, so
+// no spatial order or LDS window brings their corners together, and every
+// corner becomes one FP32 atomic request executed at the memory side -- the
+// rate that bounds the plain scatter.  Here the corner contributions of those
+// levels are instead binned by table slice (kBinSliceFloats floats) and each
+// slice is summed by one block:
+//
+//   count   per chunk of kBinChunk visiting slots, the number of items of
+//           every (level, slice) bin              -> cnt[bin][chunk]
+//   scan    exclusive prefix sum of cnt in bin-major order: the chunk's run
+//           of items inside its bin's contiguous range
+//   place   the chunk's items, ordered by bin in LDS and written out as
+//           contiguous runs: (entry within the slice, F values w * dG)
+//   reduce  one block per bin: the items sorted by entry in LDS batch by
+//           batch, each entry's run summed by the thread that owns it, then
+//           one read-add-write of the slice into the gradient
+//
+// Items are recomputed identically by count and place (same inputs, same
+// arithmetic), so place fills each chunk's run exactly; every LDS and global
+// index is still checked against its buffer.  The values are those of the
+// atomic scatter (w * dG with the same w), summed in another order.
+#include "device_math.h"
+
+namespace npm {
+
+namespace {
+
+__device__ __forceinline__ void slot_position(const float *__restrict__ pos, const uint32_t *perm,
+                                              const float *__restrict__ rec, int rec_stride,
+                                              int64_t n, int64_t s, float p[3])
+{
+    if (rec) {
+        const f32x4 a = *reinterpret_cast<const f32x4 *>(rec + (size_t)s * rec_stride);
+        p[0] = a[0]; p[1] = a[1]; p[2] = a[2];
+    } else {
+        const int64_t v = perm ? (int64_t)perm[s] : s;
+        p[0] = pos[v]; p[1] = pos[n + v]; p[2] = pos[2 * n + v];
+    }
+}
+
+// dG of slot s, level l, read from the per-tile rows (row l F + f, 32 slots)
+template <int F>
+__device__ __forceinline__ bool slot_dg(const float *__restrict__ dgt, int rows, int64_t s, int l,
+                                        float d[F])
+{
+    const float *src = dgt + (size_t)(s >> 5) * rows * 32 + (s & 31);
+    bool any = false;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        d[f] = src[(l * F + f) * 32];
+        any |= d[f] != 0.0f;
+    }
+    return any;
+}
+
+// Hashed table slot of corner b of the cell and its trilinear weight (the
+// same expressions as the atomic scatter).
+__device__ __forceinline__ uint32_t corner_slot(const int c[3], const float fr[3], int b,
+                                                uint32_t mask, float &w)
+{
+    const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+    const uint32_t X = c[0] + bx, Y = c[1] + by, Z = c[2] + bz;
+    w = (bx ? fr[0] : 1.0f - fr[0]) * (by ? fr[1] : 1.0f - fr[1]) * (bz ? fr[2] : 1.0f - fr[2]);
+    return (X ^ (Y * 2654435761u) ^ (Z * 805459861u)) & mask;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
+    }
+    return x;
+}
+
+}  // namespace
+
+template <int F>
+__global__ __launch_bounds__(kBinChunk) void k_bin_count(GridDesc g, BinDesc bd, int64_t n,
+                                                         const float *__restrict__ pos,
+                                                         const uint32_t *perm,
+                                                         const float *__restrict__ rec,
+                                                         int rec_stride,
+                                                         const float *__restrict__ dgt, int rows,
+                                                         uint32_t *__restrict__ cnt)
+{
+    __shared__ uint32_t hist[kBinMaxBins];
+    __shared__ int s_lv[NPM_MAX_LEVELS], s_res[NPM_MAX_LEVELS];
+    for (int k = threadIdx.x; k < bd.nbins; k += kBinChunk) hist[k] = 0u;
+    if (threadIdx.x < NPM_MAX_LEVELS) {
+        s_lv[threadIdx.x] = bd.lv[threadIdx.x];
+        s_res[threadIdx.x] = g.res[threadIdx.x];
+    }
+    // the sentinel after the last bin: the scan turns it into the total
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt[(size_t)bd.nbins * bd.n_chunks] = 0u;
+    __syncthreads();
+    const int64_t s = blockIdx.x * (int64_t)kBinChunk + threadIdx.x;
+    if (s < n) {
+        float p[3];
+        slot_position(pos, perm, rec, rec_stride, n, s, p);
+        for (int j = 0; j < bd.nb; ++j) {
+            const int l = s_lv[j];
+            float d[F];
+            if (!slot_dg<F>(dgt, rows, s, l, d)) continue;
+            int c[3];
+            float fr[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) lattice_cell(p[a], s_res[l], c[a], fr[a]);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                float w;
+                const uint32_t slot = corner_slot(c, fr, b, g.table_mask, w);
+                atomicAdd(&hist[j * bd.ns + (int)(slot >> bd.log2s)], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < bd.nbins; k += kBinChunk)
+        cnt[(size_t)k * bd.n_chunks + blockIdx.x] = hist[k];
+}
+
+// Exclusive prefix sum of m counters: per block of 1024, then over the block
+// totals (one block, in segments), then the totals added back.
+__global__ __launch_bounds__(1024) void k_bin_scan_local(uint32_t *__restrict__ v, int64_t m,
+                                                         uint32_t *__restrict__ totals)
+{
+    __shared__ uint32_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t i = blockIdx.x * (int64_t)1024 + t;
+    const uint32_t x = i < m ? v[i] : 0u;
+    const uint32_t inc = wave_inclusive_scan(x, lane);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        const uint32_t ws = lane < 16 ? wsum[lane] : 0u;
+        const uint32_t wi = wave_inclusive_scan(ws, lane);
+        if (lane < 16) wsum[lane] = wi - ws;
+        if (lane == 15) totals[blockIdx.x] = wi;
+    }
+    __syncthreads();
+    if (i < m) v[i] = wsum[wave] + inc - x;
+}
+
+__global__ __launch_bounds__(1024) void k_bin_scan_totals(uint32_t *__restrict__ totals, int nblk)
+{
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) carry = 0u;
+    __syncthreads();
+    for (int base = 0; base < nblk; base += 1024) {
+        const int i = base + t;
+        const uint32_t x = i < nblk ? totals[i] : 0u;
+        const uint32_t inc = wave_inclusive_scan(x, lane);
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        if (wave == 0) {
+            const uint32_t ws = lane < 16 ? wsum[lane] : 0u;
+            const uint32_t wi = wave_inclusive_scan(ws, lane);
+            if (lane < 16) wsum[lane] = wi - ws;
+        }
+        __syncthreads();
+        const uint32_t c = carry;
+        if (i < nblk) totals[i] = c + wsum[wave] + inc - x;
+        __syncthreads();
+        if (t == 1023) carry = c + wsum[15] + inc;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_bin_scan_add(uint32_t *__restrict__ v, int64_t m,
+                                                       const uint32_t *__restrict__ totals)
+{
+    const int64_t i = blockIdx.x * (int64_t)1024 + threadIdx.x;
+    if (i < m) v[i] += totals[blockIdx.x];
+}
+
+template <int F>
+__global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd, int64_t n,
+                                                         const float *__restrict__ pos,
+                                                         const uint32_t *perm,
+                                                         const float *__restrict__ rec,
+                                                         int rec_stride,
+                                                         const float *__restrict__ dgt, int rows,
+                                                         const uint32_t *__restrict__ off,
+                                                         uint32_t *__restrict__ items)
+{
+    constexpr int W = 1 + F;                 // words per item
+    constexpr int CAP = kBinChunk * 8;       // items of one chunk and level
+    __shared__ uint32_t st[CAP * W];
+    __shared__ uint16_t sb[CAP];
+    __shared__ uint32_t lb[kBinMaxSlices + 1], rk[kBinMaxSlices], gd[kBinMaxSlices];
+    __shared__ int s_lv[NPM_MAX_LEVELS], s_res[NPM_MAX_LEVELS];
+    const int t = threadIdx.x, lane = t & 63;
+    if (t < NPM_MAX_LEVELS) {
+        s_lv[t] = bd.lv[t];
+        s_res[t] = g.res[t];
+    }
+    const int64_t chunk = blockIdx.x;
+    const int64_t s = chunk * kBinChunk + t;
+    const bool live = s < n;
+    float p[3] = {0.0f, 0.0f, 0.0f};
+    if (live) slot_position(pos, perm, rec, rec_stride, n, s, p);
+    const uint32_t smask = (1u << bd.log2s) - 1u;
+    for (int j = 0; j < bd.nb; ++j) {
+        // this chunk's run of each bin of the level: global start and local base
+        if (t < 64) {
+            uint32_t c0 = 0u;
+            for (int k0 = 0; k0 < bd.ns; k0 += 64) {
+                const int k = k0 + lane;
+                uint32_t c = 0u;
+                if (k < bd.ns) {
+                    const size_t idx = (size_t)(j * bd.ns + k) * bd.n_chunks + chunk;
+                    const uint32_t g0 = off[idx];
+                    c = off[idx + 1] - g0;
+                    gd[k] = g0;
+                    rk[k] = 0u;
+                }
+                const uint32_t inc = wave_inclusive_scan(c, lane);
+                if (k < bd.ns) lb[k] = c0 + inc - c;
+                c0 += __shfl(inc, 63, 64);
+            }
+            if (lane == 0) lb[bd.ns] = c0;
+        }
+        __syncthreads();
+        const int l = s_lv[j];
+        float d[F];
+        if (live && slot_dg<F>(dgt, rows, s, l, d)) {
+            int c[3];
+            float fr[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) lattice_cell(p[a], s_res[l], c[a], fr[a]);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                float w;
+                const uint32_t slot = corner_slot(c, fr, b, g.table_mask, w);
+                const int k = (int)(slot >> bd.log2s);
+                const uint32_t q = lb[k] + atomicAdd(&rk[k], 1u);
+                if (q < lb[k + 1] && q < (uint32_t)CAP) {
+                    st[q * W] = slot & smask;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) st[q * W + 1 + f] = __float_as_uint(w * d[f]);
+                    sb[q] = (uint16_t)k;
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t tot = min(lb[bd.ns], (uint32_t)CAP);
+        for (uint32_t q = t; q < tot; q += kBinChunk) {
+            const int k = sb[q];
+            if (k >= bd.ns) continue;
+            const uint32_t dst = gd[k] + (q - lb[k]);
+            if (dst < bd.cap) {
+#pragma unroll
+                for (int i = 0; i < W; ++i) items[(size_t)dst * W + i] = st[q * W + i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One block per bin.  Thread t owns the slice entries t + NT q (q < EPT) and
+// keeps their sums in registers.  The bin's items are taken in batches of NT
+// IPT: each batch is counting-sorted by entry in LDS (integer LDS atomics
+// give each item its rank within its entry; each thread's entries get
+// consecutive runs), and every thread then adds the runs of its own entries
+// -- the FP32 additions need no atomics.  Strided ownership keeps the counter
+// accesses free of LDS bank conflicts and the final writes coalesced.
+template <int F>
+__global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, BinDesc bd,
+                                                                  const uint32_t *__restrict__ off,
+                                                                  const uint32_t *__restrict__ items,
+                                                                  float *__restrict__ grad)
+{
+    constexpr int W = 1 + F, NT = kBinReduceThreads, IPT = kBinReduceBatch;
+    constexpr int S = kBinSliceFloats / F, EPT = S / NT, BATCH = NT * IPT;
+    static_assert(S % NT == 0, "slice entries must split evenly over the threads");
+    __shared__ uint32_t cnt[S];
+    __shared__ float vals[BATCH * F];
+    __shared__ uint32_t wsum[NT / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int k = blockIdx.x, j = k / bd.ns, slice = k - j * bd.ns;
+    const uint32_t Sb = 1u << bd.log2s;              // entries of this grid's slices (<= S)
+    float acc[EPT][F];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        cnt[t + NT * q] = 0u;
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[q][f] = 0.0f;
+    }
+    const uint64_t beg = off[(size_t)k * bd.n_chunks];
+    const uint64_t end = min(off[(size_t)(k + 1) * bd.n_chunks], (uint32_t)bd.cap);
+    for (uint64_t b0 = beg; b0 < end; b0 += BATCH) {
+        __syncthreads();                                  // counters zeroed
+        uint32_t e[IPT], r[IPT];
+        float v[IPT][F];
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            const uint64_t i = b0 + (uint64_t)u * NT + t;
+            e[u] = 0xffffffffu;
+            if (i < end) {
+                const uint32_t *it = items + i * W;
+                e[u] = it[0];
+#pragma unroll
+                for (int f = 0; f < F; ++f) v[u][f] = __uint_as_float(it[1 + f]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < IPT; ++u)
+            if (e[u] < Sb) r[u] = atomicAdd(&cnt[e[u]], 1u);
+        __syncthreads();
+        // counts of the thread's entries -> the first position of each run
+        uint32_t c[EPT], tot = 0u;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            c[q] = cnt[t + NT * q];
+            tot += c[q];
+        }
+        const uint32_t inc = wave_inclusive_scan(tot, lane);
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t base = inc - tot;
+        for (int w = 0; w < wave; ++w) base += wsum[w];
+        {
+            uint32_t p = base;
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                cnt[t + NT * q] = p;
+                p += c[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            if (e[u] < Sb) {
+                const uint32_t pos = cnt[e[u]] + r[u];
+                if (pos < (uint32_t)BATCH) {
+#pragma unroll
+                    for (int f = 0; f < F; ++f) vals[pos * F + f] = v[u][f];
+                }
+            }
+        }
+        __syncthreads();
+        {
+            uint32_t p = base;
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const uint32_t stop = min(p + c[q], (uint32_t)BATCH);
+                for (uint32_t x = p; x < stop; ++x) {
+#pragma unroll
+                    for (int f = 0; f < F; ++f) acc[q][f] += vals[x * F + f];
+                }
+                p += c[q];
+                cnt[t + NT * q] = 0u;
+            }
+        }
+    }
+    float *dst = grad + ((size_t)g.offset[bd.lv[j]] + (size_t)slice * Sb) * F;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const uint32_t ent = (uint32_t)(t + NT * q);
+        if (ent < Sb) {
+#pragma unroll
+            for (int f = 0; f < F; ++f)
+                if (acc[q][f] != 0.0f) dst[ent * F + f] += acc[q][f];
+        }
+    }
+}
+
+// Which levels are binned, and the sizes of the pass: every hashed level of
+// an unordered batch; of a spatially ordered one, the hashed levels with
+// D_l >= kBinMinResOrdered (coarser ones still fit the tile's LDS window).
+bool bin_plan(const npm_ctx *ctx, int64_t n, bool ordered, BinDesc *out)
+{
+    const GridDesc &g = ctx->net.grid;
+    const int F = g.feat;
+    if (n <= 0 || !g.hashed_mask || (F != 1 && F != 2 && F != 4)) return false;
+    BinDesc b{};
+    for (int l = 0; l < g.n_levels; ++l)
+        if (((g.hashed_mask >> l) & 1u) && (!ordered || g.res[l] >= kBinMinResOrdered))
+            b.lv[b.nb++] = l;
+    if (b.nb == 0) return false;
+    int log2t = 0;
+    while ((1u << log2t) <= g.table_mask) ++log2t;
+    int log2s = 0;
+    while ((1 << (log2s + 1)) * F <= kBinSliceFloats) ++log2s;
+    b.log2s = std::min(log2s, log2t);
+    b.ns = 1 << (log2t - b.log2s);
+    b.nbins = b.nb * b.ns;
+    if (b.ns > kBinMaxSlices || b.nbins > kBinMaxBins) return false;
+    b.n_chunks = (n + kBinChunk - 1) / kBinChunk;
+    b.cap = n * 8 * b.nb;
+    if (b.cap >= ((int64_t)1 << 32) - 1 || (int64_t)b.nbins * b.n_chunks + 1 >= ((int64_t)1 << 31))
+        return false;
+    *out = b;
+    return true;
+}
+
+size_t bin_count_words(const BinDesc &b)
+{
+    const int64_t m = (int64_t)b.nbins * b.n_chunks + 1;
+    return (size_t)m + (size_t)((m + 1023) / 1024);
+}
+
+size_t bin_item_words(const BinDesc &b, int feat) { return (size_t)b.cap * (size_t)(1 + feat); }
+
+template <int F>
+static void launch_bins(const GridDesc &g, const BinDesc &b, int64_t n, const float *pos,
+                        const uint32_t *perm, const float *rec, int rec_stride, const float *dgt,
+                        int rows, float *grad, uint32_t *cnt, uint32_t *items, int phase,
+                        hipStream_t s)
+{
+    const int64_t m = (int64_t)b.nbins * b.n_chunks + 1;
+    const int nblk = (int)((m + 1023) / 1024);
+    switch (phase) {
+    case 0:
+        hipLaunchKernelGGL(k_bin_count<F>, dim3((unsigned)b.n_chunks), dim3(kBinChunk), 0, s, g, b,
+                           n, pos, perm, rec, rec_stride, dgt, rows, cnt);
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_bin_scan_local, dim3(nblk), dim3(1024), 0, s, cnt, m, cnt + m);
+        hipLaunchKernelGGL(k_bin_scan_totals, dim3(1), dim3(1024), 0, s, cnt + m, nblk);
+        hipLaunchKernelGGL(k_bin_scan_add, dim3(nblk), dim3(1024), 0, s, cnt, m, cnt + m);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_bin_place<F>, dim3((unsigned)b.n_chunks), dim3(kBinChunk), 0, s, g, b,
+                           n, pos, perm, rec, rec_stride, dgt, rows, cnt, items);
+        break;
+    default:
+        hipLaunchKernelGGL(k_bin_reduce<F>, dim3(b.nbins), dim3(kBinReduceThreads), 0, s, g, b, cnt,
+                           items, grad);
+        break;
+    }
+}
+
+hipError_t binned_scatter(npm_ctx *ctx, const BinDesc &b, int64_t n, const float *pos,
+                          const uint32_t *perm, const float *rec, int rec_stride,
+                          const float *dgt, int rows, float *grad, uint32_t *cnt,
+                          uint32_t *items, hipStream_t s)
+{
+    const GridDesc &g = ctx->net.grid;
+    static const char *names[4] = {"bin_count", "bin_scan", "bin_place", "bin_reduce"};
+    for (int phase = 0; phase < 4; ++phase) {
+        int tok;
+        timed_begin(ctx, names[phase], s, &tok);
+        switch (g.feat) {
+        case 1: launch_bins<1>(g, b, n, pos, perm, rec, rec_stride, dgt, rows, grad, cnt, items, phase, s); break;
+        case 2: launch_bins<2>(g, b, n, pos, perm, rec, rec_stride, dgt, rows, grad, cnt, items, phase, s); break;
+        default: launch_bins<4>(g, b, n, pos, perm, rec, rec_stride, dgt, rows, grad, cnt, items, phase, s); break;
+        }
+        timed_end(ctx, tok, s);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace npm

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
                                                        const float *__restrict__ rec,
                                                        int rec_stride,
                                                        const float *__restrict__ dgt, int rows,
-                                                       float *__restrict__ grad)
+                                                       float *__restrict__ grad, uint32_t skip_mask)
 {
     __shared__ uint32_t s_off[NPM_MAX_LEVELS];
     __shared__ int s_res[NPM_MAX_LEVELS];
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
         }
         wave_lds_fence();
         scatter_tile<F, WIN_PTS>(gv, tb, pos, perm, n, t, lane, grad, lo, hi, tb + 32 * kStride,
-                                 rec, rec_stride);
+                                 rec, rec_stride, skip_mask);
         wave_lds_fence();
     }
 }
@@ -398,7 +398,7 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *a
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                           const float *dir, const float *rad, const float *spdf, float *grad,
                           double *loss_out, const uint32_t *perm, const float *rec,
-                          float *dg_tiles, hipStream_t s)
+                          float *dg_tiles, const BinDesc *bins, hipStream_t s)
 {
     FusedArgs a = fused_args(ctx, n, pos);
     a.aux = aux;
@@ -422,21 +422,32 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
         const int64_t tiles = (n + 31) / 32;
         const int64_t waves = std::min<int64_t>(tiles, 4096);
         const int rows = std::max(ctx->net.mlp.in_p, 32);
-        timed_begin(ctx, "fused_scatter", s, &tok);
-        switch (ctx->net.grid.feat) {
-        case 1: hipLaunchKernelGGL(k_scatter_tiles<1>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                   ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
-                                   grad); break;
-        case 2: hipLaunchKernelGGL(k_scatter_tiles<2>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                   ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
-                                   grad); break;
-        default: hipLaunchKernelGGL(k_scatter_tiles<4>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                    ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
-                                   grad); break;
+        uint32_t skip = 0u;
+        if (bins)
+            for (int j = 0; j < bins->nb; ++j) skip |= 1u << bins->lv[j];
+        const uint32_t all = ctx->net.grid.n_levels >= 32 ? ~0u : (1u << ctx->net.grid.n_levels) - 1u;
+        if (skip != all) {
+            timed_begin(ctx, "fused_scatter", s, &tok);
+            switch (ctx->net.grid.feat) {
+            case 1: hipLaunchKernelGGL(k_scatter_tiles<1>, dim3((waves + 3) / 4), dim3(256), 0, s,
+                                       ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
+                                       grad, skip); break;
+            case 2: hipLaunchKernelGGL(k_scatter_tiles<2>, dim3((waves + 3) / 4), dim3(256), 0, s,
+                                       ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
+                                       grad, skip); break;
+            default: hipLaunchKernelGGL(k_scatter_tiles<4>, dim3((waves + 3) / 4), dim3(256), 0, s,
+                                        ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
+                                       grad, skip); break;
+            }
+            timed_end(ctx, tok, s);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
         }
-        timed_end(ctx, tok, s);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (bins) {
+            e = binned_scatter(ctx, *bins, n, pos, perm, rec, a.rec_stride, dg_tiles, rows, grad,
+                               ctx->s_bin_cnt, ctx->s_bin_items, s);
+            if (e != hipSuccess) return e;
+        }
     }
     const int blocks = backward_waves(n) / backward_wpb(a, ctx->net.mlp.in_p, ctx->net.mlp.hid_p,
                                                         ctx->net.cfg.precision == NPM_PREC_BF16);

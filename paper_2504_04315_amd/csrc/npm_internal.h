@@ -99,6 +99,10 @@ struct npm_ctx {
     // per-tile dG of a fused training batch, for the aggregated scatter
     float *s_dgt = nullptr;            // [dgt_tiles][max(in_p, 32)][32]
     int64_t dgt_tiles = 0;
+    // binned scatter of the hashed levels: per-chunk bin counts / offsets
+    // (and the scan's block totals), and the binned items
+    uint32_t *s_bin_cnt = nullptr, *s_bin_items = nullptr;
+    size_t bin_cnt_words = 0, bin_item_words = 0;
     npm::Timing timing;
 };
 
@@ -180,6 +184,47 @@ hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float 
 // cover the coarse levels.
 constexpr int64_t kSortMinBatch = 1 << 15;
 
+// Binned scatter of the hashed levels (k_bin.hip).  The corner contributions
+// of a training batch are binned by (level, table slice) in chunks of
+// kBinChunk visiting slots, and each bin (a slice of kBinSliceFloats table
+// floats) is summed by one block, replacing one memory-side FP32 atomic per
+// corner.
+constexpr int kBinChunk = 256;
+constexpr int kBinSliceFloats = 16384;      // table floats per bin (8,192 entries at F = 2)
+constexpr int kBinReduceThreads = 512;
+constexpr int kBinReduceBatch = 8;         // items per thread per sorted batch
+constexpr int kBinMaxBins = 4096;
+constexpr int kBinMaxSlices = 1024;
+// Smallest batch NPM_SCATTER_AUTO bins (the count, scan, place and reduce
+// launches cost a few microseconds each).
+constexpr int64_t kBinMinBatch = 1 << 15;
+// ... and only grids whose binned levels split into this many slices (small
+// tables leave the reduce too few blocks).
+constexpr int kBinMinBins = 256;
+// In a spatially ordered batch the hashed levels coarser than this still
+// fit the tile's LDS window and stay with the atomic scatter.
+constexpr int kBinMinResOrdered = 0;
+struct BinDesc {
+    int32_t nb;                        // binned levels
+    int32_t lv[NPM_MAX_LEVELS];        // their indices
+    int32_t log2s;                     // log2 of the table entries per slice
+    int32_t ns;                        // slices per level
+    int32_t nbins;                     // nb * ns
+    int64_t n_chunks;                  // ceil(n / kBinChunk)
+    int64_t cap;                       // item capacity: n * 8 * nb
+};
+// false when the batch has no level to bin or exceeds the pass's limits
+bool bin_plan(const npm_ctx *ctx, int64_t n, bool ordered, BinDesc *out);
+size_t bin_count_words(const BinDesc &b);
+size_t bin_item_words(const BinDesc &b, int feat);
+// dgt/rows: the per-tile dG of the batch in visiting order (perm / rec as
+// for the fused backward); cnt and items: bin_count_words and
+// bin_item_words 32-bit words
+hipError_t binned_scatter(npm_ctx *ctx, const BinDesc &b, int64_t n, const float *pos,
+                          const uint32_t *perm, const float *rec, int rec_stride,
+                          const float *dgt, int rows, float *grad, uint32_t *cnt,
+                          uint32_t *items, hipStream_t s);
+
 // fused path (k_fused.hip)
 // perm/inv (optional): visiting order and its inverse; the outputs then go
 // through `stage` (n slots of 40 floats) and an un-permuting pass
@@ -188,10 +233,11 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *a
                        float *pdf, float *sdir, float *spdf, const uint32_t *perm,
                        const uint32_t *inv, const float *rec, float *stage, hipStream_t s);
 // perm (optional): the order in which to visit the vertices; dg_tiles: the
-// per-tile dG buffer (required when grad is set)
+// per-tile dG buffer (required when grad is set); bins (optional): the levels
+// to scatter through the binned pass, with the context's bin buffers
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                           const float *dir, const float *rad, const float *spdf, float *grad,
                           double *loss_out, const uint32_t *perm, const float *rec,
-                          float *dg_tiles, hipStream_t s);
+                          float *dg_tiles, const BinDesc *bins, hipStream_t s);
 
 }  // namespace npm

@@ -69,6 +69,8 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
         return bad("the BF16 precision form runs fused only");
     if (c.grid_init != NPM_INIT_NORMAL && c.grid_init != NPM_INIT_UNIFORM) return bad("grid_init");
     if (c.batch_order < NPM_ORDER_AUTO || c.batch_order > NPM_ORDER_SPATIAL) return bad("batch_order");
+    if (c.scatter_mode < NPM_SCATTER_AUTO || c.scatter_mode > NPM_SCATTER_BINNED)
+        return bad("scatter_mode");
     if (!(std::isfinite(c.grid_init_scale) && c.grid_init_scale >= 0.0f)) return bad("grid_init_scale");
     if (!(std::isfinite(c.lr) && c.lr > 0.0f)) return bad("lr must be > 0");
     if (!(c.beta1 >= 0.0f && c.beta1 < 1.0f && c.beta2 >= 0.0f && c.beta2 < 1.0f))
@@ -222,7 +224,8 @@ static void free_ctx(npm_ctx *ctx)
                     (void *)ctx->partials, (void *)ctx->stats, (void *)ctx->s_dw_part,
                     (void *)ctx->s_perm, (void *)ctx->s_inv, (void *)ctx->s_rec,
                     (void *)ctx->s_qstage,
-                    (void *)ctx->s_cells, (void *)ctx->s_dgt,
+                    (void *)ctx->s_cells, (void *)ctx->s_dgt, (void *)ctx->s_bin_cnt,
+                    (void *)ctx->s_bin_items,
                     (void *)ctx->ema, (void *)ctx->ema_img, ctx->ema_img16, ctx->ema_grid16})
         if (p) hipFree(p);
     for (auto &p : ctx->timing.pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
@@ -428,6 +431,41 @@ static bool use_order(const npm_ctx *ctx, int64_t n, bool query)
            (order == NPM_ORDER_SPATIAL || (order == NPM_ORDER_AUTO && auto_sorts));
 }
 
+// The binned pass of a fused training batch: the plan, or false for the
+// atomic scatter alone.
+static bool use_bins(const npm_ctx *ctx, int64_t n, bool ordered, BinDesc *b)
+{
+    const int mode = ctx->net.cfg.scatter_mode;
+    if (ctx->net.cfg.exec_mode != NPM_EXEC_FUSED || mode == NPM_SCATTER_ATOMIC) return false;
+    if (mode == NPM_SCATTER_AUTO && n < kBinMinBatch) return false;
+    if (!bin_plan(ctx, n, ordered, b)) return false;
+    // a reduce of fewer blocks than compute units leaves most of the chip idle
+    return mode == NPM_SCATTER_BINNED || b->nbins >= kBinMinBins;
+}
+
+static hipError_t ensure_bins(npm_ctx *ctx, const BinDesc &b)
+{
+    const size_t cw = bin_count_words(b), iw = bin_item_words(b, ctx->net.grid.feat);
+    if (cw <= ctx->bin_cnt_words && iw <= ctx->bin_item_words) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    if (cw > ctx->bin_cnt_words) {
+        if (ctx->s_bin_cnt) hipFree(ctx->s_bin_cnt);
+        ctx->s_bin_cnt = nullptr;
+        ctx->bin_cnt_words = 0;
+        if ((e = hipMalloc((void **)&ctx->s_bin_cnt, cw * 4)) != hipSuccess) return e;
+        ctx->bin_cnt_words = cw;
+    }
+    if (iw > ctx->bin_item_words) {
+        if (ctx->s_bin_items) hipFree(ctx->s_bin_items);
+        ctx->s_bin_items = nullptr;
+        ctx->bin_item_words = 0;
+        if ((e = hipMalloc((void **)&ctx->s_bin_items, iw * 4)) != hipSuccess) return e;
+        ctx->bin_item_words = iw;
+    }
+    return hipSuccess;
+}
+
 static hipError_t ensure_qstage(npm_ctx *ctx, int64_t n)
 {
     if (n <= ctx->qstage_n) return hipSuccess;
@@ -493,8 +531,12 @@ static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const
             perm = ctx->s_perm;
         }
         if (grad) NPM_HIP(ensure_dgt(ctx, n), "dG scratch allocation");
+        BinDesc bins;
+        const bool binned = grad && use_bins(ctx, n, perm != nullptr, &bins);
+        if (binned) NPM_HIP(ensure_bins(ctx, bins), "bin scratch allocation");
         NPM_HIP(fused_backward(ctx, n, pos, aux, dir, rad, spdf, grad, loss_out, perm,
-                               perm ? ctx->s_rec : nullptr, grad ? ctx->s_dgt : nullptr, s),
+                               perm ? ctx->s_rec : nullptr, grad ? ctx->s_dgt : nullptr,
+                               binned ? &bins : nullptr, s),
                 "fused backward");
         return NPM_OK;
     }
@@ -557,7 +599,7 @@ npm_status npm_loss_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *
         if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED && ctx->net.cfg.precision == NPM_PREC_BF16) {
             // the loss of the precision form: the fused kernel with no gradient output
             NPM_HIP(fused_backward(ctx, n, pos, aux, dir, radiance, sampling_pdf, nullptr,
-                                   loss_out, nullptr, nullptr, nullptr, s), "fused loss");
+                                   loss_out, nullptr, nullptr, nullptr, nullptr, s), "fused loss");
             return NPM_OK;
         }
         NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, nullptr, aux), "encode");

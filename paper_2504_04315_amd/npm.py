@@ -20,6 +20,7 @@ GRID_DENSE, GRID_HASH = 0, 1
 PREC_FP32, PREC_BF16 = 0, 1
 EXEC_STAGED, EXEC_FUSED = 0, 1
 ORDER_AUTO, ORDER_NONE, ORDER_SPATIAL = 0, 1, 2
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_BINNED = 0, 1, 2
 INIT_NORMAL, INIT_UNIFORM = 0, 1
 STATE_PARAMS, STATE_GRADS, STATE_ADAM_M, STATE_ADAM_V, STATE_EMA = 0, 1, 2, 3, 4
 MAX_LEVELS, MAX_LAYERS = 32, 5
@@ -34,7 +35,7 @@ class npm_config(C.Structure):
         ("exec_mode", C.c_int32), ("grid_init", C.c_int32), ("grid_init_scale", C.c_float),
         ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
         ("batch_order", C.c_int32), ("ema_decay", C.c_float), ("sh_degree", C.c_int32),
-        ("reserved", C.c_int32), ("seed", C.c_uint64),
+        ("scatter_mode", C.c_int32), ("seed", C.c_uint64),
     ]
 
 
@@ -120,7 +121,7 @@ def check(status):
 
 
 def make_config(net, exec_mode=EXEC_STAGED, precision=None, lr=None, seed=None,
-                batch_order=ORDER_AUTO, ema_decay=0.0, sh_degree=None):
+                batch_order=ORDER_AUTO, ema_decay=0.0, sh_degree=None, scatter_mode=SCATTER_AUTO):
     """npm_config from a workload.NetConfig (sizes of a workload)."""
     c = npm_config()
     check(lib().npm_config_default(C.byref(c)))
@@ -138,6 +139,7 @@ def make_config(net, exec_mode=EXEC_STAGED, precision=None, lr=None, seed=None,
     c.beta1, c.beta2, c.eps = net.beta1, net.beta2, net.eps
     c.seed = net.seed if seed is None else seed
     c.batch_order = batch_order
+    c.scatter_mode = scatter_mode
     c.ema_decay = ema_decay
     c.sh_degree = getattr(net, "sh_degree", 0) if sh_degree is None else sh_degree
     return c

@@ -91,7 +91,8 @@ def test_invalid_configs_rejected_without_device():
                          ("n_lobes", 4), ("mlp_width", 65), ("mlp_hidden_layers", 0),
                          ("log2_table_size", 40), ("precision", 7), ("lr", -1.0),
                          ("beta1", 1.0), ("max_resolution", 8), ("batch_order", 3),
-                         ("ema_decay", 1.0), ("ema_decay", -0.5)]:
+                         ("ema_decay", 1.0), ("ema_decay", -0.5), ("scatter_mode", 3),
+                         ("scatter_mode", -1)]:
         c = B.npm_config.from_buffer_copy(base)
         setattr(c, field, value)
         assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1, field

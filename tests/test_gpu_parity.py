@@ -192,19 +192,90 @@ def test_cfg1_train_step_parity(O, torch, mode):
 
 
 ORDERS = {"auto": B.ORDER_AUTO, "none": B.ORDER_NONE, "spatial": B.ORDER_SPATIAL}
+SCATTERS = {"auto": B.SCATTER_AUTO, "atomic": B.SCATTER_ATOMIC, "binned": B.SCATTER_BINNED}
 
 
-@pytest.mark.parametrize("mode,order", [("staged", "auto"), ("fused", "auto"),
-                                        ("fused", "none"), ("fused", "spatial")])
+@pytest.mark.parametrize("mode,order,scatter", [
+    ("staged", "auto", "auto"), ("fused", "auto", "auto"),
+    ("fused", "none", "atomic"), ("fused", "none", "binned"),
+    ("fused", "spatial", "atomic"), ("fused", "spatial", "binned")])
 @pytest.mark.parametrize("n", [16384 + 17, 40001])
-def test_cfg2_backward_parity(O, torch, mode, order, n):
-    """Ragged tile counts, in the caller's order and in spatial order."""
-    model = B.NPM(B.make_config(W.CFG2, exec_mode=MODES[mode], batch_order=ORDERS[order]))
+def test_cfg2_backward_parity(O, torch, mode, order, scatter, n):
+    """Ragged tile counts, in the caller's order and in spatial order, with
+    the hashed levels scattered by atomics or through the binned pass."""
+    model = B.NPM(B.make_config(W.CFG2, exec_mode=MODES[mode], batch_order=ORDERS[order],
+                                scatter_mode=SCATTERS[scatter]))
     on = oracle_net(O, W.CFG2)
     params = randomize(model, on, np.random.default_rng(8), grid_sd=0.5)
     batch = W.make_batch("surface", n, seed=22)
     msgs, _, _ = check_backward(O, torch, model, on, params, batch, "cfg2")
     print("\n".join(msgs))
+    model.close()
+
+
+@pytest.mark.parametrize("n", [1, 255, 257, 3001])
+def test_binned_scatter_small_batches(O, torch, n):
+    """The binned pass on a single vertex, one chunk short of full, one
+    vertex into a second chunk, and a ragged dozen chunks."""
+    model = B.NPM(B.make_config(W.CFG2, exec_mode=B.EXEC_FUSED, batch_order=B.ORDER_NONE,
+                                scatter_mode=B.SCATTER_BINNED))
+    on = oracle_net(O, W.CFG2)
+    params = randomize(model, on, np.random.default_rng(9), grid_sd=0.5)
+    batch = W.make_batch("surface", n, seed=23)
+    msgs, _, _ = check_backward(O, torch, model, on, params, batch, f"binned n={n}")
+    print("\n".join(msgs))
+    model.close()
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "binned"])
+def test_backward_accumulates_into_grad(O, torch, scatter):
+    """npm_backward adds into grad_out: two calls give twice the gradient
+    (the binned pass adds each summed slice to what the buffer holds)."""
+    model = B.NPM(B.make_config(W.CFG2, exec_mode=B.EXEC_FUSED, batch_order=B.ORDER_SPATIAL,
+                                scatter_mode=SCATTERS[scatter]))
+    on = oracle_net(O, W.CFG2)
+    params = randomize(model, on, np.random.default_rng(10), grid_sd=0.5)
+    b = W.make_batch("surface", 5003, seed=24)
+    args = [dev(torch, a) for a in (b.pos, b.dir, b.radiance, b.pdf)]
+    grad = torch.zeros(on.n_params, dtype=torch.float32, device="cuda")
+    model.backward(*args, grad=grad)
+    model.backward(*args, grad=grad)
+    torch.cuda.synchronize()
+    ref = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, params)
+    cond = O.backward_cond(on, b.pos, b.dir, b.radiance, b.pdf, params)
+    print(P.check_grads(f"two {scatter} backward calls", grad.cpu().numpy().astype(np.float64),
+                        2 * ref["grad"], 2 * cond))
+    model.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_cfg2_backward_parity_at_training_density(O, torch, prec):
+    """A 2^18-vertex batch (the paper's training batch) in the bench's
+    launch configuration: automatic order and scatter, i.e. spatially sorted
+    with the hashed levels binned.  FP32 against the oracle to the parity
+    tolerance; the precision form's gradient by cosine against the oracle's,
+    grid and MLP, to the precision form's bar (> 0.99)."""
+    net = W.CFG2 if prec == "fp32" else W.CFG3
+    model = B.NPM(B.make_config(net, exec_mode=B.EXEC_FUSED))
+    on = oracle_net(O, net)
+    params = randomize(model, on, np.random.default_rng(11), grid_sd=0.5)
+    batch = W.make_batch("surface", (1 << 18) + 123, seed=25)
+    if prec == "fp32":
+        msgs, _, _ = check_backward(O, torch, model, on, params, batch, "cfg2 2^18")
+        print("\n".join(msgs))
+    else:
+        grad = torch.zeros(on.n_params, dtype=torch.float32, device="cuda")
+        model.backward(*(dev(torch, a) for a in (batch.pos, batch.dir, batch.radiance,
+                                                 batch.pdf)), grad=grad)
+        torch.cuda.synchronize()
+        g = grad.cpu().numpy().astype(np.float64)
+        ref = O.backward(on, batch.pos, batch.dir, batch.radiance, batch.pdf, params,
+                         with_abs=False)["grad"]
+        gp = on.grid_params
+        for name, a, r in (("grid", g[:gp], ref[:gp]), ("mlp", g[gp:], ref[gp:])):
+            cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
+            print(f"bf16 2^18 gradient cosine ({name}): {cos:.6f}")
+            assert cos > 0.99, (name, cos)
     model.close()
 
 
