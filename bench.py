@@ -65,26 +65,27 @@ WORK = {
     "staged_mlp_dw": dict(bytes=2 * (ACT_B + 32 * 4 + 32 * 4), flops=MLP_F),
     "staged_scatter": dict(bytes=12 + 32 * 4 + ATOMIC_B, flops=0),
 }
-# Binned scatter of the hashed levels (levels 5-15 of the production grid,
-# 2^19 entries x F = 2 each, in slices of 8,192 entries: 704 bins; chunks of
-# 256 vertices): one 12-byte item (slice entry, 2 FP32) per corner and level.
-L_HASHED, L_DENSE, T_HASH = 11, 5, 1 << 19
+# Binned scatter of the production grid's hashed levels in a spatially
+# ordered batch: levels 6-15 (D >= 100), 2^19 entries x F = 2 each, in slices
+# of 8,192 entries: 640 bins; chunks of 256 vertices; one 12-byte item (slice
+# entry, 2 FP32) per corner and level.  Levels 0-5 keep the windowed scatter.
+L_BINNED, L_WINDOW, T_HASH = 10, 6, 1 << 19
 BIN_ITEM_B = 12
-BIN_ITEMS_B = L_HASHED * 8 * BIN_ITEM_B           # 1,056 B per vertex
-BIN_COUNTERS_B = 4 * 704 / 256                    # one counter per bin and chunk
+BIN_ITEMS_B = L_BINNED * 8 * BIN_ITEM_B           # 960 B per vertex
+BIN_COUNTERS_B = 4 * 640 / 256                    # one counter per bin and chunk
 BIN_WORK = {
     # positions, dG of the binned levels; counters written
-    "bin_count": dict(bytes=16 + L_HASHED * 2 * 4 + BIN_COUNTERS_B, flops=0),
+    "bin_count": dict(bytes=16 + L_BINNED * 2 * 4 + BIN_COUNTERS_B, flops=0),
     # two read + write passes over the counters
     "bin_scan": dict(bytes=4 * BIN_COUNTERS_B, flops=0),
     # positions, dG, the chunk's counter pairs, items written
-    "bin_place": dict(bytes=16 + L_HASHED * 2 * 4 + 2 * BIN_COUNTERS_B + BIN_ITEMS_B, flops=0),
+    "bin_place": dict(bytes=16 + L_BINNED * 2 * 4 + 2 * BIN_COUNTERS_B + BIN_ITEMS_B, flops=0),
     # items read; the hashed tables' gradient read and written once per batch
     # (its per-vertex share at 2^20 vertices is added in main)
     "bin_reduce": dict(bytes=BIN_ITEMS_B, flops=0),
 }
-# with the hashed levels binned the atomic scatter covers the dense levels
-FUSED_SCATTER_DENSE_B = 12 + 4 + 32 * 4 + 2 * 8 * 2 * 4 * L_DENSE
+# with those levels binned the windowed scatter covers levels 0-5
+FUSED_SCATTER_DENSE_B = 12 + 4 + 32 * 4 + 2 * 8 * 2 * 4 * L_WINDOW
 ADAM_BYTES_PER_PARAM = 32      # read p, g, m, v; write p, m, v, g
 # FP32 global atomics with random addresses, one 64-byte line per request,
 # measured on the MI355X by a probe kernel: 21.1 G requests/s for the chip
@@ -368,7 +369,7 @@ def main():
     work = dict(WORK)
     if "bin_reduce" in kt:
         work.update(BIN_WORK)
-        work["bin_reduce"] = dict(bytes=BIN_ITEMS_B + 2 * L_HASHED * T_HASH * 2 * 4 / n, flops=0)
+        work["bin_reduce"] = dict(bytes=BIN_ITEMS_B + 2 * L_BINNED * T_HASH * 2 * 4 / n, flops=0)
         work["fused_scatter"] = dict(bytes=FUSED_SCATTER_DENSE_B, flops=0)
     rows = {}
     for name, (launches, tot) in kt.items():

@@ -82,12 +82,14 @@ enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
  * NPM_SCATTER_ATOMIC adds each corner's contribution with an FP32 atomic
  * (through a tile's LDS window where its corners fall together);
  * NPM_SCATTER_BINNED first bins the contributions of the hashed levels by
- * table slice and sums each slice in one block, then adds it to the gradient
- * (device scratch of about 12 n bytes per hashed level for F = 2, kept in the
- * context; dense levels keep the atomic path); NPM_SCATTER_AUTO bins
- * training batches of 2^15 vertices or more whose hashed levels split into
- * at least 256 slices (8192 / F table entries each).  Either way the gradient
- * changes only in the order of its floating-point sums.                    */
+ * table slice and sums each slice in one block (in FP64, rounded once to
+ * FP32), then adds it to the gradient.  Device scratch: 32 (1 + F) n bytes
+ * per binned level (96 n at F = 2), kept in the context.  In a spatially
+ * ordered batch only the hashed levels with D_l >= 100 are binned; the others
+ * keep the atomic path.  NPM_SCATTER_AUTO bins training batches of 2^15
+ * vertices or more whose binned levels split into at least 256 slices
+ * (16384 / F table entries each).  Either way the gradient changes only in
+ * the order and width of its floating-point sums.                          */
 enum { NPM_SCATTER_AUTO = 0, NPM_SCATTER_ATOMIC = 1, NPM_SCATTER_BINNED = 2 };
 
 /* Network configuration (copied at create).

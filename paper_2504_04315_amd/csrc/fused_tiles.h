@@ -532,12 +532,12 @@ __device__ __forceinline__ int64_t visit(const uint32_t *perm, int64_t v)
 // most corners.  The cell lookup is monotone in the position, so every corner
 // lies in the window; a corner that did not would take the direct path.
 
-template <int F, int WIN_PTS>
+template <int F, int WIN_PTS, typename WT = float>
 __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dGt,
                                              const float *__restrict__ pos, const uint32_t *perm,
                                              int64_t n, int64_t t, int lane,
                                              float *__restrict__ grad, const float *lo,
-                                             const float *hi, float *win,
+                                             const float *hi, WT *win,
                                              const float *rec = nullptr, int rec_stride = 8,
                                              uint32_t skip_mask = 0u)
 {
@@ -583,7 +583,7 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
         }
         if (use_win) {
             const int nw = ex * ey * ez * F;
-            for (int i = lane; i < nw; i += 64) win[i] = 0.0f;
+            for (int i = lane; i < nw; i += 64) win[i] = WT(0);
             wave_lds_fence();
         }
 #pragma unroll
@@ -601,7 +601,7 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
             const float w = (bx ? fx : 1.0f - fx) * (by ? fy : 1.0f - fy) * (bz ? fz : 1.0f - fz);
             const uint32_t wx = X - (uint32_t)x0, wy = Y - (uint32_t)y0, wz = Z - (uint32_t)z0;
             if (use_win && wx < (uint32_t)ex && wy < (uint32_t)ey && wz < (uint32_t)ez)
-                __hip_atomic_fetch_add(win + ((wz * ey + wy) * ex + wx) * F + f, w * d,
+                __hip_atomic_fetch_add(win + ((wz * ey + wy) * ex + wx) * F + f, WT(w * d),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             else
                 unsafeAtomicAdd(grad + (size_t)entry(X, Y, Z) * F + f, w * d);
@@ -610,11 +610,12 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
             wave_lds_fence();
             const int nw = ex * ey * ez * F;
             for (int i = lane; i < nw; i += 64) {
-                const float s = win[i];
-                if (s != 0.0f) {
+                const WT s = win[i];
+                if (s != WT(0)) {
                     const int p = i / F, pf = i % F;
                     const int pyz = p / ex, wx = p - pyz * ex, wz = pyz / ey, wy = pyz - wz * ey;
-                    unsafeAtomicAdd(grad + (size_t)entry(x0 + wx, y0 + wy, z0 + wz) * F + pf, s);
+                    unsafeAtomicAdd(grad + (size_t)entry(x0 + wx, y0 + wy, z0 + wz) * F + pf,
+                                    (float)s);
                 }
             }
             wave_lds_fence();

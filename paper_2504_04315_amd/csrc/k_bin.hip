@@ -14,9 +14,8 @@
 //           of items inside its bin's contiguous range
 //   place   the chunk's items, ordered by bin in LDS and written out as
 //           contiguous runs: (entry within the slice, F values w * dG)
-//   reduce  one block per bin: the items sorted by entry in LDS batch by
-//           batch, each entry's run summed by the thread that owns it, then
-//           one read-add-write of the slice into the gradient
+//   reduce  one block per bin: FP64 LDS accumulation of its items, then one
+//           coalesced read-add-write of the slice into the gradient
 //
 // Items are recomputed identically by count and place (same inputs, same
 // arithmetic), so place fills each chunk's run exactly; every LDS and global
@@ -193,7 +192,8 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
     constexpr int CAP = kBinChunk * 8;       // items of one chunk and level
     __shared__ uint32_t st[CAP * W];
     __shared__ uint16_t sb[CAP];
-    __shared__ uint32_t lb[kBinMaxSlices + 1], rk[kBinMaxSlices], gd[kBinMaxSlices];
+    __shared__ uint32_t lb[kBinMaxSlices + 1], rk[kBinMaxSlices];
+    __shared__ uint32_t gd[kBinMaxBins], cn[kBinMaxBins];
     __shared__ int s_lv[NPM_MAX_LEVELS], s_res[NPM_MAX_LEVELS];
     const int t = threadIdx.x, lane = t & 63;
     if (t < NPM_MAX_LEVELS) {
@@ -201,23 +201,28 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
         s_res[t] = g.res[t];
     }
     const int64_t chunk = blockIdx.x;
+    // this chunk's run of every bin (start, length), all fetched at once
+    for (int kk = t; kk < bd.nbins; kk += kBinChunk) {
+        const size_t idx = (size_t)kk * bd.n_chunks + chunk;
+        const uint32_t g0 = off[idx];
+        gd[kk] = g0;
+        cn[kk] = off[idx + 1] - g0;
+    }
     const int64_t s = chunk * kBinChunk + t;
     const bool live = s < n;
     float p[3] = {0.0f, 0.0f, 0.0f};
     if (live) slot_position(pos, perm, rec, rec_stride, n, s, p);
     const uint32_t smask = (1u << bd.log2s) - 1u;
+    __syncthreads();
     for (int j = 0; j < bd.nb; ++j) {
-        // this chunk's run of each bin of the level: global start and local base
+        // local base of the chunk's run of each bin of the level
         if (t < 64) {
             uint32_t c0 = 0u;
             for (int k0 = 0; k0 < bd.ns; k0 += 64) {
                 const int k = k0 + lane;
                 uint32_t c = 0u;
                 if (k < bd.ns) {
-                    const size_t idx = (size_t)(j * bd.ns + k) * bd.n_chunks + chunk;
-                    const uint32_t g0 = off[idx];
-                    c = off[idx + 1] - g0;
-                    gd[k] = g0;
+                    c = cn[j * bd.ns + k];
                     rk[k] = 0u;
                 }
                 const uint32_t inc = wave_inclusive_scan(c, lane);
@@ -253,7 +258,7 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
         for (uint32_t q = t; q < tot; q += kBinChunk) {
             const int k = sb[q];
             if (k >= bd.ns) continue;
-            const uint32_t dst = gd[k] + (q - lb[k]);
+            const uint32_t dst = gd[j * bd.ns + k] + (q - lb[k]);
             if (dst < bd.cap) {
 #pragma unroll
                 for (int i = 0; i < W; ++i) items[(size_t)dst * W + i] = st[q * W + i];
@@ -263,111 +268,60 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
     }
 }
 
-// One block per bin.  Thread t owns the slice entries t + NT q (q < EPT) and
-// keeps their sums in registers.  The bin's items are taken in batches of NT
-// IPT: each batch is counting-sorted by entry in LDS (integer LDS atomics
-// give each item its rank within its entry; each thread's entries get
-// consecutive runs), and every thread then adds the runs of its own entries
-// -- the FP32 additions need no atomics.  Strided ownership keeps the counter
-// accesses free of LDS bank conflicts and the final writes coalesced.
+// One block per bin: the slice's sums in LDS, accumulated in FP64 (LDS FP64
+// atomic adds run several times faster than FP32 ones on this chip, and the
+// wider sum rounds once, when it is added to the FP32 gradient), then one
+// coalesced read-add-write of the slice into the gradient.
 template <int F>
 __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, BinDesc bd,
                                                                   const uint32_t *__restrict__ off,
                                                                   const uint32_t *__restrict__ items,
                                                                   float *__restrict__ grad)
 {
-    constexpr int W = 1 + F, NT = kBinReduceThreads, IPT = kBinReduceBatch;
-    constexpr int S = kBinSliceFloats / F, EPT = S / NT, BATCH = NT * IPT;
-    static_assert(S % NT == 0, "slice entries must split evenly over the threads");
-    __shared__ uint32_t cnt[S];
-    __shared__ float vals[BATCH * F];
-    __shared__ uint32_t wsum[NT / 64];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int W = 1 + F, NT = kBinReduceThreads, U = kBinReduceBatch;
+    __shared__ double acc[kBinSliceFloats];
     const int k = blockIdx.x, j = k / bd.ns, slice = k - j * bd.ns;
-    const uint32_t Sb = 1u << bd.log2s;              // entries of this grid's slices (<= S)
-    float acc[EPT][F];
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        cnt[t + NT * q] = 0u;
-#pragma unroll
-        for (int f = 0; f < F; ++f) acc[q][f] = 0.0f;
-    }
+    const uint32_t S = 1u << bd.log2s;
+    const int nf = (int)S * F;
+    for (int i = threadIdx.x; i < nf; i += NT) acc[i] = 0.0;
+    __syncthreads();
     const uint64_t beg = off[(size_t)k * bd.n_chunks];
     const uint64_t end = min(off[(size_t)(k + 1) * bd.n_chunks], (uint32_t)bd.cap);
-    for (uint64_t b0 = beg; b0 < end; b0 += BATCH) {
-        __syncthreads();                                  // counters zeroed
-        uint32_t e[IPT], r[IPT];
-        float v[IPT][F];
-#pragma unroll
-        for (int u = 0; u < IPT; ++u) {
-            const uint64_t i = b0 + (uint64_t)u * NT + t;
-            e[u] = 0xffffffffu;
-            if (i < end) {
-                const uint32_t *it = items + i * W;
-                e[u] = it[0];
-#pragma unroll
-                for (int f = 0; f < F; ++f) v[u][f] = __uint_as_float(it[1 + f]);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < IPT; ++u)
-            if (e[u] < Sb) r[u] = atomicAdd(&cnt[e[u]], 1u);
-        __syncthreads();
-        // counts of the thread's entries -> the first position of each run
-        uint32_t c[EPT], tot = 0u;
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            c[q] = cnt[t + NT * q];
-            tot += c[q];
-        }
-        const uint32_t inc = wave_inclusive_scan(tot, lane);
-        if (lane == 63) wsum[wave] = inc;
-        __syncthreads();
-        uint32_t base = inc - tot;
-        for (int w = 0; w < wave; ++w) base += wsum[w];
-        {
-            uint32_t p = base;
-#pragma unroll
-            for (int q = 0; q < EPT; ++q) {
-                cnt[t + NT * q] = p;
-                p += c[q];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < IPT; ++u) {
-            if (e[u] < Sb) {
-                const uint32_t pos = cnt[e[u]] + r[u];
-                if (pos < (uint32_t)BATCH) {
-#pragma unroll
-                    for (int f = 0; f < F; ++f) vals[pos * F + f] = v[u][f];
-                }
-            }
-        }
-        __syncthreads();
-        {
-            uint32_t p = base;
-#pragma unroll
-            for (int q = 0; q < EPT; ++q) {
-                const uint32_t stop = min(p + c[q], (uint32_t)BATCH);
-                for (uint32_t x = p; x < stop; ++x) {
-#pragma unroll
-                    for (int f = 0; f < F; ++f) acc[q][f] += vals[x * F + f];
-                }
-                p += c[q];
-                cnt[t + NT * q] = 0u;
-            }
-        }
-    }
-    float *dst = grad + ((size_t)g.offset[bd.lv[j]] + (size_t)slice * Sb) * F;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const uint32_t ent = (uint32_t)(t + NT * q);
-        if (ent < Sb) {
+    auto add = [&](uint32_t e, const float *v) {
+        if (e < S) {
 #pragma unroll
             for (int f = 0; f < F; ++f)
-                if (acc[q][f] != 0.0f) dst[ent * F + f] += acc[q][f];
+                __hip_atomic_fetch_add(&acc[e * F + f], (double)v[f], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+    };
+    uint64_t i = beg + threadIdx.x;
+    // U items in flight per thread: all loads issued before the first add
+    for (; i + (uint64_t)(U - 1) * NT < end; i += (uint64_t)U * NT) {
+        uint32_t e[U];
+        float v[U][F];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t *it = items + (i + (uint64_t)u * NT) * W;
+            e[u] = it[0];
+#pragma unroll
+            for (int f = 0; f < F; ++f) v[u][f] = __uint_as_float(it[1 + f]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) add(e[u], v[u]);
+    }
+    for (; i < end; i += NT) {
+        const uint32_t *it = items + i * W;
+        float v[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) v[f] = __uint_as_float(it[1 + f]);
+        add(it[0], v);
+    }
+    __syncthreads();
+    float *dst = grad + ((size_t)g.offset[bd.lv[j]] + (size_t)slice * S) * F;
+    for (int i2 = threadIdx.x; i2 < nf; i2 += NT) {
+        const double a = acc[i2];
+        if (a != 0.0) dst[i2] += (float)a;
     }
 }
 

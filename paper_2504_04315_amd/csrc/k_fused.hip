@@ -148,7 +148,11 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
 // the memory system accepts, and at the one wave per SIMD the MLP kernel's
 // registers allow, a wave waiting on its atomics leaves its SIMD idle, while
 // this kernel runs four waves per SIMD.
-constexpr int kScatterRows = 64;    // per wave: 32 dG rows + 32 window rows
+// per wave: 32 dG rows, then the window of kScatterWinRows rows holding FP64
+// sums (LDS FP64 atomic adds run several times faster than FP32 ones on this
+// chip): kScatterWinRows * kStride / (2 F) lattice points
+constexpr int kScatterWinRows = 32;
+constexpr int kScatterRows = 32 + kScatterWinRows;
 
 template <int F>
 __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
     stage_levels(g, s_off, s_res);
     __syncthreads();
     const GridView gv = grid_view(g, s_off, s_res, nullptr, nullptr);
-    constexpr int WIN_PTS = (kScatterRows - 32) * kStride / F;
+    constexpr int WIN_PTS = kScatterWinRows * kStride / (2 * F);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float *tb = buf + wave * kScatterRows * kStride;
     const int lr = g.n_levels * g.feat;           // dG rows the scatter reads (<= 32)
@@ -190,8 +194,9 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
             *reinterpret_cast<f32x4 *>(tb + (i >> 3) * kStride + (i & 7) * 4) = q;
         }
         wave_lds_fence();
-        scatter_tile<F, WIN_PTS>(gv, tb, pos, perm, n, t, lane, grad, lo, hi, tb + 32 * kStride,
-                                 rec, rec_stride, skip_mask);
+        scatter_tile<F, WIN_PTS, double>(gv, tb, pos, perm, n, t, lane, grad, lo, hi,
+                                         reinterpret_cast<double *>(tb + 32 * kStride), rec,
+                                         rec_stride, skip_mask);
         wave_lds_fence();
     }
 }
