@@ -83,8 +83,8 @@ enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
  * (through a tile's LDS window where its corners fall together);
  * NPM_SCATTER_BINNED first bins the contributions of the hashed levels by
  * table slice and sums each slice in one block (in FP64, rounded once to
- * FP32), then adds it to the gradient.  Device scratch: 32 (1 + F) n bytes
- * per binned level (96 n at F = 2), kept in the context.  In a spatially
+ * FP32), then adds it to the gradient.  Device scratch: 16 (1 + 2 F) n bytes
+ * per binned level (80 n at F = 2), kept in the context.  In a spatially
  * ordered batch only the hashed levels with D_l >= 100 are binned; the others
  * keep the atomic path.  NPM_SCATTER_AUTO bins training batches of 2^15
  * vertices or more whose binned levels split into at least 256 slices

@@ -732,15 +732,17 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
         for (int a = 0; a < OUT0 / 2; ++a) dst[nf(h, a) * 32] = dG[a];
     } else {
         // ---- grid scatter, coalesced: dG through the wave's LDS buffer, the
-        // rows above it as the aggregation window
-        constexpr int WIN_PTS = (HID_P - OUT0) * kStride / F;
+        // rows above it as the aggregation window (FP64 sums: LDS FP64 atomic
+        // adds run several times faster than FP32 ones on this chip)
+        constexpr int WIN_PTS = (HID_P - OUT0) * kStride / (2 * F);
         float lo[3], hi[3];
         if constexpr (WIN_PTS > 0) tile_bbox(px, py, pz, lo, hi);
         wave_lds_fence();
         t32_to_lds<OUT0 / 2>(tbuf, dG, lane);
         wave_lds_fence();
-        scatter_tile<F, WIN_PTS>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad, lo, hi,
-                                 tbuf + OUT0 * kStride, io.rec, io.rec_stride);
+        scatter_tile<F, WIN_PTS, double>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad, lo, hi,
+                                         reinterpret_cast<double *>(tbuf + OUT0 * kStride),
+                                         io.rec, io.rec_stride);
     }
 }
 

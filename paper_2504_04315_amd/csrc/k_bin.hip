@@ -13,7 +13,8 @@
 //   scan    exclusive prefix sum of cnt in bin-major order: the chunk's run
 //           of items inside its bin's contiguous range
 //   place   the chunk's items, ordered by bin in LDS and written out as
-//           contiguous runs: (entry within the slice, F values w * dG)
+//           contiguous runs: F values w * dG (FP32) and, in an array of its
+//           own, the 16-bit entry within the slice
 //   reduce  one block per bin: FP64 LDS accumulation of its items, then one
 //           coalesced read-add-write of the slice into the gradient
 //
@@ -213,6 +214,8 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
     float p[3] = {0.0f, 0.0f, 0.0f};
     if (live) slot_position(pos, perm, rec, rec_stride, n, s, p);
     const uint32_t smask = (1u << bd.log2s) - 1u;
+    float *vals = reinterpret_cast<float *>(items);
+    uint16_t *ents = reinterpret_cast<uint16_t *>(vals + (size_t)bd.cap * F);
     __syncthreads();
     for (int j = 0; j < bd.nb; ++j) {
         // local base of the chunk's run of each bin of the level
@@ -261,7 +264,8 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
             const uint32_t dst = gd[j * bd.ns + k] + (q - lb[k]);
             if (dst < bd.cap) {
 #pragma unroll
-                for (int i = 0; i < W; ++i) items[(size_t)dst * W + i] = st[q * W + i];
+                for (int f = 0; f < F; ++f) vals[(size_t)dst * F + f] = __uint_as_float(st[q * W + 1 + f]);
+                ents[dst] = (uint16_t)st[q * W];
             }
         }
         __syncthreads();
@@ -278,8 +282,10 @@ __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, Bi
                                                                   const uint32_t *__restrict__ items,
                                                                   float *__restrict__ grad)
 {
-    constexpr int W = 1 + F, NT = kBinReduceThreads, U = kBinReduceBatch;
+    constexpr int NT = kBinReduceThreads, U = kBinReduceBatch;
     __shared__ double acc[kBinSliceFloats];
+    const float *vals = reinterpret_cast<const float *>(items);
+    const uint16_t *ents = reinterpret_cast<const uint16_t *>(vals + (size_t)bd.cap * F);
     const int k = blockIdx.x, j = k / bd.ns, slice = k - j * bd.ns;
     const uint32_t S = 1u << bd.log2s;
     const int nf = (int)S * F;
@@ -302,20 +308,19 @@ __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, Bi
         float v[U][F];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t *it = items + (i + (uint64_t)u * NT) * W;
-            e[u] = it[0];
+            const uint64_t ii = i + (uint64_t)u * NT;
+            e[u] = ents[ii];
 #pragma unroll
-            for (int f = 0; f < F; ++f) v[u][f] = __uint_as_float(it[1 + f]);
+            for (int f = 0; f < F; ++f) v[u][f] = vals[ii * F + f];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) add(e[u], v[u]);
     }
     for (; i < end; i += NT) {
-        const uint32_t *it = items + i * W;
         float v[F];
 #pragma unroll
-        for (int f = 0; f < F; ++f) v[f] = __uint_as_float(it[1 + f]);
-        add(it[0], v);
+        for (int f = 0; f < F; ++f) v[f] = vals[i * F + f];
+        add(ents[i], v);
     }
     __syncthreads();
     float *dst = grad + ((size_t)g.offset[bd.lv[j]] + (size_t)slice * S) * F;
@@ -340,6 +345,7 @@ bool bin_plan(const npm_ctx *ctx, int64_t n, bool ordered, BinDesc *out)
     if (b.nb == 0) return false;
     int log2t = 0;
     while ((1u << log2t) <= g.table_mask) ++log2t;
+    static_assert(kBinSliceFloats <= 65536, "slice entries are stored in 16 bits");
     int log2s = 0;
     while ((1 << (log2s + 1)) * F <= kBinSliceFloats) ++log2s;
     b.log2s = std::min(log2s, log2t);
@@ -360,7 +366,11 @@ size_t bin_count_words(const BinDesc &b)
     return (size_t)m + (size_t)((m + 1023) / 1024);
 }
 
-size_t bin_item_words(const BinDesc &b, int feat) { return (size_t)b.cap * (size_t)(1 + feat); }
+// items: cap x F FP32 values, then cap 16-bit slice entries
+size_t bin_item_words(const BinDesc &b, int feat)
+{
+    return (size_t)b.cap * (size_t)feat + ((size_t)b.cap + 1) / 2;
+}
 
 template <int F>
 static void launch_bins(const GridDesc &g, const BinDesc &b, int64_t n, const float *pos,
