@@ -68,10 +68,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
                      a.perm, a.qstage, a.rec, a.aux, a.rec_stride};
     const int lane = threadIdx.x & 63;
     const int64_t ntiles = (a.n + 31) / 32;
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t t = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6); t < ntiles;
-         t += nwaves)
-        query_tile<IN_P, HID_P, NH, F, BF, PG>(gv, smem, io, t, lane);
+    const int wpb = blockDim.x / 64, wave = threadIdx.x >> 6;
+    if (gridDim.x % 8 == 0) {
+        // Workgroups are dispatched to the eight XCDs in turn (block b on XCD
+        // b mod 8), each XCD with its own L2: give each XCD a contiguous
+        // eighth of the tiles, so that the tiles it runs at one time are
+        // neighbours in the batch's order and share grid lines in its L2
+        // (FP32 query 0.56 -> 0.53 ms at 2^20 vertices).  Any placement of
+        // the blocks still covers every tile once.
+        const int64_t xcd = blockIdx.x % 8, bl = blockIdx.x / 8;
+        const int64_t wpx = (int64_t)(gridDim.x / 8) * wpb, span = (ntiles + 7) / 8;
+        const int64_t t0 = xcd * span, t1 = t0 + span < ntiles ? t0 + span : ntiles;
+        for (int64_t t = t0 + bl * wpb + wave; t < t1; t += wpx)
+            query_tile<IN_P, HID_P, NH, F, BF, PG>(gv, smem, io, t, lane);
+    } else {
+        const int64_t nwaves = (int64_t)gridDim.x * wpb;
+        for (int64_t t = blockIdx.x * (int64_t)wpb + wave; t < ntiles; t += nwaves)
+            query_tile<IN_P, HID_P, NH, F, BF, PG>(gv, smem, io, t, lane);
+    }
 }
 
 // Rows of a wave's transpose buffer: the widest matrix side the weight
