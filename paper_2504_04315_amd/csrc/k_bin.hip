@@ -193,9 +193,11 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
     constexpr int CAP = kBinChunk * 8;       // items of one chunk and level
     __shared__ uint32_t st[CAP * W];
     __shared__ uint16_t sb[CAP];
-    __shared__ uint32_t lb[kBinMaxSlices + 1], rk[kBinMaxSlices];
-    __shared__ uint32_t gd[kBinMaxBins], cn[kBinMaxBins];
     __shared__ int s_lv[NPM_MAX_LEVELS], s_res[NPM_MAX_LEVELS];
+    // sized by the launch: each bin's run start and length, then the level's
+    // local bases and ranks (bin_place_lds_bytes)
+    extern __shared__ __attribute__((aligned(16))) uint32_t dyn[];
+    uint32_t *gd = dyn, *cn = dyn + bd.nbins, *lb = cn + bd.nbins, *rk = lb + bd.ns + 1;
     const int t = threadIdx.x, lane = t & 63;
     if (t < NPM_MAX_LEVELS) {
         s_lv[t] = bd.lv[t];
@@ -391,8 +393,9 @@ static void launch_bins(const GridDesc &g, const BinDesc &b, int64_t n, const fl
         hipLaunchKernelGGL(k_bin_scan_add, dim3(nblk), dim3(1024), 0, s, cnt, m, cnt + m);
         break;
     case 2:
-        hipLaunchKernelGGL(k_bin_place<F>, dim3((unsigned)b.n_chunks), dim3(kBinChunk), 0, s, g, b,
-                           n, pos, perm, rec, rec_stride, dgt, rows, cnt, items);
+        hipLaunchKernelGGL(k_bin_place<F>, dim3((unsigned)b.n_chunks), dim3(kBinChunk),
+                           (size_t)(2 * b.nbins + 2 * b.ns + 1) * 4, s, g, b, n, pos, perm, rec,
+                           rec_stride, dgt, rows, cnt, items);
         break;
     default:
         hipLaunchKernelGGL(k_bin_reduce<F>, dim3(b.nbins), dim3(kBinReduceThreads), 0, s, g, b, cnt,

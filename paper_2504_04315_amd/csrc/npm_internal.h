@@ -189,7 +189,7 @@ constexpr int64_t kSortMinBatch = 1 << 15;
 // kBinChunk visiting slots, and each bin (a slice of kBinSliceFloats table
 // floats) is summed by one block in FP64 LDS, replacing one memory-side FP32
 // atomic per corner.
-constexpr int kBinChunk = 256;
+constexpr int kBinChunk = 512;
 constexpr int kBinSliceFloats = 16384;      // table floats per bin (8,192 entries at F = 2)
 constexpr int kBinReduceThreads = 1024;
 constexpr int kBinReduceBatch = 4;         // items in flight per thread
