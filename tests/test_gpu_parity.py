@@ -248,6 +248,20 @@ def test_backward_accumulates_into_grad(O, torch, scatter):
     model.close()
 
 
+def test_cfg2_backward_parity_full_size(O, torch):
+    """The bench's training workload and launch configuration: 2^20 vertices
+    on the 16-level hash grid, automatic order and scatter (spatially sorted,
+    levels 6-15 binned), every entry of the gradient and the loss against
+    the FP64 oracle to the parity tolerance."""
+    model = B.NPM(B.make_config(W.CFG2, exec_mode=B.EXEC_FUSED))
+    on = oracle_net(O, W.CFG2)
+    params = randomize(model, on, np.random.default_rng(12), grid_sd=0.5)
+    batch = W.make_batch("surface", W.N_CFG2, seed=26)
+    msgs, _, _ = check_backward(O, torch, model, on, params, batch, "cfg2 2^20")
+    print("\n".join(msgs))
+    model.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_cfg2_backward_parity_at_training_density(O, torch, prec):
     """A 2^18-vertex batch (the paper's training batch) in the bench's
