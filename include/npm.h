@@ -88,8 +88,11 @@ enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
  * ordered batch only the hashed levels with D_l >= 100 are binned; the others
  * keep the atomic path.  NPM_SCATTER_AUTO bins training batches of 2^15
  * vertices or more whose binned levels split into at least 256 slices
- * (16384 / F table entries each).  Either way the gradient changes only in
- * the order and width of its floating-point sums.                          */
+ * (16384 / F table entries each).  Both fall back to the atomic path when
+ * the pass does not apply: no hashed level to bin, more than 2048 bins or
+ * 1024 slices per level, or 2^32 items or more (n * 8 * binned levels).
+ * Either way the gradient changes only in the order and width of its
+ * floating-point sums.                                                     */
 enum { NPM_SCATTER_AUTO = 0, NPM_SCATTER_ATOMIC = 1, NPM_SCATTER_BINNED = 2 };
 
 /* Network configuration (copied at create).
