@@ -21,8 +21,12 @@ from test_gpu_parity import (adam_hp, check_backward, check_query, check_stages,
 
 pytestmark = pytest.mark.gpu
 
-MODES = {"staged": (B.EXEC_STAGED, B.ORDER_AUTO), "fused": (B.EXEC_FUSED, B.ORDER_NONE),
-         "fused-spatial": (B.EXEC_FUSED, B.ORDER_SPATIAL)}
+MODES = {"staged": (B.EXEC_STAGED, B.ORDER_AUTO, B.SCATTER_AUTO),
+         "fused": (B.EXEC_FUSED, B.ORDER_NONE, B.SCATTER_ATOMIC),
+         "fused-spatial": (B.EXEC_FUSED, B.ORDER_SPATIAL, B.SCATTER_ATOMIC),
+         # every hashed level through the binned pass (the 2-level net's one
+         # hashed level is a single bin)
+         "fused-binned": (B.EXEC_FUSED, B.ORDER_NONE, B.SCATTER_BINNED)}
 
 
 @pytest.fixture(scope="module")
@@ -33,11 +37,11 @@ def torch():
 
 
 def model_of(net, mode, **kw):
-    ex, order = MODES[mode]
-    return B.NPM(B.make_config(net, exec_mode=ex, batch_order=order, **kw))
+    ex, order, scatter = MODES[mode]
+    return B.NPM(B.make_config(net, exec_mode=ex, batch_order=order, scatter_mode=scatter, **kw))
 
 
-@pytest.mark.parametrize("mode", ["staged", "fused", "fused-spatial"])
+@pytest.mark.parametrize("mode", ["staged", "fused", "fused-spatial", "fused-binned"])
 @pytest.mark.parametrize("name,n", [("TINYP", 3001), ("CFG2P", 8192 + 45)])
 def test_product_stages_query_and_gradient(O, torch, mode, name, n):
     net = getattr(W, name)
@@ -62,7 +66,7 @@ def test_product_stages_query_and_gradient(O, torch, mode, name, n):
     model.close()
 
 
-@pytest.mark.parametrize("mode", ["staged", "fused"])
+@pytest.mark.parametrize("mode", ["staged", "fused", "fused-binned"])
 def test_product_train_step(O, torch, mode):
     """npm_train_step_aux = backward + Adam, one step from the GPU's state,
     within the Adam spread of the gradient's tolerance."""
