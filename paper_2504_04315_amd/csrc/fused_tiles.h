@@ -373,6 +373,7 @@ __device__ __forceinline__ GridView grid_view(const GridDesc &g, const uint32_t 
 // dimension; each wave accumulates dW over all its tiles in registers and
 // writes one partial at the end.
 constexpr int kStride = 36;   // LDS row stride (floats) of the transpose buffer
+constexpr int kTransRows = 64;   // rows of a wave's transpose buffer (T32 registers 0..31)
 
 // Writes a T32-layout vector of width 2*REGS into the wave's LDS buffer.
 template <int REGS>
@@ -410,17 +411,30 @@ __device__ __forceinline__ void dw_tile(float *buf, const float *dz, const float
                                         f32x16 (*acc)[IN_P / 32], int lane)
 {
     constexpr int NBO = OUT_P / 32, NBI = IN_P / 32;
+    static_assert(OUT_P <= kTransRows, "the transpose buffer holds kTransRows rows");
     float A[NBO][16], Bv[NBI][16];
     wave_lds_fence();
     t32_to_lds<OUT_P / 2>(buf, dz, lane);
     wave_lds_fence();
 #pragma unroll
     for (int b = 0; b < NBO; ++b) lds_rows(buf, b, lane, A[b]);
+    // the layer input in pieces of at most kTransRows rows: registers
+    // [32, 48) of a T32 vector hold its rows [64, 96)
+    constexpr int P0R = IN_P < kTransRows ? IN_P : kTransRows;
     wave_lds_fence();
-    t32_to_lds<IN_P / 2>(buf, xin, lane);
+    t32_to_lds<P0R / 2>(buf, xin, lane);
     wave_lds_fence();
 #pragma unroll
-    for (int b = 0; b < NBI; ++b) lds_rows(buf, b, lane, Bv[b]);
+    for (int b = 0; b < P0R / 32; ++b) lds_rows(buf, b, lane, Bv[b]);
+    if constexpr (IN_P > kTransRows) {
+        constexpr int P1R = IN_P - kTransRows;
+        static_assert(P1R <= kTransRows, "layer inputs are at most 2 kTransRows wide");
+        wave_lds_fence();
+        t32_to_lds<P1R / 2>(buf, xin + kTransRows / 2, lane);
+        wave_lds_fence();
+#pragma unroll
+        for (int b = 0; b < P1R / 32; ++b) lds_rows(buf, b, lane, Bv[kTransRows / 32 + b]);
+    }
     if constexpr (BF) {
         // step s2 takes the vertices 16 (l/32) + 8 s2 + e: the lane's own values
 #pragma unroll
@@ -724,12 +738,16 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
             dw_tile<HID_P, IN0, BF>(tbuf, dh, x, dw.l0, lane);
         }
     }
-    float dG[OUT0 / 2];
-    layer<BF, HID_P, OUT0>(im, dh, dG, lane);
+    // input gradient: of the grid features only with NPM-product inputs (the
+    // first 32 rows; the caller stages only that block of W_0^T)
+    constexpr int DGR = PG > 0 ? 32 : OUT0;
+    static_assert(PG == 0 || STORE_DG, "NPM-product tiles store dG for the scatter kernels");
+    float dG[DGR / 2];
+    layer<BF, HID_P, DGR>(im, dh, dG, lane);
     if constexpr (STORE_DG) {
         float *dst = dg_tiles + (size_t)t * OUT0 * 32 + (lane & 31);
 #pragma unroll
-        for (int a = 0; a < OUT0 / 2; ++a) dst[nf(h, a) * 32] = dG[a];
+        for (int a = 0; a < DGR / 2; ++a) dst[nf(h, a) * 32] = dG[a];
     } else {
         // ---- grid scatter, coalesced: dG through the wave's LDS buffer, the
         // rows above it as the aggregation window (FP64 sums: LDS FP64 atomic

@@ -89,10 +89,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 }
 
 // Rows of a wave's transpose buffer: the widest matrix side the weight
-// gradients transpose (hidden width, or a first-layer input wider than it).
+// gradients transpose at once (hidden width, or the first-layer input, which
+// a wider-than-kTransRows input passes in two pieces).
 constexpr int trans_rows(int in_p, int hid_p)
 {
-    return (in_p < 32 ? 32 : in_p) > hid_p ? (in_p < 32 ? 32 : in_p) : hid_p;
+    const int in0 = in_p < 32 ? 32 : in_p;
+    const int piece = in0 < kTransRows ? in0 : kTransRows;
+    return piece > hid_p ? piece : hid_p;
+}
+
+// Weight-image elements a training block stages in LDS: all of them, except
+// that with NPM-product inputs only the grid features' input gradient is
+// needed, so of W_0^T -- the last segment, its 32-row blocks in order --
+// only the first block is staged.
+static int64_t staged_elems(const FusedArgs &a, int in_p, int hid_p, int pg)
+{
+    const int in0 = in_p < 32 ? 32 : in_p;
+    const int dg_rows = pg > 0 ? 32 : in0;
+    return (int64_t)a.fwd_elems + a.bwd_elems - (int64_t)(in0 - dg_rows) * hid_p;
 }
 
 template <int IN_P, int HID_P, int NH, int F, bool BF, int PG>
@@ -103,7 +117,9 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     __shared__ int s_res[NPM_MAX_LEVELS];
     __shared__ double red[256];
     constexpr int ESZ = BF ? 2 : 4;
-    const int img_bytes = (a.fwd_elems + a.bwd_elems) * ESZ;
+    constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
+    const int img_bytes =
+        (a.fwd_elems + a.bwd_elems - (PG > 0 ? (IN0 - 32) * HID_P : 0)) * ESZ;
     for (int i = threadIdx.x; i < img_bytes / 16; i += blockDim.x)
         reinterpret_cast<f32x4 *>(smem)[i] = reinterpret_cast<const f32x4 *>(a.img)[i];
     stage_levels(a.g, s_off, s_res);
@@ -304,12 +320,11 @@ static int backward_waves(int64_t n)
 // room for the kernel's static arrays (level table, FP64 loss partials).
 constexpr size_t kLdsBytes = 160 * 1024 - 4096;
 
-// Waves per block of the backward kernel: four, or two when the weight images
-// and four waves' transpose buffers exceed the LDS (the FP32 images of a
-// 96-wide first layer).
-static int backward_wpb(const FusedArgs &a, int in_p, int hid_p, bool bf)
+// Waves per block of the backward kernel: four, or two when the staged
+// weight images and four waves' transpose buffers exceed the LDS.
+static int backward_wpb(const FusedArgs &a, int in_p, int hid_p, bool bf, int pg)
 {
-    const size_t img = ((size_t)(a.fwd_elems + a.bwd_elems) * (bf ? 2 : 4) + 15) / 16 * 16;
+    const size_t img = ((size_t)staged_elems(a, in_p, hid_p, pg) * (bf ? 2 : 4) + 15) / 16 * 16;
     return img + (size_t)4 * trans_rows(in_p, hid_p) * kStride * sizeof(float) <= kLdsBytes ? 4 : 2;
 }
 
@@ -317,9 +332,9 @@ template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0>
 static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
 {
     const int waves = backward_waves(a.n);
-    const int wpb = backward_wpb(a, IN_P, HID_P, BF);
+    const int wpb = backward_wpb(a, IN_P, HID_P, BF, PG);
     const int blocks = waves / wpb;
-    const size_t img = ((size_t)(a.fwd_elems + a.bwd_elems) * (BF ? 2 : 4) + 15) / 16 * 16;
+    const size_t img = ((size_t)staged_elems(a, IN_P, HID_P, PG) * (BF ? 2 : 4) + 15) / 16 * 16;
     const size_t lds = img + (size_t)wpb * trans_rows(IN_P, HID_P) * kStride * sizeof(float);
     const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
     if (lds > kLdsBytes || (size_t)count * sizeof(float) > lds) return hipErrorInvalidValue;
@@ -469,7 +484,8 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
         }
     }
     const int blocks = backward_waves(n) / backward_wpb(a, ctx->net.mlp.in_p, ctx->net.mlp.hid_p,
-                                                        ctx->net.cfg.precision == NPM_PREC_BF16);
+                                                        ctx->net.cfg.precision == NPM_PREC_BF16,
+                                                        ctx->net.mlp.sh_degree > 0 ? 1 : 0);
     if (grad) {
         const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
         timed_begin(ctx, "fused_dw_sum", s, &tok);
