@@ -227,6 +227,31 @@ def test_binned_scatter_small_batches(O, torch, n):
     model.close()
 
 
+# hashed grids with F = 4 (8 levels, 16..512, T = 2^16: 4,096-entry slices)
+# and F = 1 (16 levels, 16..1024, T = 2^17: 16,384-entry slices)
+F4_HASH = W.NetConfig(n_levels=8, feat=4, base_res=16, max_res=512, log2_table=16,
+                      dense_only=False, n_hidden=3, width=64, grid_init="uniform",
+                      grid_init_scale=0.1, seed=13)
+F1_HASH = W.NetConfig(n_levels=16, feat=1, base_res=16, max_res=1024, log2_table=17,
+                      dense_only=False, n_hidden=2, width=32, grid_init="uniform",
+                      grid_init_scale=0.1, seed=14)
+
+
+@pytest.mark.parametrize("order", ["none", "spatial"])
+@pytest.mark.parametrize("net", [F4_HASH, F1_HASH], ids=["F4", "F1"])
+def test_binned_scatter_other_feature_counts(O, torch, net, order):
+    """The binned pass at F = 4 and F = 1 (its other instantiations), in the
+    caller's order (every hashed level binned) and in spatial order."""
+    model = B.NPM(B.make_config(net, exec_mode=B.EXEC_FUSED, batch_order=ORDERS[order],
+                                scatter_mode=B.SCATTER_BINNED))
+    on = oracle_net(O, net)
+    params = randomize(model, on, np.random.default_rng(15), grid_sd=0.5)
+    batch = W.make_batch("surface", 5003, seed=27)
+    msgs, _, _ = check_backward(O, torch, model, on, params, batch, f"F={net.feat} {order}")
+    print("\n".join(msgs))
+    model.close()
+
+
 @pytest.mark.parametrize("scatter", ["atomic", "binned"])
 def test_backward_accumulates_into_grad(O, torch, scatter):
     """npm_backward adds into grad_out: two calls give twice the gradient
