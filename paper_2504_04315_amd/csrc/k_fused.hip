@@ -260,21 +260,33 @@ __global__ __launch_bounds__(256) void k_query_unstage(int64_t n, const uint32_t
     if (spdf) spdf[i] = c[kStageSpdf];
 }
 
-// Sums the per-block partials of the MLP weight gradient into grad: a block
-// of 256 threads covers 64 weights, its four thread rows a quarter of the
-// partials each, then the rows add in LDS.
+// Sum of the blocks' weight-gradient partials into the gradient: a block of
+// 256 threads covers 16 weights, its 16 thread rows a sixteenth of the
+// partials each (several loads in flight per thread, 768 blocks at the
+// production size), then the rows add in LDS.
 __global__ __launch_bounds__(256) void k_dw_sum(const float *__restrict__ part, int nparts,
                                                 int count, float *__restrict__ grad)
 {
-    __shared__ float red[4][64];
-    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + x;
-    float s = 0.0f;
-    if (i < count)
-        for (int p = y; p < nparts; p += 4) s += part[(int64_t)p * count + i];
-    red[y][x] = s;
+    __shared__ float red[16][17];
+    const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + x;
+    float s0 = 0.0f, s1 = 0.0f;
+    if (i < count) {
+        int p = y;
+        for (; p + 16 < nparts; p += 32) {
+            s0 += part[(int64_t)p * count + i];
+            s1 += part[(int64_t)(p + 16) * count + i];
+        }
+        if (p < nparts) s0 += part[(int64_t)p * count + i];
+    }
+    red[y][x] = s0 + s1;
     __syncthreads();
-    if (y == 0 && i < count) grad[i] += (red[0][x] + red[1][x]) + (red[2][x] + red[3][x]);
+    if (y == 0 && i < count) {
+        float t = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) t += red[r][x];
+        grad[i] += t;
+    }
 }
 
 // ------------------------------------------------------------------ launch
@@ -489,7 +501,7 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
     if (grad) {
         const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
         timed_begin(ctx, "fused_dw_sum", s, &tok);
-        hipLaunchKernelGGL(k_dw_sum, dim3((count + 63) / 64), dim3(256), 0, s, ctx->s_dw_part,
+        hipLaunchKernelGGL(k_dw_sum, dim3((count + 15) / 16), dim3(256), 0, s, ctx->s_dw_part,
                            blocks, count, grad + ctx->net.lay.grid_params);
         timed_end(ctx, tok, s);
         e = hipGetLastError();
