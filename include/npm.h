@@ -270,6 +270,30 @@ npm_status npm_encode_aux(npm_ctx *ctx, int64_t n, const float *pos, const float
 npm_status npm_forward_raw_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                                float *raw, void *stream);
 
+/* npm_backward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and result as npm_backward_aux (aux NULL on a
+ * radiance-based network), but the call allocates nothing: its scratch (the
+ * spatial order of the batch and the per-tile input gradients) lives in one
+ * fixed array of NPM_STATIC_SCRATCH_BYTES per device, held from the first
+ * npm_create on that device until the process ends, instead of the
+ * context's grow-on-demand buffers.
+ *   - n must be at most NPM_STATIC_MAX_N (NPM_ERR_INVALID_ARG otherwise).
+ *   - The context must be NPM_EXEC_FUSED (NPM_ERR_STATE otherwise).
+ *   - The grid gradient is always added with the atomic scatter (never the
+ *     binned pass, whose scratch grows with n); the result differs from
+ *     npm_backward's only in the order of its floating-point sums.
+ *   - Kernel timing (npm_set_timing) does not cover these calls.
+ *   - Every call on a device shares that device's array, which keeps the
+ *     last call's contents: calls that overlap on one device (two streams,
+ *     two contexts, two threads) race and give wrong gradients; serialise
+ *     them on one stream.                                                  */
+#define NPM_STATIC_MAX_N 32768
+#define NPM_STATIC_SCRATCH_BYTES (16u << 20)
+npm_status npm_backward_static(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                               const float *dir, const float *radiance, const float *sampling_pdf,
+                               float *grad_out, double *loss_out, void *stream);
+
 /* Stage outputs, for checking each step of the path on its own.
  *   npm_corner_index: idx [L][8][n] global table entry of corner b of level
  *     l (corner b has offsets (b&1, b>>1&1, b>>2&1) in x, y, z).

@@ -54,6 +54,7 @@ __global__ void k_sort_count(const float *__restrict__ pos, int64_t n, uint32_t 
 // of 1024 threads scans its 1024 counts in LDS and records their total; then
 // each block adds the totals of the blocks before it.
 constexpr int kScanBlocks = kSortCells / 1024;     // 256
+static_assert(kSortCells + kScanBlocks == (int)kSortCellWords, "cell scratch layout");
 
 __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *part)
 {

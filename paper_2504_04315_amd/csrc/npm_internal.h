@@ -183,6 +183,9 @@ hipError_t spatial_order(npm_ctx *ctx, int64_t n, const float *pos, const float 
 // 1.28 ms); a batch of 2^15 vertices is still dense enough for the window to
 // cover the coarse levels.
 constexpr int64_t kSortMinBatch = 1 << 15;
+// 32-bit words of the sort's cell scratch: 2^18 cell counters, then 256
+// block totals of its scan.
+constexpr size_t kSortCellWords = ((size_t)1 << 18) + 256;
 
 // Binned scatter of the hashed levels (k_bin.hip).  The corner contributions
 // of a training batch are binned by (level, table slice) in chunks of

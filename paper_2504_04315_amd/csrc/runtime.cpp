@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -165,6 +166,62 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
 }
 
 // --------------------------------------------------------------------------
+// Scratch of npm_backward_static, the entry point for callers that cannot
+// allocate: one fixed array per device (each device holds its own copy of a
+// __device__ array, at its own address, until the process ends).  In host
+// code `scratch` names a host-side stand-in, never device memory: kernels and
+// copies get the device address that hipGetSymbolAddress returns, resolved
+// once per device by the first npm_create on it (with that device current).
+static __device__ __align__(256) unsigned char scratch[NPM_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Byte offsets of the parts of the array for a batch of at most
+// NPM_STATIC_MAX_N vertices: the sort's cell counters, the visiting order
+// and its inverse, the input records (64 bytes with NPM-product inputs), the
+// per-tile dG (at most 96 rows of 32 floats per 32-vertex tile).
+constexpr size_t kScrCells = 0;
+constexpr size_t kScrPerm = kScrCells + ((kSortCellWords * 4 + 255) / 256) * 256;
+constexpr size_t kScrInv = kScrPerm + (size_t)NPM_STATIC_MAX_N * 4;
+constexpr size_t kScrRec = kScrInv + (size_t)NPM_STATIC_MAX_N * 4;
+constexpr size_t kScrDgt = kScrRec + (size_t)NPM_STATIC_MAX_N * 64;
+constexpr size_t kScrEnd = kScrDgt + (size_t)(NPM_STATIC_MAX_N / 32) * 96 * 32 * 4;
+static_assert(kScrEnd <= NPM_STATIC_SCRATCH_BYTES, "static scratch layout exceeds the array");
+}  // namespace
+
+// Resolves the array's address on device `dev` (the current device) once.
+static void static_scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[dev]) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[dev] = e;
+    g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+    g_scratch_done[dev] = true;
+}
+
+// The array's device address on `dev`, or null with the reason in *err.
+static void *static_scratch(int dev, std::string *err)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = "device index beyond the static scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev])
+        *err = std::string("static scratch address not resolved: ") +
+               (g_scratch_done[dev] ? hipGetErrorString(g_scratch_err[dev]) : "no context created");
+    return g_scratch_ptr[dev];
+}
+
+// --------------------------------------------------------------------------
 extern "C" {
 
 const char *npm_last_error(void) { return g_err.c_str(); }
@@ -251,6 +308,7 @@ npm_status npm_create(const npm_config *cfg, npm_ctx **out)
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(NPM_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName +
                                            ", the library is built for gfx950");
+    static_scratch_setup(dev);
     npm_ctx *ctx = new (std::nothrow) npm_ctx();
     if (!ctx) return fail(NPM_ERR_OOM, "host allocation");
     ctx->net = net;
@@ -496,7 +554,7 @@ static hipError_t ensure_sort(npm_ctx *ctx, int64_t n)
     if (e == hipSuccess)
         e = hipMalloc((void **)&ctx->s_rec, (size_t)n * (ctx->net.cfg.sh_degree ? 64 : 32));
     if (e == hipSuccess && !ctx->s_cells)
-        e = hipMalloc((void **)&ctx->s_cells, ((size_t)1 << 18) * 4 + 256 * 4);  // counts, block totals
+        e = hipMalloc((void **)&ctx->s_cells, kSortCellWords * 4);  // counts, block totals
     if (e != hipSuccess) return e;
     ctx->sort_n = n;
     return hipSuccess;
@@ -576,6 +634,59 @@ npm_status npm_backward_aux(npm_ctx *ctx, int64_t n, const float *pos, const flo
     } catch (...) {
         return fail(NPM_ERR_HIP, "unexpected exception");
     }
+}
+
+npm_status npm_backward_static(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                               const float *dir, const float *radiance, const float *sampling_pdf,
+                               float *grad_out, double *loss_out, void *stream)
+{
+    npm_status st = check_train(ctx, n, pos, dir, radiance, sampling_pdf);
+    if (st != NPM_OK) return st;
+    if ((st = check_aux(ctx, n, aux)) != NPM_OK) return st;
+    if (grad_out && !aligned4(grad_out)) return fail(NPM_ERR_INVALID_ARG, "misaligned grad_out");
+    if (n > NPM_STATIC_MAX_N)
+        return fail(NPM_ERR_INVALID_ARG, "npm_backward_static takes at most NPM_STATIC_MAX_N = " +
+                                             std::to_string(NPM_STATIC_MAX_N) +
+                                             " vertices (its scratch is a fixed array); got " +
+                                             std::to_string(n));
+    if (ctx->net.cfg.exec_mode != NPM_EXEC_FUSED)
+        return fail(NPM_ERR_STATE, "npm_backward_static runs the fused path: the context must be "
+                                   "NPM_EXEC_FUSED");
+    if (ctx->net.mlp.in_p > 96) return fail(NPM_ERR_STATE, "network input too wide for the static scratch");
+    if (n == 0) return NPM_OK;
+    std::string why;
+    unsigned char *base = (unsigned char *)static_scratch(ctx->device, &why);
+    if (!base) return fail(NPM_ERR_HIP, why);
+    uint32_t *cells = (uint32_t *)(base + kScrCells);
+    uint32_t *perm = (uint32_t *)(base + kScrPerm);
+    uint32_t *inv = (uint32_t *)(base + kScrInv);
+    float *rec = (float *)(base + kScrRec);
+    float *dgt = (float *)(base + kScrDgt);
+    float *grad = grad_out ? grad_out : ctx->grads;
+    hipStream_t s = (hipStream_t)stream;
+    // no event pairs: timing would create events, which allocates
+    const bool timing = ctx->timing.enabled;
+    ctx->timing.enabled = false;
+    hipError_t e = hipSuccess;
+    const bool ordered = use_order(ctx, n);
+    try {
+        // every part of the array a kernel reads below is written earlier in
+        // this call: the sort zeroes its counters with a kernel and writes the
+        // order, its inverse and the records of the n slots; the tile kernel
+        // writes every dG row the scatter reads, for every tile of the batch
+        if (ordered)
+            e = spatial_order(ctx, n, pos, aux, dir, radiance, sampling_pdf, perm, inv, rec, cells,
+                              s);
+        if (e == hipSuccess)
+            e = fused_backward(ctx, n, pos, aux, dir, radiance, sampling_pdf, grad, loss_out,
+                               ordered ? perm : nullptr, ordered ? rec : nullptr, dgt, nullptr, s);
+    } catch (...) {
+        ctx->timing.enabled = timing;
+        return fail(NPM_ERR_HIP, "unexpected exception");
+    }
+    ctx->timing.enabled = timing;
+    if (e != hipSuccess) return hip_fail(e, "static backward");
+    return NPM_OK;
 }
 
 npm_status npm_loss(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,

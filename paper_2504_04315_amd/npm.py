@@ -83,7 +83,9 @@ SIGNATURES = {
     "npm_train_step_aux": [_P, _i64, _P, _P, _P, _P, _P, _P, _P],
     "npm_encode_aux": [_P, _i64, _P, _P, _P, _P],
     "npm_forward_raw_aux": [_P, _i64, _P, _P, _P, _P],
+    "npm_backward_static": [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _P],
 }
+STATIC_MAX_N = 32768
 
 _lib = None
 
@@ -219,6 +221,13 @@ class NPM:
         check(lib().npm_backward_aux(self._ctx, pos.shape[1], _ptr(pos), _ptr(aux), _ptr(dir),
                                      _ptr(radiance), _ptr(pdf), _ptr(grad), _ptr(loss),
                                      _stream(stream)))
+
+    def backward_static(self, pos, dir, radiance, pdf, grad=None, loss=None, stream=None,
+                        aux=None):
+        """npm_backward_static: npm_backward with no allocation (fixed scratch)."""
+        check(lib().npm_backward_static(self._ctx, pos.shape[1], _ptr(pos), _ptr(aux), _ptr(dir),
+                                        _ptr(radiance), _ptr(pdf), _ptr(grad), _ptr(loss),
+                                        _stream(stream)))
 
     def loss(self, pos, dir, radiance, pdf, out=None, stream=None, aux=None):
         import torch

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     names = set()
-    for h in ("npm.h",):
+    for h in ("npm.h", "npm_serve.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
         names |= set(re.findall(r"^\s*(?:npm_status|const char \*)\s*(npm_\w+)\s*\(", text, re.M))
     return names
@@ -29,6 +29,9 @@ def test_every_declared_symbol_is_exported():
     for n in sorted(names):
         assert hasattr(lib, n), n
     assert set(B.SIGNATURES) <= names
+    from paper_2504_04315_amd import serve as S
+    assert set(S.SIGNATURES) <= names
+    assert {"npm_server_create", "npm_submit_train", "npm_backward_static"} <= names
 
 
 def test_version_and_last_error():
