@@ -673,12 +673,21 @@ static double oracle_loss_grad_one(const npmo_net *net, const double *raw, const
     return g * lv;
 }
 
-/* Condition scale of d loss / d raw for one sample: each derivative of
- * oracle_loss_grad_one with its dot products and differences replaced by
- * sums of absolute values, times a factor for the relative error of the
- * responsibilities (log terms carry kappa times the rounding of mu.w) and for
- * the rounding of the raw outputs themselves (condition rawcond, amplified by
- * the head's sensitivity, of order 1 + kappa).                             */
+/* Condition scale of d loss / d raw for one sample: the first-order bound on
+ * the error of an FP32 evaluation, in units of the unit roundoff, from two
+ * independent sources, which add:
+ *   - rounding inside the head with exact raw outputs: each derivative of
+ *     oracle_loss_grad_one with its dot products and differences replaced by
+ *     sums of absolute values, times the relative error of the
+ *     responsibilities r_k = exp(t_k - log V).  The log term t_k carries
+ *     kappa_k (mu_k . w - 1), whose dot product rounds with an error of the
+ *     order of the unit roundoff, amplified by kappa_k, and log V carries
+ *     the r-weighted mean of those: relative error 1 + kappa_k + sum_j r_j
+ *     kappa_j;
+ *   - the raw outputs' own rounding (condition rawcond_i from the MLP
+ *     forward), carried through the head's Jacobian:
+ *     sum_i |d draw_j / d raw_i| rawcond_i, the Jacobian taken by central
+ *     differences of oracle_loss_grad_one in FP64.                         */
 static void oracle_head_cond(const npmo_net *net, const double *raw, const double *rawcond,
                              const double w3[3], double wgt, double invN, double *cdraw)
 {
@@ -690,14 +699,8 @@ static void oracle_head_cond(const npmo_net *net, const double *raw, const doubl
     oracle_map(net, raw, lob);
     double lv = oracle_logpdf(net, lob, w3, terms);
     double g = fabs(wgt * invN);
-    double rk_sum = 0.0, kmax = 0.0, cmax = 0.0;
-    for (int k = 0; k < K; ++k) {
-        double r = exp(terms[k] - lv);
-        rk_sum += r * lob[k].kappa;
-        if (lob[k].kappa > kmax) kmax = lob[k].kappa;
-    }
-    for (int j = 0; j < net->n_out; ++j) if (rawcond[j] > cmax) cmax = rawcond[j];
-    double input = 1.0 + (1.0 + kmax) * cmax;
+    double rk_sum = 0.0;
+    for (int k = 0; k < K; ++k) rk_sum += exp(terms[k] - lv) * lob[k].kappa;
     for (int k = 0; k < K; ++k) {
         const oracle_lobe *b = &lob[k];
         double r = exp(terms[k] - lv), kap = b->kappa;
@@ -707,11 +710,23 @@ static void oracle_head_cond(const npmo_net *net, const double *raw, const doubl
             a2 += fabs(b->t2[d] * w3[d]);
             am += fabs(b->mu[d] * w3[d]);
         }
-        double resp = (1.0 + kap + rk_sum) * input;
+        double resp = 1.0 + kap + rk_sum;
         cdraw[4 * k + 0] = g * r * kap * PI * b->theta * (1.0 - b->theta) * a1 * resp;
         cdraw[4 * k + 1] = g * r * kap * b->sinT * 2.0 * PI * b->phi * (1.0 - b->phi) * a2 * resp;
         cdraw[4 * k + 2] = g * r * (1.0 + 2.0 * kap / expm1(2.0 * kap) + kap * (am + 1.0)) * resp;
         cdraw[4 * k + 3] = g * (r + b->lambda) * resp;
+    }
+    double rp[4 * NPMO_MAX_LOBES], dp[4 * NPMO_MAX_LOBES], dm[4 * NPMO_MAX_LOBES];
+    for (int i = 0; i < net->n_out; ++i) {
+        if (rawcond[i] == 0.0) continue;
+        double h = 1e-5 * (fabs(raw[i]) > 1.0 ? fabs(raw[i]) : 1.0);
+        for (int j = 0; j < net->n_out; ++j) rp[j] = raw[j];
+        rp[i] = raw[i] + h;
+        oracle_loss_grad_one(net, rp, w3, wgt, invN, dp);
+        rp[i] = raw[i] - h;
+        oracle_loss_grad_one(net, rp, w3, wgt, invN, dm);
+        for (int j = 0; j < net->n_out; ++j)
+            cdraw[j] += fabs(dp[j] - dm[j]) / (2.0 * h) * rawcond[i];
     }
 }
 
@@ -784,19 +799,121 @@ static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, con
                 gcond[idx[l * 8 + b] * F + f] += cw[l * 8 + b] * cdelta[l * F + f];
 }
 
+/* The vertex loops of the backward run over contiguous ranges, one per
+ * thread; each thread adds into its own zeroed copy of the m accumulated
+ * arrays (thread 0 into the caller's), and the copies are then added to the
+ * caller's in thread order, so the sums do not depend on scheduling.  A copy
+ * costs time in proportion to the np parameters and a vertex a fixed amount
+ * of work (measured: about 4,000 times a parameter's share of allocating,
+ * zeroing and adding), so the batch takes about sqrt(4,000 n / (m np))
+ * threads, at least 256 vertices each, at most the OpenMP maximum.        */
+static int oracle_threads(int64_t n, int64_t np, int m)
+{
+    int64_t t = omp_get_max_threads();
+    if (t > n / 256) t = n / 256;
+    const double s = sqrt(4000.0 * (double)n / ((double)m * (double)(np > 0 ? np : 1)));
+    if ((double)t > s) t = (int64_t)s;
+    return t < 1 ? 1 : (int)t;
+}
+
+/* buf holds (T - 1) copies of each of the m accumulated arrays acc[0..m). */
+static void oracle_add_copies(int T, int m, double *const *acc, const double *buf, int64_t np)
+{
+    for (int a = 0; a < m; ++a) {
+        const double *b = buf + (size_t)a * (T - 1) * np;
+        double *d = acc[a];
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < np; ++k) {
+            double v = d[k];
+            for (int t = 1; t < T; ++t) v += b[(size_t)(t - 1) * np + k];
+            d[k] = v;
+        }
+    }
+}
+
 void npmo_backward_cond(const npmo_net *net, int64_t n, int64_t n_total, const float *pos,
                         const float *aux /* [7][n] or NULL */, const float *dir, const float *rad,
                         const float *spdf, const double *params,
                         double *gcond /* [n_params], accumulated */)
 {
     double invN = 1.0 / (double)n_total;
-    for (int64_t i = 0; i < n; ++i) {
-        float p3[3] = {pos[i], pos[n + i], pos[2 * n + i]}, a7[7];
-        double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
-        oracle_aux_fetch(aux, n, i, a7);
-        oracle_backward_cond_one(net, p3, a7, w3, oracle_weight(rad[i], spdf[i]), invN, params,
-                                 gcond);
+    int64_t np = net->n_params;
+    int T = oracle_threads(n, np, 1);
+    double *buf = T > 1 ? calloc((size_t)(T - 1) * np, sizeof(double)) : NULL;
+    if (!buf) T = 1;
+#pragma omp parallel num_threads(T)
+    {
+        int t = omp_get_thread_num();
+        double *gc = t == 0 ? gcond : buf + (size_t)(t - 1) * np;
+        for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i) {
+            float p3[3] = {pos[i], pos[n + i], pos[2 * n + i]}, a7[7];
+            double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
+            oracle_aux_fetch(aux, n, i, a7);
+            oracle_backward_cond_one(net, p3, a7, w3, oracle_weight(rad[i], spdf[i]), invN,
+                                     params, gc);
+        }
     }
+    if (T > 1) {
+        double *acc[1] = {gcond};
+        oracle_add_copies(T, 1, acc, buf, np);
+    }
+    free(buf);
+}
+
+/* One vertex of the backward: returns its loss term, adds its gradient
+ * contributions (and their magnitudes) into grad (gabs). */
+static double oracle_backward_one(const npmo_net *net, int64_t n, int64_t i, const float *pos,
+                                  const float *aux, const float *dir, const float *rad,
+                                  const float *spdf, const double *params, double invN,
+                                  double *grad, double *gabs, double *draw_out, double *dG_out)
+{
+    int L = net->n_levels, F = net->feat;
+    double G[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES], draw[4 * NPMO_MAX_LOBES];
+    double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
+    double delta[NPMO_MAX_WIDTH], prev[NPMO_MAX_WIDTH];
+    int64_t idx[NPMO_MAX_LEVELS * 8];
+    double cw[NPMO_MAX_LEVELS * 8];
+    float px = pos[i], py = pos[n + i], pz = pos[2 * n + i], a7[7];
+    oracle_aux_fetch(aux, n, i, a7);
+    oracle_encode_one(net, px, py, pz, params, G, NULL);
+    oracle_aux_one(net, a7, G, NULL);
+    oracle_mlp_one(net, G, params, acts, raw, NULL);
+    double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
+    double loss = oracle_loss_grad_one(net, raw, w3, oracle_weight(rad[i], spdf[i]), invN, draw);
+    if (draw_out) for (int j = 0; j < net->n_out; ++j) draw_out[i * net->n_out + j] = draw[j];
+    /* delta holds dLoss/d(output of layer i), i from last to first.        */
+    for (int j = 0; j < net->n_out; ++j) delta[j] = draw[j];
+    for (int li = net->n_layers - 1; li >= 0; --li) {
+        const double *W = params + net->layer_offset[li];
+        double *dW = grad + net->layer_offset[li];
+        double *aW = gabs ? gabs + net->layer_offset[li] : NULL;
+        int nin = net->layer_in[li], nout = net->layer_out[li];
+        /* hidden layer outputs pass through ReLU: derivative 0 at 0         */
+        if (li < net->n_layers - 1)
+            for (int o = 0; o < nout; ++o) if (!(acts[li + 1][o] > 0.0)) delta[o] = 0.0;
+        for (int o = 0; o < nout; ++o)
+            for (int k = 0; k < nin; ++k) {
+                double t = delta[o] * acts[li][k];
+                dW[(int64_t)o * nin + k] += t;
+                if (aW) aW[(int64_t)o * nin + k] += fabs(t);
+            }
+        for (int k = 0; k < nin; ++k) {
+            double s = 0.0;
+            for (int o = 0; o < nout; ++o) s += W[(int64_t)o * nin + k] * delta[o];
+            prev[k] = s;
+        }
+        for (int k = 0; k < nin; ++k) delta[k] = prev[k];
+    }
+    if (dG_out) for (int j = 0; j < net->n_in; ++j) dG_out[i * net->n_in + j] = delta[j];
+    oracle_corners_one(net, px, py, pz, idx, cw);
+    for (int l = 0; l < L; ++l)
+        for (int b = 0; b < 8; ++b)
+            for (int f = 0; f < F; ++f) {
+                double t = cw[l * 8 + b] * delta[l * F + f];
+                grad[idx[l * 8 + b] * F + f] += t;
+                if (gabs) gabs[idx[l * 8 + b] * F + f] += fabs(t);
+            }
+    return loss;
 }
 
 double npmo_backward(const npmo_net *net, int64_t n, int64_t n_total, const float *pos,
@@ -805,55 +922,32 @@ double npmo_backward(const npmo_net *net, int64_t n, int64_t n_total, const floa
                      double *grad /* [n_params] */, double *gabs /* [n_params] or NULL */,
                      double *draw_out /* [n][4K] or NULL */, double *dG_out /* [n][n_in] or NULL */)
 {
-    int L = net->n_levels, F = net->feat;
-    double invN = 1.0 / (double)n_total, loss = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        double G[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES], draw[4 * NPMO_MAX_LOBES];
-        double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
-        double delta[NPMO_MAX_WIDTH], prev[NPMO_MAX_WIDTH];
-        int64_t idx[NPMO_MAX_LEVELS * 8];
-        double cw[NPMO_MAX_LEVELS * 8];
-        float px = pos[i], py = pos[n + i], pz = pos[2 * n + i], a7[7];
-        oracle_aux_fetch(aux, n, i, a7);
-        oracle_encode_one(net, px, py, pz, params, G, NULL);
-        oracle_aux_one(net, a7, G, NULL);
-        oracle_mlp_one(net, G, params, acts, raw, NULL);
-        double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
-        loss += oracle_loss_grad_one(net, raw, w3, oracle_weight(rad[i], spdf[i]), invN, draw);
-        if (draw_out) for (int j = 0; j < net->n_out; ++j) draw_out[i * net->n_out + j] = draw[j];
-        /* delta holds dLoss/d(output of layer i), i from last to first.    */
-        for (int j = 0; j < net->n_out; ++j) delta[j] = draw[j];
-        for (int li = net->n_layers - 1; li >= 0; --li) {
-            const double *W = params + net->layer_offset[li];
-            double *dW = grad + net->layer_offset[li];
-            double *aW = gabs ? gabs + net->layer_offset[li] : NULL;
-            int nin = net->layer_in[li], nout = net->layer_out[li];
-            /* hidden layer outputs pass through ReLU: derivative 0 at 0     */
-            if (li < net->n_layers - 1)
-                for (int o = 0; o < nout; ++o) if (!(acts[li + 1][o] > 0.0)) delta[o] = 0.0;
-            for (int o = 0; o < nout; ++o)
-                for (int k = 0; k < nin; ++k) {
-                    double t = delta[o] * acts[li][k];
-                    dW[(int64_t)o * nin + k] += t;
-                    if (aW) aW[(int64_t)o * nin + k] += fabs(t);
-                }
-            for (int k = 0; k < nin; ++k) {
-                double s = 0.0;
-                for (int o = 0; o < nout; ++o) s += W[(int64_t)o * nin + k] * delta[o];
-                prev[k] = s;
-            }
-            for (int k = 0; k < nin; ++k) delta[k] = prev[k];
-        }
-        if (dG_out) for (int j = 0; j < net->n_in; ++j) dG_out[i * net->n_in + j] = delta[j];
-        oracle_corners_one(net, px, py, pz, idx, cw);
-        for (int l = 0; l < L; ++l)
-            for (int b = 0; b < 8; ++b)
-                for (int f = 0; f < F; ++f) {
-                    double t = cw[l * 8 + b] * delta[l * F + f];
-                    grad[idx[l * 8 + b] * F + f] += t;
-                    if (gabs) gabs[idx[l * 8 + b] * F + f] += fabs(t);
-                }
+    double invN = 1.0 / (double)n_total;
+    int64_t np = net->n_params;
+    int m = gabs ? 2 : 1;
+    int T = oracle_threads(n, np, m);
+    double tloss[256];
+    if (T > 256) T = 256;
+    double *buf = T > 1 ? calloc((size_t)m * (T - 1) * np, sizeof(double)) : NULL;
+    if (!buf) T = 1;
+#pragma omp parallel num_threads(T)
+    {
+        int t = omp_get_thread_num();
+        double *g = t == 0 ? grad : buf + (size_t)(t - 1) * np;
+        double *a = !gabs ? NULL : (t == 0 ? gabs : buf + (size_t)(T - 1 + t - 1) * np);
+        double l = 0.0;
+        for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i)
+            l += oracle_backward_one(net, n, i, pos, aux, dir, rad, spdf, params, invN, g, a,
+                                     draw_out, dG_out);
+        tloss[t] = l;
     }
+    double loss = 0.0;
+    for (int t = 0; t < T; ++t) loss += tloss[t];
+    if (T > 1) {
+        double *acc[2] = {grad, gabs};
+        oracle_add_copies(T, m, acc, buf, np);
+    }
+    free(buf);
     return loss;
 }
 
@@ -882,6 +976,14 @@ void npmo_adam(int64_t np, double *params, const double *grad, double *m, double
 void npmo_ema(int64_t np, double *ema, const double *params, double decay)
 {
     for (int64_t i = 0; i < np; ++i) ema[i] = decay * ema[i] + (1.0 - decay) * params[i];
+}
+
+/* Threads npmo_backward runs a batch of n vertices on (with_abs: also the
+ * magnitudes), and npmo_backward_cond (with_abs = 0).                     */
+int npmo_backward_threads(const npmo_net *net, int64_t n, int with_abs)
+{
+    int T = oracle_threads(n, net->n_params, with_abs ? 2 : 1);
+    return T > 256 ? 256 : T;
 }
 
 /* Thread count of the OpenMP loops (timing of the oracle on one core);

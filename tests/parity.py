@@ -15,11 +15,17 @@ to the (possibly cancelled) result:
   oracle's sample when each raw output moves by its own 1e-5 tolerance,
   except samples whose CDF margin is below 1e-5, where FP32 and FP64 may
   pick different lobes;
+* sample pdf: the log-pdf bound at the sample plus the sample's own move
+  (its bound above) through the gradient of log V in the direction;
 * gradients: |d| <= 1e-5 * cond, where cond is the oracle's condition scale
-  of the entry: the sizes of all the terms an FP32 evaluation rounds,
-  propagated from the KL-gradient head through the MLP and the scatter
-  (sums of many signed terms -- dG = W^T delta, the atomic sums over
-  vertices -- have errors proportional to them, not to the result).
+  of the entry: the first-order bound on an FP32 evaluation's error in
+  units of the unit roundoff -- the sizes of all the terms it rounds,
+  propagated from the KL-gradient head (its own rounding, amplified by
+  kappa, plus the raw outputs' rounding through the head's Jacobian)
+  through the MLP and the scatter (sums of many signed terms -- dG =
+  W^T delta, the atomic sums over vertices -- have errors proportional to
+  them, not to the result).  Its size against an FP32 evaluation's actual
+  errors is pinned on the CPU (tests/test_oracle_cond.py).
 """
 import numpy as np
 
@@ -89,6 +95,31 @@ def sample_bound(O, net, raw, raw_scale, u, base=2e-5, rtol=RTOL):
         w1, _ = O.sample_raw(net, r, u)
         b += np.abs(w1 - w0).max(axis=1)
     return b
+
+
+def sample_logpdf_bound(O, net, raw, sdir, sb, lp_bound, kappa_max, h=1e-6):
+    """Bound on |log V_gpu(w_gpu) - log V_ref(w_ref)| for a sample: the
+    log-density's own bound at the sample, plus the move of the sample
+    itself, |w_gpu - w_ref| <= sqrt(3) sb (sb bounds each component),
+    through the gradient of log V in the direction (central differences of
+    the oracle's log-density in FP64), and the second-order term with the
+    Hessian bounded by kappa_max^2."""
+    g = np.zeros_like(sdir)
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = h
+        g[:, d] = (O.logpdf(net, raw, sdir + e) - O.logpdf(net, raw, sdir - e)) / (2.0 * h)
+    move = np.sqrt(3.0) * sb
+    return lp_bound + np.linalg.norm(g, axis=1) * move + 0.5 * kappa_max ** 2 * move ** 2
+
+
+def cond_quantiles(cond, gabs):
+    """cond / sum|contributions| at the median and the 99th percentile."""
+    nz = gabs > 0
+    if not nz.any():
+        return "cond/gabs: no contributions"
+    q = np.quantile(cond[nz] / gabs[nz], [0.5, 0.99])
+    return f"cond/gabs median {q[0]:.3g}, p99 {q[1]:.3g}"
 
 
 def check_grads(name, got, ref, gabs, rtol=RTOL, atol=1e-12):

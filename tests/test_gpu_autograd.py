@@ -191,4 +191,7 @@ def test_twin_training_run(O, torch):
         json.dump(dict(gpu=dev_losses.tolist(), oracle=ref_losses.tolist()),
                   open(os.path.join(out, "cfg4_twin.json"), "w"))
     assert dev_losses[0] == pytest.approx(ref_losses[0], rel=1e-5)
-    assert dev_max < 0.05 * abs(ref_losses[0])
+    # a correct pair of runs stays within 4.1e-4 over the 200 steps (they
+    # part only where Adam's sign-like early steps take a near-zero gradient
+    # either way); a few times that is the bar
+    assert dev_max < 2e-3

@@ -91,9 +91,11 @@ def check_query(O, torch, model, on, params, batch, idx=None, seed=11, sid=3, au
                                 np.repeat(sb[:, None], 3, axis=1)))
     _, d2 = O.loss_grad(on, q["raw"][keep], q["sdir"][keep].T.astype(np.float32), ones[keep],
                         ones[keep], n_total=1)
+    lb2 = P.logpdf_bound(d2, raw_scale[keep], kmax[keep])
     msgs.append(P.check_logpdf("sample_pdf", out["sample_pdf"].cpu().numpy()[sel][keep],
                                q["slogpdf"][keep],
-                               P.logpdf_bound(d2, raw_scale[keep], kmax[keep]) + 1e-4))
+                               P.sample_logpdf_bound(O, on, q["raw"][keep], q["sdir"][keep], sb,
+                                                     lb2, kmax[keep])))
     return msgs, q
 
 
@@ -159,7 +161,9 @@ def check_backward(O, torch, model, on, params, batch, tag, aux=None):
     g = grad.cpu().numpy().astype(np.float64)
     gp = on.grid_params
     msgs = [P.check_grads(f"{tag} grad(grid)", g[:gp], ref["grad"][:gp], ref["cond"][:gp]),
-            P.check_grads(f"{tag} grad(mlp)", g[gp:], ref["grad"][gp:], ref["cond"][gp:])]
+            P.check_grads(f"{tag} grad(mlp)", g[gp:], ref["grad"][gp:], ref["cond"][gp:]),
+            f"{tag} grid " + P.cond_quantiles(ref["cond"][:gp], ref["gabs"][:gp]),
+            f"{tag} mlp " + P.cond_quantiles(ref["cond"][gp:], ref["gabs"][gp:])]
     lv = float(loss.cpu().numpy()[0])
     assert abs(lv - ref["loss"]) <= 1e-5 * max(1.0, abs(ref["loss"])), (lv, ref["loss"])
     msgs.append(f"{tag} loss {lv:.9g} vs oracle {ref['loss']:.9g}")
