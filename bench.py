@@ -122,51 +122,87 @@ def parse():
 
 
 def cpu_baseline(netcfg, batch, params, seconds):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload:
-    query (OpenMP over vertices) and backward (serial) on vertex subsets,
-    Adam over every parameter; scaled to vertices per second of a step."""
+    """The FP64 oracle, as it stands, on the host cores.  Query (OpenMP over
+    vertices) and training step (the backward over one contiguous vertex
+    range per thread, then Adam over every parameter), each timed with all
+    cores and with one thread, on bounded samples of the bench's 2^20-vertex
+    batch, and on cfg1's whole 16,384-vertex batch; the headline value is
+    the all-core rate of a whole step (query + training) on the bench batch."""
     from oracle import oracle as O
-    on = O.Net(netcfg.n_levels, netcfg.feat, netcfg.base_res, netcfg.max_res,
-               netcfg.log2_table, netcfg.dense_only, netcfg.n_hidden, netcfg.width,
-               netcfg.n_lobes)
+    from paper_2504_04315_amd import workload as W
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # calibrate on small samples, then size them to the time budget
-    def t_query(m):
-        sub = batch.subset(np.arange(m))
+    old = O.set_threads(threads)
+
+    def onet(c):
+        return O.Net(c.n_levels, c.feat, c.base_res, c.max_res, c.log2_table, c.dense_only,
+                     c.n_hidden, c.width, c.n_lobes)
+
+    def t_query(on, b, p, m):
+        sub = b.subset(np.arange(m))
         t0 = time.perf_counter()
-        O.query(on, sub.pos, params, dirs=sub.dir, seed=1, stream=0)
+        O.query(on, sub.pos, p, dirs=sub.dir, seed=1, stream=0)
+        return (time.perf_counter() - t0) / m
+
+    def t_backward(on, b, p, m):
+        sub = b.subset(np.arange(m))
+        t0 = time.perf_counter()
+        O.backward(on, sub.pos, sub.dir, sub.radiance, sub.pdf, p, n_total=b.n, with_abs=False)
+        return (time.perf_counter() - t0) / m
+
+    def t_adam(p):
+        q, g, m, v = p.copy(), np.zeros_like(p), np.zeros_like(p), np.zeros_like(p)
+        t0 = time.perf_counter()
+        O.adam(q, g, m, v, 1, 1e-2)
         return time.perf_counter() - t0
 
-    def t_backward(m):
-        sub = batch.subset(np.arange(m))
-        t0 = time.perf_counter()
-        O.backward(on, sub.pos, sub.dir, sub.radiance, sub.pdf, params, n_total=batch.n,
-                   with_abs=False)
-        return time.perf_counter() - t0
+    def legs(on, b, p, budget, th):
+        """Per-vertex query and backward times on samples sized to the budget."""
+        O.set_threads(th)
+        q0 = t_query(on, b, p, min(b.n, 4096 * th))
+        b0 = t_backward(on, b, p, min(b.n, 1024 * th))
+        mq = int(min(b.n, max(4096, 0.2 * budget / q0)))
+        mb = int(min(b.n, max(1024, 0.8 * budget / b0)))
+        return (t_query(on, b, p, mq), mq), (t_backward(on, b, p, mb), mb)
 
-    q0, b0 = t_query(8192) / 8192, t_backward(4096) / 4096
-    mq = int(min(batch.n, max(8192, 0.2 * seconds / q0)))
-    mb = int(min(batch.n, max(4096, 0.8 * seconds / b0)))
-    tq, tb = t_query(mq), t_backward(mb)
-    old = O.set_threads(1)
-    m1 = max(4096, min(mq, int(0.1 * seconds / (q0 * threads))))
-    tq1 = t_query(m1)
+    out = {"unit": "vertices/s", "kind": "oracle", "cores": threads}
+    on2 = onet(netcfg)
+    ta2 = t_adam(params)
+    rows = {}
+    for th in (threads, 1):
+        (q, mq), (bw, mb) = legs(on2, batch, params, seconds * (0.7 if th > 1 else 0.2), th)
+        rows[th] = dict(query_vertices_per_s=1.0 / q, train_vertices_per_s=1.0 / (bw + ta2 / batch.n),
+                        query_sample=mq, train_sample=mb,
+                        backward_threads=O.backward_threads(on2, mb, False))
+    b1 = W.make_batch("cube", W.N_CFG1, seed=1)
+    on1 = onet(W.CFG1)
+    rng = np.random.default_rng(1)
+    p1 = np.zeros(on1.n_params)
+    p1[:on1.grid_params] = rng.normal(0, 1e-2, on1.grid_params)
+    for i, (o, k) in enumerate(on1.layer_shape):
+        a = math.sqrt(6.0 / (o + k))
+        p1[on1.layer_offset[i]:on1.layer_offset[i] + o * k] = rng.uniform(-a, a, o * k)
+    ta1 = t_adam(p1)
+    cfg1 = {}
+    for th in (threads, 1):
+        O.set_threads(th)
+        q = t_query(on1, b1, p1, b1.n)
+        bw = t_backward(on1, b1, p1, b1.n)
+        cfg1[str(th)] = dict(query_vertices_per_s=1.0 / q,
+                             train_vertices_per_s=1.0 / (bw + ta1 / b1.n),
+                             backward_threads=O.backward_threads(on1, b1.n, False))
     O.set_threads(old)
-    p = params.copy()
-    g = np.zeros_like(p)
-    m = np.zeros_like(p)
-    v = np.zeros_like(p)
-    t0 = time.perf_counter()
-    O.adam(p, g, m, v, 1, 1e-2)
-    ta = time.perf_counter() - t0
-    per_vertex = tq / mq + tb / mb + ta / batch.n
-    return {"value": 1.0 / per_vertex, "unit": "vertices/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle query on {mq} vertices ({threads} OpenMP threads, {tq:.2f} s), "
-                      f"backward on {mb} vertices (serial, {tb:.2f} s), Adam over all "
-                      f"{p.size} parameters ({ta:.2f} s), of the same 2^20-vertex batch; "
-                      f"per-vertex times summed and inverted",
-            "query_vertices_per_s": mq / tq, "train_vertices_per_s": 1.0 / (tb / mb + ta / batch.n),
-            "query_vertices_per_s_1_thread": m1 / tq1}
+    a = rows[threads]
+    out["value"] = 1.0 / (1.0 / a["query_vertices_per_s"] + 1.0 / a["train_vertices_per_s"])
+    out["sample"] = (f"the 2^20-vertex bench batch: query of {a['query_sample']} vertices and "
+                     f"backward of {a['train_sample']} ({threads} OpenMP threads; the backward "
+                     f"ran on {a['backward_threads']}), Adam over all {params.size} parameters "
+                     f"(one thread, {ta2:.2f} s); per-vertex times summed and inverted; one-thread "
+                     f"rates from smaller samples; cfg1 whole (16,384 vertices)")
+    out["cfg2"] = {str(k): v for k, v in rows.items()}
+    out["cfg1"] = cfg1
+    out["query_vertices_per_s"] = a["query_vertices_per_s"]
+    out["train_vertices_per_s"] = a["train_vertices_per_s"]
+    return out
 
 
 def serving_bench(n_sessions=32, per_session=6, load=0.7, sweep=(0.3, 0.9)):

@@ -71,6 +71,8 @@ def lib():
         L.npmo_adam.argtypes = [i64, P, P, P, P, i64, C.c_double, C.c_double, C.c_double,
                                 C.c_double]
         L.npmo_ema.argtypes = [i64, P, P, C.c_double]
+        L.npmo_backward_threads.argtypes = [P, i64, i32]
+        L.npmo_backward_threads.restype = i32
         L.npmo_set_threads.argtypes = [C.c_int]
         L.npmo_set_threads.restype = C.c_int
         _lib = L
@@ -305,6 +307,11 @@ def ema(avg, params, decay):
     for a in (avg, params):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().npmo_ema(avg.size, _p(avg), _p(params), decay)
+
+
+def backward_threads(net, n, with_abs=True):
+    """Threads the oracle's backward runs a batch of n vertices on."""
+    return lib().npmo_backward_threads(net.ref, n, int(with_abs))
 
 
 def set_threads(n):

@@ -15,6 +15,8 @@ import numpy as np
 import pytest
 import torch
 
+from paper_2504_04315_amd import workload as W
+
 
 def _head_case(rng, n=40):
     raw = rng.normal(size=(n, 32))
@@ -201,3 +203,32 @@ def test_ema_closed_forms(O):
         O.ema(e, np.full(3, float(t)), d)
     ref = sum((1 - d) * d ** (T - t) * t for t in range(1, T + 1))
     np.testing.assert_allclose(e, ref, rtol=1e-13)
+
+
+@pytest.mark.parametrize("with_abs", [False, True])
+def test_parallel_backward_equals_serial(O, with_abs):
+    """The backward and its condition scales on several threads (contiguous
+    vertex ranges, per-thread sums added in thread order) equal the serial
+    loop up to the order of FP64 additions."""
+    net = W.TINY
+    on = O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table,
+               net.dense_only, net.n_hidden, net.width, net.n_lobes)
+    rng = np.random.default_rng(17)
+    params = rng.normal(0, 0.3, on.n_params)
+    b = W.make_batch("cube", 4000, seed=17)
+    old = O.set_threads(1)
+    try:
+        s = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, params, with_abs=with_abs)
+        sc = O.backward_cond(on, b.pos, b.dir, b.radiance, b.pdf, params)
+        O.set_threads(4)
+        assert O.backward_threads(on, b.n, with_abs) == 4
+        p = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, params, with_abs=with_abs)
+        pc = O.backward_cond(on, b.pos, b.dir, b.radiance, b.pdf, params)
+    finally:
+        O.set_threads(old)
+    scale = s["gabs"] if with_abs else np.abs(s["grad"]).max()
+    np.testing.assert_allclose(p["grad"], s["grad"], rtol=0, atol=1e-12 * np.max(scale))
+    if with_abs:
+        np.testing.assert_allclose(p["gabs"], s["gabs"], rtol=1e-12)
+    np.testing.assert_allclose(pc, sc, rtol=1e-12)
+    assert p["loss"] == pytest.approx(s["loss"], rel=1e-13)
