@@ -13,6 +13,8 @@
 // accumulation; mappings, softmax, log-density and sampling in FP32.
 #pragma once
 
+#include <type_traits>
+
 #include "device_math.h"
 
 namespace npm {
@@ -545,6 +547,39 @@ __device__ __forceinline__ int64_t visit(const uint32_t *perm, int64_t v)
 // batch this covers the coarse levels, where the 32 vertices of a tile share
 // most corners.  The cell lookup is monotone in the position, so every corner
 // lies in the window; a corner that did not would take the direct path.
+//
+// Window sums (WT): FP64, or (WT = int) 32-bit fixed point, which keeps the
+// precision form free of FP64 and of FP32 LDS atomics (slow on this chip).
+// In fixed point each level gets a power-of-two scale from the largest |dG|
+// of its rows in the tile: with max |dG| < 2^e every contribution w dG
+// (w <= 1) is below 2^e, at most 32 of them land on one lattice point (one
+// per vertex of the tile), so at the scale 2^(25 - e) every sum stays below
+// 2^30; each contribution is rounded to a multiple of 2^(e - 25) and the sum
+// is exact, independent of the order of the adds.
+template <typename WT> struct WinScale {
+    __device__ __forceinline__ WT enc(float v) const { return WT(v); }
+    __device__ __forceinline__ float dec(WT s) const { return (float)s; }
+};
+template <> struct WinScale<int> {
+    int k = 0;                               // the scale is 2^k (ldexp: no overflow of 2^k itself)
+    // the scale of level l from its F rows of the tile's dG (all lanes call
+    // it); false when they are all zero
+    template <int F>
+    __device__ __forceinline__ bool set_level(const float *dGt, int l, int lane)
+    {
+        float m = 0.0f;
+        for (int i = lane; i < F * 32; i += 64) m = fmaxf(m, fabsf(dGt[(l * F + i / 32) * kStride + (i & 31)]));
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        if (!(m > 0.0f)) return false;
+        int e;
+        frexpf(m, &e);                       // m < 2^e
+        k = 25 - e;
+        return true;
+    }
+    __device__ __forceinline__ int enc(float v) const { return (int)rintf(ldexpf(v, k)); }
+    __device__ __forceinline__ float dec(int s) const { return ldexpf((float)s, -k); }
+};
 
 template <int F, int WIN_PTS, typename WT = float>
 __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dGt,
@@ -595,6 +630,11 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
             use_win = ex <= WIN_PTS && ey <= WIN_PTS && ez <= WIN_PTS &&
                       ex * ey <= WIN_PTS && ex * ey * ez <= WIN_PTS;
         }
+        WinScale<WT> sc;
+        if constexpr (std::is_same<WT, int>::value) {
+            // a level whose dG rows are all zero has nothing to scatter
+            if (use_win && !sc.template set_level<F>(dGt, l, lane)) continue;
+        }
         if (use_win) {
             const int nw = ex * ey * ez * F;
             for (int i = lane; i < nw; i += 64) win[i] = WT(0);
@@ -615,7 +655,7 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
             const float w = (bx ? fx : 1.0f - fx) * (by ? fy : 1.0f - fy) * (bz ? fz : 1.0f - fz);
             const uint32_t wx = X - (uint32_t)x0, wy = Y - (uint32_t)y0, wz = Z - (uint32_t)z0;
             if (use_win && wx < (uint32_t)ex && wy < (uint32_t)ey && wz < (uint32_t)ez)
-                __hip_atomic_fetch_add(win + ((wz * ey + wy) * ex + wx) * F + f, WT(w * d),
+                __hip_atomic_fetch_add(win + ((wz * ey + wy) * ex + wx) * F + f, sc.enc(w * d),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             else
                 unsafeAtomicAdd(grad + (size_t)entry(X, Y, Z) * F + f, w * d);
@@ -629,7 +669,7 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
                     const int p = i / F, pf = i % F;
                     const int pyz = p / ex, wx = p - pyz * ex, wz = pyz / ey, wy = pyz - wz * ey;
                     unsafeAtomicAdd(grad + (size_t)entry(x0 + wx, y0 + wy, z0 + wz) * F + pf,
-                                    (float)s);
+                                    sc.dec(s));
                 }
             }
             wave_lds_fence();
@@ -750,17 +790,19 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
         for (int a = 0; a < DGR / 2; ++a) dst[nf(h, a) * 32] = dG[a];
     } else {
         // ---- grid scatter, coalesced: dG through the wave's LDS buffer, the
-        // rows above it as the aggregation window (FP64 sums: LDS FP64 atomic
-        // adds run several times faster than FP32 ones on this chip)
+        // rows above it as the aggregation window: FP64 sums (LDS FP64 atomic
+        // adds run several times faster than FP32 ones on this chip), or in
+        // the precision form 32-bit fixed point (no FP64)
+        using WinT = typename std::conditional<BF, int, double>::type;
         constexpr int WIN_PTS = (HID_P - OUT0) * kStride / (2 * F);
         float lo[3], hi[3];
         if constexpr (WIN_PTS > 0) tile_bbox(px, py, pz, lo, hi);
         wave_lds_fence();
         t32_to_lds<OUT0 / 2>(tbuf, dG, lane);
         wave_lds_fence();
-        scatter_tile<F, WIN_PTS, double>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad, lo, hi,
-                                         reinterpret_cast<double *>(tbuf + OUT0 * kStride),
-                                         io.rec, io.rec_stride);
+        scatter_tile<F, WIN_PTS, WinT>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad, lo, hi,
+                                       reinterpret_cast<WinT *>(tbuf + OUT0 * kStride), io.rec,
+                                       io.rec_stride);
     }
 }
 

@@ -15,13 +15,16 @@
 //   place   the chunk's items, ordered by bin in LDS and written out as
 //           contiguous runs: F values w * dG (FP32) and, in an array of its
 //           own, the 16-bit entry within the slice
-//   reduce  one block per bin: FP64 LDS accumulation of its items, then one
+//   reduce  one block per bin: LDS accumulation of its items -- FP64, or in
+//           the precision form 64-bit fixed point (no FP64) -- then one
 //           coalesced read-add-write of the slice into the gradient
 //
 // Items are recomputed identically by count and place (same inputs, same
 // arithmetic), so place fills each chunk's run exactly; every LDS and global
 // index is still checked against its buffer.  The values are those of the
 // atomic scatter (w * dG with the same w), summed in another order.
+#include <type_traits>
+
 #include "device_math.h"
 
 namespace npm {
@@ -86,11 +89,14 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_count(GridDesc g, BinDesc bd,
                                                          const float *__restrict__ rec,
                                                          int rec_stride,
                                                          const float *__restrict__ dgt, int rows,
-                                                         uint32_t *__restrict__ cnt)
+                                                         uint32_t *__restrict__ cnt,
+                                                         uint32_t *__restrict__ cmax)
 {
     __shared__ uint32_t hist[kBinMaxBins];
     __shared__ int s_lv[NPM_MAX_LEVELS], s_res[NPM_MAX_LEVELS];
+    __shared__ uint32_t s_max;
     for (int k = threadIdx.x; k < bd.nbins; k += kBinChunk) hist[k] = 0u;
+    if (threadIdx.x == 0) s_max = 0u;
     if (threadIdx.x < NPM_MAX_LEVELS) {
         s_lv[threadIdx.x] = bd.lv[threadIdx.x];
         s_res[threadIdx.x] = g.res[threadIdx.x];
@@ -99,6 +105,7 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_count(GridDesc g, BinDesc bd,
     if (blockIdx.x == 0 && threadIdx.x == 0) cnt[(size_t)bd.nbins * bd.n_chunks] = 0u;
     __syncthreads();
     const int64_t s = blockIdx.x * (int64_t)kBinChunk + threadIdx.x;
+    float dmax = 0.0f;      // largest |dG| the chunk bins (bounds every item)
     if (s < n) {
         float p[3];
         slot_position(pos, perm, rec, rec_stride, n, s, p);
@@ -106,6 +113,8 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_count(GridDesc g, BinDesc bd,
             const int l = s_lv[j];
             float d[F];
             if (!slot_dg<F>(dgt, rows, s, l, d)) continue;
+#pragma unroll
+            for (int f = 0; f < F; ++f) dmax = fmaxf(dmax, fabsf(d[f]));
             int c[3];
             float fr[3];
 #pragma unroll
@@ -118,9 +127,12 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_count(GridDesc g, BinDesc bd,
             }
         }
     }
+    // non-negative floats order as their bit patterns
+    atomicMax(&s_max, __float_as_uint(dmax));
     __syncthreads();
     for (int k = threadIdx.x; k < bd.nbins; k += kBinChunk)
         cnt[(size_t)k * bd.n_chunks + blockIdx.x] = hist[k];
+    if (threadIdx.x == 0) cmax[blockIdx.x] = s_max;
 }
 
 // Exclusive prefix sum of m counters: per block of 1024, then over the block
@@ -145,13 +157,23 @@ __global__ __launch_bounds__(1024) void k_bin_scan_local(uint32_t *__restrict__ 
     if (i < m) v[i] = wsum[wave] + inc - x;
 }
 
-__global__ __launch_bounds__(1024) void k_bin_scan_totals(uint32_t *__restrict__ totals, int nblk)
+// (The same single block also reduces the chunks' largest |dG| to the
+// batch's, cmax[n_chunks], which scales the fixed-point reduce.)
+__global__ __launch_bounds__(1024) void k_bin_scan_totals(uint32_t *__restrict__ totals, int nblk,
+                                                          uint32_t *__restrict__ cmax,
+                                                          int64_t n_chunks)
 {
     __shared__ uint32_t wsum[16];
-    __shared__ uint32_t carry;
+    __shared__ uint32_t carry, bmax;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    if (t == 0) carry = 0u;
+    if (t == 0) {
+        carry = 0u;
+        bmax = 0u;
+    }
     __syncthreads();
+    uint32_t mx = 0u;
+    for (int64_t i = t; i < n_chunks; i += 1024) mx = max(mx, cmax[i]);
+    atomicMax(&bmax, mx);
     for (int base = 0; base < nblk; base += 1024) {
         const int i = base + t;
         const uint32_t x = i < nblk ? totals[i] : 0u;
@@ -170,6 +192,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan_totals(uint32_t *__restrict__
         if (t == 1023) carry = c + wsum[15] + inc;
         __syncthreads();
     }
+    if (t == 0) cmax[n_chunks] = bmax;
 }
 
 __global__ __launch_bounds__(1024) void k_bin_scan_add(uint32_t *__restrict__ v, int64_t m,
@@ -274,33 +297,56 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
     }
 }
 
-// One block per bin: the slice's sums in LDS, accumulated in FP64 (LDS FP64
-// atomic adds run several times faster than FP32 ones on this chip, and the
-// wider sum rounds once, when it is added to the FP32 gradient), then one
-// coalesced read-add-write of the slice into the gradient.
-template <int F>
+// One block per bin: the slice's sums in LDS, then one coalesced
+// read-add-write of the slice into the gradient.  The sums are FP64 (LDS
+// FP64 atomic adds run several times faster than FP32 ones on this chip, and
+// the wider sum rounds once, when it is added to the FP32 gradient), or, in
+// the precision form (FIXED), 64-bit fixed point: with every item below the
+// batch's largest |dG|, M < 2^e, and c items in the bin (c <= 2^b), the scale
+// 2^(62 - e - b) keeps every entry's sum below 2^62; each item is rounded to
+// a multiple of 2^(e + b - 62) (below 1e-12 of M for any bin of at most 2^23
+// items) and the sum is exact in any order.
+template <int F, bool FIXED>
 __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, BinDesc bd,
                                                                   const uint32_t *__restrict__ off,
                                                                   const uint32_t *__restrict__ items,
+                                                                  const uint32_t *__restrict__ bmax,
                                                                   float *__restrict__ grad)
 {
     constexpr int NT = kBinReduceThreads, U = kBinReduceBatch;
-    __shared__ double acc[kBinSliceFloats];
+    using AccT = typename std::conditional<FIXED, unsigned long long, double>::type;
+    __shared__ AccT acc[kBinSliceFloats];
     const float *vals = reinterpret_cast<const float *>(items);
     const uint16_t *ents = reinterpret_cast<const uint16_t *>(vals + (size_t)bd.cap * F);
     const int k = blockIdx.x, j = k / bd.ns, slice = k - j * bd.ns;
     const uint32_t S = 1u << bd.log2s;
     const int nf = (int)S * F;
-    for (int i = threadIdx.x; i < nf; i += NT) acc[i] = 0.0;
-    __syncthreads();
     const uint64_t beg = off[(size_t)k * bd.n_chunks];
     const uint64_t end = min(off[(size_t)(k + 1) * bd.n_chunks], (uint32_t)bd.cap);
+    int kx = 0;                                  // fixed point: the scale is 2^kx
+    if constexpr (FIXED) {
+        const float M = __uint_as_float(*bmax);
+        if (!(M > 0.0f) || end <= beg) return;   // nothing to add (block-uniform)
+        int e;
+        frexpf(M, &e);                           // M < 2^e
+        const uint64_t c = end - beg;
+        const int b = c > 1 ? 64 - __clzll((long long)(c - 1)) : 0;   // c <= 2^b
+        kx = 62 - e - b;
+    }
+    for (int i = threadIdx.x; i < nf; i += NT) acc[i] = AccT(0);
+    __syncthreads();
     auto add = [&](uint32_t e, const float *v) {
         if (e < S) {
 #pragma unroll
-            for (int f = 0; f < F; ++f)
-                __hip_atomic_fetch_add(&acc[e * F + f], (double)v[f], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int f = 0; f < F; ++f) {
+                if constexpr (FIXED)
+                    __hip_atomic_fetch_add(&acc[e * F + f],
+                                           (unsigned long long)__float2ll_rn(ldexpf(v[f], kx)),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                else
+                    __hip_atomic_fetch_add(&acc[e * F + f], (double)v[f], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
     };
     uint64_t i = beg + threadIdx.x;
@@ -327,8 +373,13 @@ __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, Bi
     __syncthreads();
     float *dst = grad + ((size_t)g.offset[bd.lv[j]] + (size_t)slice * S) * F;
     for (int i2 = threadIdx.x; i2 < nf; i2 += NT) {
-        const double a = acc[i2];
-        if (a != 0.0) dst[i2] += (float)a;
+        if constexpr (FIXED) {
+            const long long a = (long long)acc[i2];
+            if (a != 0) dst[i2] += ldexpf(__ll2float_rn(a), -kx);
+        } else {
+            const double a = acc[i2];
+            if (a != 0.0) dst[i2] += (float)a;
+        }
     }
 }
 
@@ -362,10 +413,12 @@ bool bin_plan(const npm_ctx *ctx, int64_t n, bool ordered, BinDesc *out)
     return true;
 }
 
+// counters (bin-major, and the sentinel), the scan's block totals, then the
+// chunks' largest |dG| and the batch's
 size_t bin_count_words(const BinDesc &b)
 {
     const int64_t m = (int64_t)b.nbins * b.n_chunks + 1;
-    return (size_t)m + (size_t)((m + 1023) / 1024);
+    return (size_t)m + (size_t)((m + 1023) / 1024) + (size_t)b.n_chunks + 1;
 }
 
 // items: cap x F FP32 values, then cap 16-bit slice entries
@@ -378,18 +431,20 @@ template <int F>
 static void launch_bins(const GridDesc &g, const BinDesc &b, int64_t n, const float *pos,
                         const uint32_t *perm, const float *rec, int rec_stride, const float *dgt,
                         int rows, float *grad, uint32_t *cnt, uint32_t *items, int phase,
-                        hipStream_t s)
+                        bool fixed, hipStream_t s)
 {
     const int64_t m = (int64_t)b.nbins * b.n_chunks + 1;
     const int nblk = (int)((m + 1023) / 1024);
+    uint32_t *cmax = cnt + m + nblk;             // n_chunks + 1 words
     switch (phase) {
     case 0:
         hipLaunchKernelGGL(k_bin_count<F>, dim3((unsigned)b.n_chunks), dim3(kBinChunk), 0, s, g, b,
-                           n, pos, perm, rec, rec_stride, dgt, rows, cnt);
+                           n, pos, perm, rec, rec_stride, dgt, rows, cnt, cmax);
         break;
     case 1:
         hipLaunchKernelGGL(k_bin_scan_local, dim3(nblk), dim3(1024), 0, s, cnt, m, cnt + m);
-        hipLaunchKernelGGL(k_bin_scan_totals, dim3(1), dim3(1024), 0, s, cnt + m, nblk);
+        hipLaunchKernelGGL(k_bin_scan_totals, dim3(1), dim3(1024), 0, s, cnt + m, nblk, cmax,
+                           b.n_chunks);
         hipLaunchKernelGGL(k_bin_scan_add, dim3(nblk), dim3(1024), 0, s, cnt, m, cnt + m);
         break;
     case 2:
@@ -398,8 +453,12 @@ static void launch_bins(const GridDesc &g, const BinDesc &b, int64_t n, const fl
                            rec_stride, dgt, rows, cnt, items);
         break;
     default:
-        hipLaunchKernelGGL(k_bin_reduce<F>, dim3(b.nbins), dim3(kBinReduceThreads), 0, s, g, b, cnt,
-                           items, grad);
+        if (fixed)
+            hipLaunchKernelGGL((k_bin_reduce<F, true>), dim3(b.nbins), dim3(kBinReduceThreads), 0, s,
+                               g, b, cnt, items, cmax + b.n_chunks, grad);
+        else
+            hipLaunchKernelGGL((k_bin_reduce<F, false>), dim3(b.nbins), dim3(kBinReduceThreads), 0, s,
+                               g, b, cnt, items, cmax + b.n_chunks, grad);
         break;
     }
 }
@@ -410,14 +469,16 @@ hipError_t binned_scatter(npm_ctx *ctx, const BinDesc &b, int64_t n, const float
                           uint32_t *items, hipStream_t s)
 {
     const GridDesc &g = ctx->net.grid;
+    // the precision form sums in fixed point (no FP64)
+    const bool fx = ctx->net.cfg.precision == NPM_PREC_BF16;
     static const char *names[4] = {"bin_count", "bin_scan", "bin_place", "bin_reduce"};
     for (int phase = 0; phase < 4; ++phase) {
         int tok;
         timed_begin(ctx, names[phase], s, &tok);
         switch (g.feat) {
-        case 1: launch_bins<1>(g, b, n, pos, perm, rec, rec_stride, dgt, rows, grad, cnt, items, phase, s); break;
-        case 2: launch_bins<2>(g, b, n, pos, perm, rec, rec_stride, dgt, rows, grad, cnt, items, phase, s); break;
-        default: launch_bins<4>(g, b, n, pos, perm, rec, rec_stride, dgt, rows, grad, cnt, items, phase, s); break;
+        case 1: launch_bins<1>(g, b, n, pos, perm, rec, rec_stride, dgt, rows, grad, cnt, items, phase, fx, s); break;
+        case 2: launch_bins<2>(g, b, n, pos, perm, rec, rec_stride, dgt, rows, grad, cnt, items, phase, fx, s); break;
+        default: launch_bins<4>(g, b, n, pos, perm, rec, rec_stride, dgt, rows, grad, cnt, items, phase, fx, s); break;
         }
         timed_end(ctx, tok, s);
         const hipError_t e = hipGetLastError();

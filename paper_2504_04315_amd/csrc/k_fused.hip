@@ -178,13 +178,14 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
 // the memory system accepts, and at the one wave per SIMD the MLP kernel's
 // registers allow, a wave waiting on its atomics leaves its SIMD idle, while
 // this kernel runs four waves per SIMD.
-// per wave: 32 dG rows, then the window of kScatterWinRows rows holding FP64
-// sums (LDS FP64 atomic adds run several times faster than FP32 ones on this
-// chip): kScatterWinRows * kStride / (2 F) lattice points
+// per wave: 32 dG rows, then the window of kScatterWinRows rows holding the
+// sums -- FP64 (LDS FP64 atomic adds run several times faster than FP32 ones
+// on this chip), or 32-bit fixed point in the precision form (WT = int, no
+// FP64): kScatterWinRows * kStride / (2 F) lattice points
 constexpr int kScatterWinRows = 32;
 constexpr int kScatterRows = 32 + kScatterWinRows;
 
-template <int F>
+template <int F, typename WT>
 __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
                                                        const float *__restrict__ pos,
                                                        const uint32_t *perm,
@@ -224,9 +225,9 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(GridDesc g, int64_t n,
             *reinterpret_cast<f32x4 *>(tb + (i >> 3) * kStride + (i & 7) * 4) = q;
         }
         wave_lds_fence();
-        scatter_tile<F, WIN_PTS, double>(gv, tb, pos, perm, n, t, lane, grad, lo, hi,
-                                         reinterpret_cast<double *>(tb + 32 * kStride), rec,
-                                         rec_stride, skip_mask);
+        scatter_tile<F, WIN_PTS, WT>(gv, tb, pos, perm, n, t, lane, grad, lo, hi,
+                                     reinterpret_cast<WT *>(tb + 32 * kStride), rec, rec_stride,
+                                     skip_mask);
         wave_lds_fence();
     }
 }
@@ -407,6 +408,23 @@ static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
         }                                                                                         \
     } while (0)
 
+bool fused_shape_supported(const Net &net)
+{
+    const MlpDesc &m = net.mlp;
+    const int F = net.grid.feat;
+    if (m.sh_degree > 0) {
+        switch (m.sh_degree * 100000 + F * 10000 + m.in_p * 100 + (m.hid_p == 64) * 10 + m.n_hidden) {
+        case 429612: case 429613: case 449612: case 449613: case 221602: return true;
+        default: return false;
+        }
+    }
+    switch (F * 1000 + (m.in_p == 32) * 100 + (m.hid_p == 64) * 10 + m.n_hidden) {
+    case 1002: case 1112: case 1113: case 2002: case 2012: case 2112: case 2113:
+    case 4012: case 4013: case 4112: case 4113: return m.in_p <= 32;
+    default: return false;
+    }
+}
+
 hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                        const float *dir, uint64_t seed, uint32_t stream_id, float *lobes,
                        float *pdf, float *sdir, float *spdf, const uint32_t *perm,
@@ -474,17 +492,17 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
         const uint32_t all = ctx->net.grid.n_levels >= 32 ? ~0u : (1u << ctx->net.grid.n_levels) - 1u;
         if (skip != all) {
             timed_begin(ctx, "fused_scatter", s, &tok);
+            const bool fixed = ctx->net.cfg.precision == NPM_PREC_BF16;
+            const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define NPM_SCATTER_LAUNCH(FV, WT)                                                                \
+    hipLaunchKernelGGL((k_scatter_tiles<FV, WT>), grid, block, 0, s, ctx->net.grid, n, pos, perm, \
+                       rec, a.rec_stride, dg_tiles, rows, grad, skip)
             switch (ctx->net.grid.feat) {
-            case 1: hipLaunchKernelGGL(k_scatter_tiles<1>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                       ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
-                                       grad, skip); break;
-            case 2: hipLaunchKernelGGL(k_scatter_tiles<2>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                       ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
-                                       grad, skip); break;
-            default: hipLaunchKernelGGL(k_scatter_tiles<4>, dim3((waves + 3) / 4), dim3(256), 0, s,
-                                        ctx->net.grid, n, pos, perm, rec, a.rec_stride, dg_tiles, rows,
-                                       grad, skip); break;
+            case 1: if (fixed) NPM_SCATTER_LAUNCH(1, int); else NPM_SCATTER_LAUNCH(1, double); break;
+            case 2: if (fixed) NPM_SCATTER_LAUNCH(2, int); else NPM_SCATTER_LAUNCH(2, double); break;
+            default: if (fixed) NPM_SCATTER_LAUNCH(4, int); else NPM_SCATTER_LAUNCH(4, double); break;
             }
+#undef NPM_SCATTER_LAUNCH
             timed_end(ctx, tok, s);
             e = hipGetLastError();
             if (e != hipSuccess) return e;

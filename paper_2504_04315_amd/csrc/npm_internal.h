@@ -231,6 +231,9 @@ hipError_t binned_scatter(npm_ctx *ctx, const BinDesc &b, int64_t n, const float
                           uint32_t *items, hipStream_t s);
 
 // fused path (k_fused.hip)
+// whether the fused kernels are instantiated for the network's shape (the
+// dispatch tables of k_fused.hip)
+bool fused_shape_supported(const Net &net);
 // perm/inv (optional): visiting order and its inverse; the outputs then go
 // through `stage` (n slots of 40 floats) and an un-permuting pass
 hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,

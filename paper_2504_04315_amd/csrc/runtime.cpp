@@ -161,6 +161,10 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     const int64_t lowp_grid = c.precision == NPM_PREC_BF16 ? 2 * L.grid_params : 0;
     L.device_bytes = 16 * L.n_params + 6 * img + (int64_t)kPartials * 8 + 64 + lowp_grid +
                      (c.ema_decay > 0.0f ? 4 * L.n_params + 6 * img + lowp_grid : 0);
+    if (c.exec_mode == NPM_EXEC_FUSED && !fused_shape_supported(n))
+        return bad("no fused kernels for this network shape (fused: F 1, 2 or 4; 16 or 32 grid "
+                   "features; hidden width 32 (16 inputs, 2 hidden layers) or 64 (2 or 3 hidden "
+                   "layers)); the staged path takes any shape");
     *net = n;
     return NPM_OK;
 }

@@ -31,7 +31,8 @@ def test_every_declared_symbol_is_exported():
     assert set(B.SIGNATURES) <= names
     from paper_2504_04315_amd import serve as S
     assert set(S.SIGNATURES) <= names
-    assert {"npm_server_create", "npm_submit_train", "npm_backward_static"} <= names
+    assert {"npm_server_create", "npm_submit_train", "npm_server_hold",
+            "npm_backward_static"} <= names
 
 
 def test_version_and_last_error():
@@ -106,6 +107,14 @@ def test_invalid_configs_rejected_without_device():
     c.precision = B.PREC_BF16
     c.exec_mode = B.EXEC_STAGED
     assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+    # a fused context needs kernels for its shape: 16 inputs into three
+    # 32-wide hidden layers have none (the staged path takes it)
+    c = B.npm_config.from_buffer_copy(base)
+    c.n_levels, c.mlp_width, c.exec_mode = 8, 32, B.EXEC_FUSED
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+    assert b"no fused kernels" in lib.npm_last_error()
+    c.exec_mode = B.EXEC_STAGED
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == 0
 
 
 def test_moving_average_adds_its_buffers_to_the_layout():
