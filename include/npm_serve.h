@@ -94,8 +94,14 @@ npm_status npm_submit_train(npm_server *srv, int32_t sid, int64_t n, const float
                             const float *dir, const float *radiance, const float *sampling_pdf,
                             double *stats_out, uint64_t *req);
 
+/* hold != 0: the server forms no new round (rounds already launched
+ * finish); requests submitted meanwhile wait, in order, and are formed into
+ * rounds once the server is released (hold 0), e.g. to hand over a whole
+ * wavefront's requests at once.  npm_drain releases a hold.               */
+npm_status npm_server_hold(npm_server *srv, int32_t hold);
 /* Blocks until the request has completed on the device (timeout_us < 0:
- * no limit; NPM_ERR_TIMEOUT on expiry).                                    */
+ * no limit; NPM_ERR_TIMEOUT on expiry; NPM_ERR_STATE without a limit while
+ * the server is held and the request is not yet in a round).               */
 npm_status npm_wait(npm_server *srv, uint64_t req, int64_t timeout_us);
 /* Blocks until every submitted request has completed.                       */
 npm_status npm_drain(npm_server *srv);

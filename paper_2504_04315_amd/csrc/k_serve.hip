@@ -31,11 +31,17 @@ struct DevReq {
     float invN;
 };
 
+// A round launches one kernel per (network shape, request kind) group: at
+// most two kinds for each of the kServeShapes shapes serve_supports admits.
+constexpr int kServeShapes = 4;
+constexpr int kMaxRoundGroups = 2 * kServeShapes;
+
 struct RoundHdr {
-    uint32_t counter[4];         // chunk counters, one per launch (zero at upload)
+    uint32_t counter[kMaxRoundGroups];   // chunk counters, one per launch (zero at upload)
     int32_t n_req;
     int32_t pad[3];
 };
+static_assert(sizeof(RoundHdr) <= 64, "the round header sits in the first 64 bytes");
 
 constexpr int kQueryChunkTiles = 4;    // one tile per wave
 constexpr int kTrainWaveTiles = 4;     // tiles per wave per training chunk
@@ -205,6 +211,7 @@ bool serve_supports(const npm_config *cfg)
     if (describe(cfg, &net, &err) != NPM_OK) return false;
     if (cfg->sh_degree != 0) return false;
     const int k = shape_key(net);
+    static_assert(kServeShapes == 4, "the shapes listed here and in launch_shape");
     return k == 2113 || k == 4012 || k == 2002 || k == 2112;
 }
 
@@ -307,7 +314,8 @@ hipError_t serve_launch_round(RoundBuffers *b, const std::vector<ServeRequest> &
         hloss[j] = 0.0;
         hstats[j] = q.stats;
     }
-    if ((int)groups.size() > 4) return hipErrorNotSupported;   // one counter per launch
+    // one counter per launch; serve_supports admits kServeShapes shapes
+    if ((int)groups.size() > kMaxRoundGroups) return hipErrorNotSupported;
     hipError_t e = hipMemcpyAsync(dev, host, L.total, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
     RoundHdr *dh = (RoundHdr *)dev;

@@ -54,6 +54,7 @@ struct Request {
 struct Session {
     npm_ctx *ctx = nullptr;
     bool alive = false;
+    bool reserved = false;       // taken by a create still allocating its context
     bool shared = false;         // served by the persistent kernels
     int64_t bytes = 0;
     int64_t outstanding = 0;     // submitted, not yet completed
@@ -90,6 +91,7 @@ struct npm_server {
     int64_t bytes_in_use = 0;
     npm_server_stats stats{};
     bool stop = false;
+    bool held = false;            // npm_server_hold: no round is formed
     std::thread sched, completer;
 };
 
@@ -145,7 +147,7 @@ void scheduler(npm_server *s)
 {
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        s->cv_sched.wait(lk, [&] { return s->stop || !s->pending.empty(); });
+        s->cv_sched.wait(lk, [&] { return s->stop || (!s->pending.empty() && !s->held); });
         if (s->pending.empty() && s->stop) break;
         // a free descriptor buffer (bounds the rounds in flight)
         int slot = -1;
@@ -187,14 +189,22 @@ void scheduler(npm_server *s)
             work.push_back(w);
         }
         lk.unlock();
-        hipError_t e;
-        if (plain) e = execute_plain(work, s->stream);
-        else e = serve_launch_round(&s->bufs[slot], work, s->stream);
+        const hipError_t e = plain ? execute_plain(work, s->stream)
+                                   : serve_launch_round(&s->bufs[slot], work, s->stream);
+        // The event follows whatever part of the round did launch (also when
+        // a later launch failed): the completion thread releases the round's
+        // descriptor buffer only after the device has passed it.  Without an
+        // event the stream is drained here instead.
         hipEvent_t ev = nullptr;
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
+        hipError_t ee = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (ee == hipSuccess) ee = hipEventRecord(ev, s->stream);
+        if (ee != hipSuccess) {
+            if (ev) hipEventDestroy(ev);
+            ev = nullptr;
+            hipStreamSynchronize(s->stream);
+        }
         lk.lock();
-        rd.failed = e != hipSuccess;
+        rd.failed = e != hipSuccess || ee != hipSuccess;
         rd.done_ev = ev;
         s->inflight.push_back(rd);
         s->cv_inflight.notify_all();
@@ -268,9 +278,21 @@ npm_status npm_server_create(const npm_server_config *cfg, npm_server **out)
     return NPM_OK;
 }
 
+npm_status npm_server_hold(npm_server *s, int32_t hold)
+{
+    if (!s) return sfail(NPM_ERR_INVALID_ARG, "null server");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->held = hold != 0;
+    }
+    s->cv_sched.notify_all();
+    return NPM_OK;
+}
+
 npm_status npm_drain(npm_server *s)
 {
     if (!s) return sfail(NPM_ERR_INVALID_ARG, "null server");
+    npm_server_hold(s, 0);
     std::unique_lock<std::mutex> lk(s->mu);
     s->cv_done.wait(lk, [&] {
         for (auto &kv : s->reqs) if (!kv.second.done) return false;
@@ -318,20 +340,24 @@ npm_status npm_session_create(npm_server *s, const npm_config *cfg, int32_t *sid
     std::unique_lock<std::mutex> lk(s->mu);
     int slot = -1;
     for (int i = 0; i < (int)s->sessions.size(); ++i)
-        if (!s->sessions[i].alive) { slot = i; break; }
+        if (!s->sessions[i].alive && !s->sessions[i].reserved) { slot = i; break; }
     if (slot < 0) return sfail(NPM_ERR_BUDGET, "no free session slot");
     if (s->bytes_in_use + bytes > s->cfg.budget_bytes)
         return sfail(NPM_ERR_BUDGET, "session does not fit the HBM budget");
-    s->bytes_in_use += bytes;            // reserve before the (slow) allocation
+    // the slot and the bytes are taken before the (slow) allocation, so that
+    // a concurrent create picks another slot
+    s->bytes_in_use += bytes;
+    s->sessions[slot].reserved = true;
     lk.unlock();
     npm_ctx *ctx = nullptr;
     st = npm_create(&c, &ctx);
     lk.lock();
+    Session &se = s->sessions[slot];
+    se.reserved = false;
     if (st != NPM_OK) {
         s->bytes_in_use -= bytes;
         return st;
     }
-    Session &se = s->sessions[slot];
     se.ctx = ctx;
     se.alive = true;
     se.shared = shared;
@@ -423,6 +449,9 @@ npm_status npm_wait(npm_server *s, uint64_t req, int64_t timeout_us)
     auto it = s->reqs.find(req);
     if (it == s->reqs.end()) return sfail(NPM_ERR_INVALID_ARG, "unknown request");
     auto ready = [&] { return s->reqs[req].done; };
+    if (timeout_us < 0 && s->held && s->reqs[req].round < 0)
+        return sfail(NPM_ERR_STATE, "the server is held and the request not yet in a round: "
+                                    "release it (npm_server_hold 0) before waiting");
     if (timeout_us < 0) s->cv_done.wait(lk, ready);
     else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
         return sfail(NPM_ERR_TIMEOUT, "request not complete");

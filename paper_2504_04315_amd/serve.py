@@ -45,6 +45,7 @@ SIGNATURES = {
     "npm_submit_train": [_P, _i32, _i64, _P, _P, _P, _P, _P, _P],
     "npm_wait": [_P, _u64, _i64],
     "npm_drain": [_P],
+    "npm_server_hold": [_P, _i32],
     "npm_request_info_get": [_P, _u64, _P],
     "npm_server_stats_get": [_P, _P],
 }
@@ -111,6 +112,10 @@ class Server:
 
     def wait(self, req, timeout_us=-1):
         B.check(lib().npm_wait(self._h, req, timeout_us))
+
+    def hold(self, on=True):
+        """While held the server forms no round; release to run what queued."""
+        B.check(lib().npm_server_hold(self._h, int(on)))
 
     def drain(self):
         B.check(lib().npm_drain(self._h))

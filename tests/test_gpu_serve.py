@@ -3,14 +3,25 @@ persistent multi-session kernels.
 
 * A query gives the same result (bit for bit) alone and in a mix of other
   sessions' requests, and the same as the session's own fused path.
-* A training batch gives the same parameters alone and in the mix, within
-  the parity tolerance (the order of atomic adds differs).
-* Admission respects the HBM budget; every request completes exactly once.
-* The per-session plain path agrees with the FP64 oracle.
+* A training batch through the shared kernels matches the FP64 oracle's
+  gradient at the session's parameters to the precision form's bar
+  (cosine > 0.99, grid and MLP) and its loss to the pdf target, and equals
+  the session's own fused train step up to the order of FP32 sums; it gives
+  the same result alone and in a mix.
+* The per-session plain path (FP32) matches the oracle to the parity
+  tolerance.
+* A round holding three network shapes, each with queries and training
+  batches, gives every request its alone result.
+* Admission respects the HBM budget; every request completes exactly once;
+  concurrent session creation hands out distinct sessions.
 """
+import threading
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
+import parity as P
 from paper_2504_04315_amd import npm as B
 from paper_2504_04315_amd import serve as S
 from paper_2504_04315_amd import workload as W
@@ -31,9 +42,174 @@ def dev(torch, a):
 
 
 
+def small_net(seed):
+    return replace(W.CFG5, log2_table=14, seed=seed)
+
+
 def small_cfg(seed):
-    from dataclasses import replace
-    return B.make_config(replace(W.CFG5, log2_table=14, seed=seed))
+    return B.make_config(small_net(seed))
+
+
+def oracle_net(O, net):
+    return O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table,
+                 net.dense_only, net.n_hidden, net.width, net.n_lobes)
+
+
+def cosine(a, b):
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def test_shared_train_against_oracle_and_own_step(O, torch):
+    """One training batch through the shared persistent kernels: the first
+    Adam moment after the step is (1 - beta1) g, compared with the oracle's
+    gradient at the session's initial parameters and with the same step run
+    by an identical context's own fused BF16 npm_train_step."""
+    net = small_net(61)
+    cfg = B.make_config(net)
+    n_params = B.layout_of(cfg).n_params
+    srv = S.Server(budget_bytes=4 << 30, max_sessions=4)
+    sid = srv.create_session(cfg)
+    p0 = srv.session_state(sid, n_params).astype(np.float64)
+    b = W.make_batch("surface", 12289, seed=62)
+    args = [dev(torch, a) for a in (b.pos, b.dir, b.radiance, b.pdf)]
+    st = torch.zeros(2, dtype=torch.float64, device="cuda")
+    srv.wait(srv.submit_train(sid, *args, stats=st))
+    m_srv = srv.session_state(sid, n_params, B.STATE_ADAM_M).astype(np.float64)
+    on = oracle_net(O, net)
+    ref = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, p0)
+    cond = O.backward_cond(on, b.pos, b.dir, b.radiance, b.pdf, p0)
+    c1 = float(1.0 - np.float32(net.beta1))
+    gp = on.grid_params
+    for name, sl in (("grid", slice(0, gp)), ("mlp", slice(gp, None))):
+        cs = cosine(m_srv[sl], c1 * ref["grad"][sl])
+        print(f"serving train gradient cosine vs oracle ({name}): {cs:.6f}")
+        assert cs > 0.99, (name, cs)
+    # loss: the pdf target (relative error <= 1e-2) bounds |d log V| by 1e-2
+    # per sample, so the weighted mean moves by at most 1e-2 mean(w)
+    w = np.where((b.radiance > 0) & (b.pdf > 0), b.radiance / np.maximum(b.pdf, 1e-30), 0.0)
+    ls = float(st[0].cpu())
+    print(f"serving loss {ls:.7f} vs oracle {ref['loss']:.7f} (bound {1e-2 * w.mean():.2e})")
+    assert abs(ls - ref["loss"]) <= 1e-2 * w.mean()
+    # the session's own fused path on an identical context
+    own = B.NPM(cfg)
+    assert np.array_equal(own.get_state(), p0.astype(np.float32))
+    st2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    own.train_step(*args, stats=st2)
+    torch.cuda.synchronize()
+    m_own = own.get_state(B.STATE_ADAM_M).astype(np.float64)
+    print(P.assert_within("serving vs own train step (first moment)", m_srv, m_own,
+                          c1 * 1e-5 * cond + 1e-30))
+    assert abs(ls - float(st2[0].cpu())) <= 1e-9 * abs(ls)
+    own.close()
+    srv.close()
+
+
+def test_plain_path_train_against_oracle(O, torch):
+    """The per-session plain path (FP32, one kernel per stage) against the
+    FP64 oracle: the first moment (1 - beta1) g to the gradient tolerance,
+    the loss to 1e-5."""
+    net = small_net(71)
+    srv = S.Server(budget_bytes=4 << 30, max_sessions=2, plain_path=True)
+    sid = srv.create_session(B.make_config(net))
+    n_params = B.layout_of(B.make_config(net)).n_params
+    p0 = srv.session_state(sid, n_params).astype(np.float64)
+    b = W.make_batch("surface", 4099, seed=72)
+    st = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ins = [dev(torch, a) for a in (b.pos, b.dir, b.radiance, b.pdf)]
+    srv.wait(srv.submit_train(sid, *ins, stats=st))
+    m = srv.session_state(sid, n_params, B.STATE_ADAM_M).astype(np.float64)
+    on = oracle_net(O, net)
+    ref = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, p0)
+    cond = O.backward_cond(on, b.pos, b.dir, b.radiance, b.pdf, p0)
+    c1 = float(1.0 - np.float32(net.beta1))
+    # m = fl32(c1 * g): the gradient's tolerance plus one rounding of m
+    print(P.assert_within("plain path first moment", m, c1 * ref["grad"],
+                          c1 * 1e-5 * cond + 2.0 ** -23 * np.abs(m) + 1e-30))
+    assert float(st[0].cpu()) == pytest.approx(ref["loss"], rel=1e-5)
+    srv.close()
+
+
+# The four network shapes the shared kernels take (shape key F, first-layer
+# width, hidden width, hidden layers): 16 x F2 -> 64 x 3 (the serving
+# workload), 16 x F2 -> 64 x 2, 4 x F4 -> 64 x 2, 8 x F2 -> 32 x 2.
+SHAPES = [small_net(81), replace(small_net(82), n_hidden=2),
+          replace(small_net(83), n_levels=4, feat=4, max_res=128, n_hidden=2),
+          replace(small_net(84), n_levels=8, max_res=256, width=32, n_hidden=2)]
+
+
+def test_round_of_three_shapes_and_both_kinds(torch):
+    """Sessions of three shapes each submit a query and a training batch
+    while the server is held, so that all six requests form one round (six
+    kernel groups); each result equals the same request run alone."""
+    nets = SHAPES[1:]
+    n_params = [B.layout_of(B.make_config(n)).n_params for n in nets]
+    qb = [W.make_batch("surface", 3001 + 1000 * i, seed=90 + i) for i in range(3)]
+    tb = [W.make_batch("surface", 5003 + 1000 * i, seed=95 + i) for i in range(3)]
+
+    def outs(n):
+        return dict(lobes=torch.empty((4, 8, n), device="cuda"), pdf=torch.empty(n, device="cuda"),
+                    sdir=torch.empty((3, n), device="cuda"), spdf=torch.empty(n, device="cuda"))
+
+    keep = []          # request buffers must stay valid until the requests complete
+
+    def run(srv, sids, which):
+        q_out, rids = {}, []
+        for i in which:
+            q_out[i] = outs(qb[i].n)
+            qi = [dev(torch, qb[i].pos), dev(torch, qb[i].dir)]
+            ti = [dev(torch, a) for a in (tb[i].pos, tb[i].dir, tb[i].radiance, tb[i].pdf)]
+            keep.append((qi, ti))
+            rids.append(srv.submit_query(sids[i], *qi, seed=5, stream_id=i, **q_out[i]))
+            rids.append(srv.submit_train(sids[i], *ti))
+        return q_out, rids
+
+    mix = S.Server(budget_bytes=4 << 30, max_sessions=4)
+    m_sids = [mix.create_session(B.make_config(n)) for n in nets]
+    mix.hold(True)
+    m_out, rids = run(mix, m_sids, range(3))
+    mix.drain()
+    for r in rids:
+        mix.wait(r)                       # raises if the request failed
+    rounds = {mix.info(r).round for r in rids}
+    assert len(rounds) == 1, rounds
+    for i, net in enumerate(nets):
+        alone = S.Server(budget_bytes=4 << 30, max_sessions=2)
+        a_sid = [None] * 3
+        a_sid[i] = alone.create_session(B.make_config(net))
+        a_out, a_rids = run(alone, a_sid, [i])
+        alone.drain()
+        for r in a_rids:
+            alone.wait(r)
+        for k in a_out[i]:
+            assert torch.equal(a_out[i][k], m_out[i][k]), (i, k)
+        ma = alone.session_state(a_sid[i], n_params[i], B.STATE_ADAM_M)
+        mm = mix.session_state(m_sids[i], n_params[i], B.STATE_ADAM_M)
+        scale = float(np.abs(ma).max())
+        np.testing.assert_allclose(mm, ma, rtol=1e-5, atol=1e-6 * scale)
+        alone.close()
+    mix.close()
+
+
+def test_concurrent_session_creation(torch):
+    """Sessions created from several threads at once get distinct ids."""
+    srv = S.Server(budget_bytes=4 << 30, max_sessions=16)
+    got, errs = [], []
+
+    def make(seed):
+        try:
+            got.append(srv.create_session(small_cfg(seed)))
+        except Exception as e:     # noqa: BLE001 -- reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=make, args=(200 + i,)) for i in range(8)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    assert sorted(got) == sorted(set(got)) and len(got) == 8
+    assert srv.stats().sessions == 8
+    srv.close()
 
 
 def test_query_alone_equals_mix(torch):
@@ -52,13 +228,14 @@ def test_query_alone_equals_mix(torch):
     srv_a.wait(r)
     # the same request in a mix with three other sessions' queries and trains
     mix = outs(b.n)
-    others = []
+    others = []        # request buffers, kept until the requests complete
     for i, sid in enumerate(m_sids[1:]):
         ob = W.make_batch("surface", 5000 + 977 * i, seed=10 + i)
-        others.append(srv_m.submit_train(sid, dev(torch, ob.pos), dev(torch, ob.dir),
-                                         dev(torch, ob.radiance), dev(torch, ob.pdf)))
+        ins = [dev(torch, a) for a in (ob.pos, ob.dir, ob.radiance, ob.pdf)]
         o = outs(ob.n)
-        others.append(srv_m.submit_query(sid, dev(torch, ob.pos), dev(torch, ob.dir), **o))
+        others.append((ins, o))
+        srv_m.submit_train(sid, *ins)
+        srv_m.submit_query(sid, ins[0], ins[1], **o)
     r2 = srv_m.submit_query(m_sids[0], pos, dirs, seed=3, stream_id=1, **mix)
     srv_m.drain()
     for k in alone:
@@ -85,10 +262,11 @@ def test_train_alone_equals_mix(torch):
     st_a = torch.zeros(2, dtype=torch.float64, device="cuda")
     st_m = torch.zeros(2, dtype=torch.float64, device="cuda")
     srv_a.wait(srv_a.submit_train(a, pos, dirs, rad, pdf, stats=st_a))
+    others = []        # request buffers, kept until the requests complete
     for i, sid in enumerate(m[1:]):
         ob = W.make_batch("surface", 7000 + 1000 * i, seed=40 + i)
-        srv_m.submit_train(sid, dev(torch, ob.pos), dev(torch, ob.dir), dev(torch, ob.radiance),
-                           dev(torch, ob.pdf))
+        others.append([dev(torch, a) for a in (ob.pos, ob.dir, ob.radiance, ob.pdf)])
+        srv_m.submit_train(sid, *others[-1])
     srv_m.submit_train(m[0], pos, dirs, rad, pdf, stats=st_m)
     srv_m.drain()
     pa = S.session_ctx_state(srv_a, a, n_params)
