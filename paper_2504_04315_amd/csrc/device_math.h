@@ -284,6 +284,55 @@ __device__ __forceinline__ void mfma_layer_bf16(const __bf16 *__restrict__ img, 
         for (int v = 0; v < 16; ++v) y[16 * b + v] = acc[b][v];
 }
 
+// y (OUT_P wide) = A x for a 32-vertex tile (x, y in the tile layout), A read
+// from a row-major FP32 image in LDS whose rows are S floats apart: TR =
+// false, A = W with element (o, i) at o S + i; TR = true, A = W^T, element
+// (o, i) of A at i S + o.  One 4-byte read per lane and MFMA (the reads of a
+// half-wave fall in distinct banks: S is odd, or the lanes read one row).
+template <int IN_P, int OUT_P, int S, bool TR>
+__device__ __forceinline__ void mfma_layer_rm(const float *__restrict__ img, const float *x,
+                                              float *y, int lane)
+{
+    constexpr int NB = OUT_P / 32;
+    const int i = lane & 31, h = lane >> 5;
+    f32x16 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
+    const float *base = TR ? img + 4 * h * S + i : img + i * S + 4 * h;
+    auto wt = [&](int a, int b) {
+        const int k = 8 * (a >> 2) + (a & 3);     // nf(h, a) - 4 h
+        return TR ? base[k * S + 32 * b] : base[32 * b * S + k];
+    };
+    // the weights of step a + PD are read while the MFMAs of step a run (the
+    // compiler barrier keeps the reads ahead of the MFMAs)
+    constexpr int NA = IN_P / 2, PD = 4;
+    float w[PD][NB];
+#pragma unroll
+    for (int a = 0; a < PD && a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) w[a][b] = wt(a, b);
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        float cur[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) cur[b] = w[a % PD][b];
+        if (a + PD < NA) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) w[a % PD][b] = wt(a + PD, b);
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[b], x[a], acc[b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) y[16 * b + v] = acc[b][v];
+}
+
 // ------------------------------------------------------------------ NPM-product
 // Real orthonormal spherical harmonics of the first four bands at the vector
 // (x, y, z) (Sec. 4.3 encodes the outgoing direction and the normal with

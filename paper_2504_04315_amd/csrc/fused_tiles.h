@@ -32,68 +32,100 @@ struct GridView {
 
 // ------------------------------------------------------------------ encode
 // Features of the tile vertex for this half-wave: register 4 g + j F + f holds
-// feature f of level (8 g + 4 h) / F + j.
-template <int IN_P, int F, bool BF>
+// feature f of level (8 g + 4 h) / F + j; the registers past the grid
+// features are zero.  The half-wave's levels are taken in batches of LBF / F
+// (8 LBF floats of corner values): every corner load of a batch is issued
+// before any is used, so the gathers of several levels are in flight
+// together.  A batch starting at or beyond n_levels is skipped (the branch
+// also keeps the compiler from hoisting later batches' loads, which would
+// exhaust the registers); a level beyond n_levels inside a batch reads level
+// 0 with zero weight.
+template <int IN_P, int F, bool BF, int LBF = 8, int IN_G = IN_P>
 __device__ __forceinline__ void encode_tile(const GridView &gv, int h, float px, float py,
                                             float pz, float *x)
 {
-    constexpr int PER = 4 / F;   // levels per group and half
+    // IN_G: the grid features' share of the IN_P inputs (NPM-product inputs
+    // follow them), rounded up to the 8 features of a register group
+    constexpr int GROUPS = (IN_G + 7) / 8;
+    constexpr int PER = 4 / F;                // levels per group and half
+    constexpr int NLV = GROUPS * PER;         // levels of this half-wave
+    constexpr int LB0 = LBF / F < 1 ? 1 : LBF / F;
+    constexpr int LB = LB0 < NLV ? LB0 : NLV; // levels per batch
+    auto level = [&](int q) { return (8 * (q / PER) + 4 * h) / F + q % PER; };
 #pragma unroll
-    for (int g = 0; g < IN_P / 8; ++g) {
+    for (int q0 = 0; q0 < NLV; q0 += LB) {
+        if (level(q0) >= gv.n_levels) {
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int l = (8 * g + 4 * h) / F + j;
+            for (int qq = 0; qq < LB && q0 + qq < NLV; ++qq)
+#pragma unroll
+                for (int f = 0; f < F; ++f) x[4 * ((q0 + qq) / PER) + ((q0 + qq) % PER) * F + f] = 0.0f;
+            continue;
+        }
+        float val[LB][8][F];
+        float fr[LB][3];
+        bool live[LB];
+#pragma unroll
+        for (int qq = 0; qq < LB; ++qq) {
+            const int q = q0 + qq;
+            if (q >= NLV) break;
+            const int l = level(q);
+            live[qq] = l < gv.n_levels;
+            const int lc = live[qq] ? l : 0;
+            const int D = gv.res[lc];
+            int cx, cy, cz;
+            lattice_cell(px, D, cx, fr[qq][0]);
+            lattice_cell(py, D, cy, fr[qq][1]);
+            lattice_cell(pz, D, cz, fr[qq][2]);
+            const uint32_t d1 = (uint32_t)D + 1u;
+            const bool hashed = (gv.hashed_mask >> lc) & 1u;
+            const uint32_t off = gv.off[lc];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint32_t X = cx + (b & 1), Y = cy + ((b >> 1) & 1), Z = cz + ((b >> 2) & 1);
+                const uint32_t e = off + (hashed ? ((X ^ (Y * 2654435761u) ^ (Z * 805459861u)) & gv.table_mask)
+                                                 : X + d1 * (Y + d1 * Z));
+                if constexpr (BF) {
+                    if constexpr (F == 2) {
+                        const __half2 t = *reinterpret_cast<const __half2 *>(gv.g16 + 2 * (size_t)e);
+                        val[qq][b][0] = __low2float(t); val[qq][b][1] = __high2float(t);
+                    } else {
+#pragma unroll
+                        for (int f = 0; f < F; ++f) val[qq][b][f] = __half2float(gv.g16[(size_t)e * F + f]);
+                    }
+                } else {
+                    if constexpr (F == 1) {
+                        val[qq][b][0] = gv.g32[e];
+                    } else if constexpr (F == 2) {
+                        const float2 t = *reinterpret_cast<const float2 *>(gv.g32 + 2 * (size_t)e);
+                        val[qq][b][0] = t.x; val[qq][b][1] = t.y;
+                    } else {
+                        const float4 t = *reinterpret_cast<const float4 *>(gv.g32 + 4 * (size_t)e);
+                        val[qq][b][0] = t.x; val[qq][b][1] = t.y; val[qq][b][2] = t.z; val[qq][b][3] = t.w;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int qq = 0; qq < LB; ++qq) {
+            const int q = q0 + qq;
+            if (q >= NLV) break;
+            const float fx = fr[qq][0], fy = fr[qq][1], fz = fr[qq][2];
+            const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
             float acc[F];
 #pragma unroll
             for (int f = 0; f < F; ++f) acc[f] = 0.0f;
-            if (l < gv.n_levels) {
-                const int D = gv.res[l];
-                int cx, cy, cz;
-                float fx, fy, fz;
-                lattice_cell(px, D, cx, fx);
-                lattice_cell(py, D, cy, fy);
-                lattice_cell(pz, D, cz, fz);
-                const uint32_t d1 = (uint32_t)D + 1u;
-                const bool hashed = (gv.hashed_mask >> l) & 1u;
-                const uint32_t off = gv.off[l];
-                float val[8][F];
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const uint32_t X = cx + (b & 1), Y = cy + ((b >> 1) & 1), Z = cz + ((b >> 2) & 1);
-                    const uint32_t e = off + (hashed ? ((X ^ (Y * 2654435761u) ^ (Z * 805459861u)) & gv.table_mask)
-                                                     : X + d1 * (Y + d1 * Z));
-                    if constexpr (BF) {
-                        if constexpr (F == 2) {
-                            const __half2 t = *reinterpret_cast<const __half2 *>(gv.g16 + 2 * (size_t)e);
-                            val[b][0] = __low2float(t); val[b][1] = __high2float(t);
-                        } else {
+            for (int b = 0; b < 8; ++b) {
+                const float w = wx[b & 1] * wy[(b >> 1) & 1] * wz[(b >> 2) & 1];
 #pragma unroll
-                            for (int f = 0; f < F; ++f) val[b][f] = __half2float(gv.g16[(size_t)e * F + f]);
-                        }
-                    } else {
-                        if constexpr (F == 1) {
-                            val[b][0] = gv.g32[e];
-                        } else if constexpr (F == 2) {
-                            const float2 t = *reinterpret_cast<const float2 *>(gv.g32 + 2 * (size_t)e);
-                            val[b][0] = t.x; val[b][1] = t.y;
-                        } else {
-                            const float4 t = *reinterpret_cast<const float4 *>(gv.g32 + 4 * (size_t)e);
-                            val[b][0] = t.x; val[b][1] = t.y; val[b][2] = t.z; val[b][3] = t.w;
-                        }
-                    }
-                }
-                const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const float w = wx[b & 1] * wy[(b >> 1) & 1] * wz[(b >> 2) & 1];
-#pragma unroll
-                    for (int f = 0; f < F; ++f) acc[f] += w * val[b][f];
-                }
+                for (int f = 0; f < F; ++f) acc[f] += w * val[qq][b][f];
             }
 #pragma unroll
-            for (int f = 0; f < F; ++f) x[4 * g + j * F + f] = acc[f];
+            for (int f = 0; f < F; ++f) x[4 * (q / PER) + (q % PER) * F + f] = live[qq] ? acc[f] : 0.0f;
         }
     }
+#pragma unroll
+    for (int a = 4 * GROUPS; a < IN_P / 2; ++a) x[a] = 0.0f;
 }
 
 // NPM-product inputs (Sec. 4.3) of the tile vertex into the feature
@@ -265,7 +297,9 @@ __device__ __forceinline__ void query_tile(const GridView &gv, const void *img, 
         if (io.pdf) { wx = io.dir[vv]; wy = io.dir[n + vv]; wz = io.dir[2 * n + vv]; }
     }
     float x[IN_P / 2];
-    encode_tile<IN_P, F, BF>(gv, h, px, py, pz, x);
+    // two levels' corners in flight at F = 2: the query kernel runs three
+    // waves per SIMD, which hide the rest
+    encode_tile<IN_P, F, BF, 4, (PG > 0 ? ProductShape<PG>::GF : IN_P)>(gv, h, px, py, pz, x);
     if constexpr (PG > 0) {
         float a7[7];
         load_aux(io.rec, io.rec_stride, io.aux, n, valid ? v : n - 1, vv, a7);
@@ -702,6 +736,71 @@ __device__ __forceinline__ void tile_bbox(float px, float py, float pz, float *l
 // STORE_DG: the tile's dG is stored at dg_tiles + t * OUT0 * 32 (row r =
 // feature r, 32 vertices of the visiting order) for the aggregated scatter
 // kernel; otherwise it is scattered into the grid here.
+// A training vertex's inputs: position, direction, radiance estimate and
+// sampling pdf of visiting slot v (the vertex vv), from the slot's record or
+// the SoA arrays.
+struct TrainInputs {
+    float px, py, pz, wx, wy, wz, rad, spdf;
+};
+__device__ __forceinline__ TrainInputs train_inputs(const TrainIO &io, int64_t v, int64_t vv)
+{
+    TrainInputs in;
+    const int64_t n = io.n;
+    if (io.rec) {
+        const f32x4 *r = reinterpret_cast<const f32x4 *>(io.rec + (size_t)v * io.rec_stride);
+        const f32x4 a = r[0], b = r[1];
+        in.px = a[0]; in.py = a[1]; in.pz = a[2]; in.wx = a[3];
+        in.wy = b[0]; in.wz = b[1]; in.rad = b[2]; in.spdf = b[3];
+    } else {
+        in.px = io.pos[vv]; in.py = io.pos[n + vv]; in.pz = io.pos[2 * n + vv];
+        in.wx = io.dir[vv]; in.wy = io.dir[n + vv]; in.wz = io.dir[2 * n + vv];
+        in.rad = io.rad[vv]; in.spdf = io.spdf[vv];
+    }
+    return in;
+}
+
+// The KL-gradient head (Sec. 4.2, eq. mcgradients) of a tile: d = d loss /
+// d raw for this half-wave's four lobes, from the raw outputs o; lacc
+// accumulates -w log V (FP64) of half 0's vertices.
+__device__ __forceinline__ void kl_head(const float *o, const TrainInputs &in, bool valid,
+                                        float invN, int h, float *d, double &lacc)
+{
+    const float wgt = valid ? sample_weight(in.rad, in.spdf) : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) d[i] = 0.0f;
+    Lobe L[4];
+    map_half(o, L);
+    float lt[4];
+    const float lv = logpdf_half(L, in.wx, in.wy, in.wz, lt);
+    if (wgt != 0.0f) {
+        const float g = -wgt * invN;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            lobe_grad(L[r], o[4 * r], o[4 * r + 1], o[4 * r + 2], expf(lt[r] - lv),
+                      expf(L[r].loglam), g, in.wx, in.wy, in.wz, d + 4 * r);
+        if (h == 0) lacc -= (double)wgt * (double)lv;
+    }
+}
+
+// The MLP input of a tile vertex in the tile layout: the grid encoding, the
+// padding rows of a narrow input zero, then the NPM-product inputs.
+template <int IN_P, int F, bool BF, int PG>
+__device__ __forceinline__ void tile_input(const GridView &gv, const TrainIO &io,
+                                           const TrainInputs &in, int64_t v, int64_t vv, int h,
+                                           float *x)
+{
+    constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
+    encode_tile<IN_P, F, BF, 8, (PG > 0 ? ProductShape<PG>::GF : IN_P)>(gv, h, in.px, in.py, in.pz,
+                                                                       x);
+#pragma unroll
+    for (int i = IN_P / 2; i < IN0 / 2; ++i) x[i] = 0.0f;
+    if constexpr (PG > 0) {
+        float a7[7];
+        load_aux(io.rec, io.rec_stride, io.aux, io.n, v, vv, a7);
+        aux_fill<IN_P, ProductShape<PG>::GF, ProductShape<PG>::SHD>(h, a7, x);
+    }
+}
+
 template <int IN_P, int HID_P, int NH, int F, bool BF, bool STORE_DG = false, int PG = 0>
 __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fwd, const char *bwd,
                                               float *tbuf, const TrainIO &io, int64_t t, int lane,
@@ -715,48 +814,17 @@ __device__ __forceinline__ void backward_tile(const GridView &gv, const char *fw
     const int64_t n = io.n;
     const int64_t v = t * 32 + (lane & 31);
     const bool valid = v < n;
-    float px, py, pz, wx, wy, wz, rad, spdf;
-    const int64_t vv = visit(io.perm, valid ? v : n - 1);
-    if (io.rec) {
-        const f32x4 *r = reinterpret_cast<const f32x4 *>(io.rec + (size_t)(valid ? v : n - 1) * io.rec_stride);
-        const f32x4 a = r[0], b = r[1];
-        px = a[0]; py = a[1]; pz = a[2]; wx = a[3]; wy = b[0]; wz = b[1]; rad = b[2]; spdf = b[3];
-    } else {
-        px = io.pos[vv]; py = io.pos[n + vv]; pz = io.pos[2 * n + vv];
-        wx = io.dir[vv]; wy = io.dir[n + vv]; wz = io.dir[2 * n + vv];
-        rad = io.rad[vv]; spdf = io.spdf[vv];
-    }
+    const int64_t vs = valid ? v : n - 1;
+    const int64_t vv = visit(io.perm, vs);
+    const TrainInputs in = train_inputs(io, vs, vv);
+    const float px = in.px, py = in.py, pz = in.pz;
     float x[IN0 / 2];
-    encode_tile<IN_P, F, BF>(gv, h, px, py, pz, x);
-#pragma unroll
-    for (int i = IN_P / 2; i < IN0 / 2; ++i) x[i] = 0.0f;
-    if constexpr (PG > 0) {
-        float a7[7];
-        load_aux(io.rec, io.rec_stride, io.aux, n, valid ? v : n - 1, vv, a7);
-        aux_fill<IN_P, ProductShape<PG>::GF, ProductShape<PG>::SHD>(h, a7, x);
-    }
+    tile_input<IN_P, F, BF, PG>(gv, io, in, vs, vv, h, x);
     float acts[NH][HID_P / 2];
     float o[16];
     mlp_forward<IN_P, HID_P, NH, BF, true>(fwd, x, acts, o, lane);
-    // ---- KL-gradient head
-    const float wgt = valid ? sample_weight(rad, spdf) : 0.0f;
     float d[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) d[i] = 0.0f;
-    {
-        Lobe L[4];
-        map_half(o, L);
-        float lt[4];
-        const float lv = logpdf_half(L, wx, wy, wz, lt);
-        if (wgt != 0.0f) {
-            const float g = -wgt * io.invN;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                lobe_grad(L[r], o[4 * r], o[4 * r + 1], o[4 * r + 2], expf(lt[r] - lv),
-                          expf(L[r].loglam), g, wx, wy, wz, d + 4 * r);
-            if (h == 0) lacc -= (double)wgt * (double)lv;
-        }
-    }
+    kl_head(o, in, valid, io.invN, h, d, lacc);
     if (!io.grad) return;          // loss only
     // ---- weight gradient of the output layer, then the delta chain
     dw_tile<32, HID_P, BF>(tbuf, d, acts[NH - 1], dw.last, lane);

@@ -196,10 +196,51 @@ static void pack_images(const PackDesc &d, const float *src, float *img, void *i
                            (__bf16 *)img16);
 }
 
+// The row-major image of the training kernel (MlpDesc::rm_off): layer L as
+// its padded rows x cols matrix, rows cols + 1 floats apart, zero outside
+// the real weights.
+struct RmDesc {
+    int64_t off[NPM_MAX_LAYERS + 1];
+    int64_t src[NPM_MAX_LAYERS];
+    int32_t cols[NPM_MAX_LAYERS], out_r[NPM_MAX_LAYERS], in_r[NPM_MAX_LAYERS];
+    int32_t n_layers;
+};
+
+__global__ void k_pack_rm(RmDesc d, const float *__restrict__ params, float *__restrict__ dst)
+{
+    const int64_t total = d.off[d.n_layers];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int L = 0;
+        while (L + 1 < d.n_layers && i >= d.off[L + 1]) ++L;
+        const int64_t k = i - d.off[L];
+        const int S = d.cols[L] + 1;
+        const int o = (int)(k / S), c = (int)(k % S);
+        dst[i] = (o < d.out_r[L] && c < d.in_r[L]) ? params[d.src[L] + (int64_t)o * d.in_r[L] + c]
+                                                   : 0.0f;
+    }
+}
+
 hipError_t launch_pack_mlp(npm_ctx *ctx, hipStream_t s)
 {
     const PackDesc d = pack_desc(ctx->net);
     pack_images(d, ctx->params, ctx->mlp_img, ctx->mlp_img16, s);
+    {
+        const Net &net = ctx->net;
+        RmDesc r{};
+        r.n_layers = net.lay.n_layers;
+        for (int i = 0; i < r.n_layers; ++i) {
+            r.off[i] = net.mlp.rm_off[i];
+            r.src[i] = net.lay.layer_offset[i];
+            r.cols[i] = i == 0 ? std::max(net.mlp.in_p, 32) : net.mlp.hid_p;
+            r.out_r[i] = net.lay.layer_out[i];
+            r.in_r[i] = net.lay.layer_in[i];
+        }
+        r.off[r.n_layers] = net.mlp.rm_elems;
+        const int blocks = (int)std::min<int64_t>((net.mlp.rm_elems + 255) / 256, 256);
+        hipLaunchKernelGGL(k_pack_rm, dim3(blocks), dim3(256), 0, s, r, ctx->params,
+                           ctx->mlp_img + net.mlp.fwd_elems + net.mlp.bwd_elems);
+    }
     if (ctx->ema) pack_images(d, ctx->ema, ctx->ema_img, ctx->ema_img16, s);
     return hipGetLastError();
 }

@@ -23,6 +23,8 @@
 // Precision form (BF16 = true): grid features read from an FP16 copy, MLP
 // weights and activations in BF16 on v_mfma_f32_32x32x16_bf16 with FP32
 // accumulation; mappings, softmax, log-density and sampling in FP32.
+#include <type_traits>
+
 #include "fused_tiles.h"
 
 namespace npm {
@@ -88,20 +90,167 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     }
 }
 
-// Rows of a wave's transpose buffer: the widest matrix side the weight
-// gradients transpose at once (hidden width, or the first-layer input, which
-// a wider-than-kTransRows input passes in two pieces).
-constexpr int trans_rows(int in_p, int hid_p)
+// ------------------------------------------------------------------ training
+// The training kernel splits the weight gradients of a block among its WV
+// waves.  In every round each wave runs encode, forward, KL-gradient head and
+// delta chain for its own 32-vertex tile (the block takes a contiguous run of
+// tiles, WV at a time); per layer, from the output layer back, the waves put
+// the layer's deltas and inputs into a shared LDS exchange buffer, transposed
+// (rows = features, one column per vertex of the round), and each wave
+// accumulates its own share of that layer's 32x32 weight-gradient blocks
+// over all 32 WV vertices of the round (the MFMA reduction dimension).  Each
+// dW block belongs to one wave, which keeps ceil(blocks / WV) accumulators in
+// registers instead of all of them and writes them straight to the block's
+// partial at the end: no register spills, no per-wave partial sums.
+//
+// Layers are numbered 0 (the first, IN0 inputs) to NH (the output layer, 32
+// outputs); the phases run from NH down to 0, and the dW blocks are numbered
+// in that order, block g belonging to wave g % WV in its slot g / WV.
+template <int IN_P, int HID_P, int NH, int WV>
+struct BlockPlan {
+    static constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
+    static constexpr int out_p(int L) { return L == NH ? 32 : HID_P; }
+    static constexpr int in_p(int L) { return L == 0 ? IN0 : HID_P; }
+    static constexpr int nbi(int L) { return in_p(L) / 32; }
+    static constexpr int blocks(int L) { return (out_p(L) / 32) * nbi(L); }
+    // the first block of layer L in phase order
+    static constexpr int first(int L)
+    {
+        int g = 0;
+        for (int l = NH; l > L; --l) g += blocks(l);
+        return g;
+    }
+    static constexpr int total() { return first(-1); }
+    static constexpr int slots() { return (total() + WV - 1) / WV; }
+    // rows of the exchange buffer in phase L: the deltas, then the inputs
+    static constexpr int rows(int L) { return out_p(L) + in_p(L); }
+    static constexpr int max_rows()
+    {
+        int r = 0;
+        for (int l = 0; l <= NH; ++l) r = rows(l) > r ? rows(l) : r;
+        return r;
+    }
+    // row stride of the exchange buffer (elements): the round's 32 WV
+    // vertices plus a pad that puts consecutive rows 4 banks apart, so that
+    // the 16-byte reads of 16 lanes on 16 rows hit distinct banks
+    static constexpr int xs(bool bf) { return 32 * WV + (bf ? 8 : 4); }
+    // FP32 row-major image: layer L's rows are in_p(L) + 1 floats apart
+    static constexpr int rm_stride(int L) { return in_p(L) + 1; }
+    static constexpr int rm_off(int L)
+    {
+        int o = 0;
+        for (int l = 0; l < L; ++l) o += out_p(l) * rm_stride(l);
+        return o;
+    }
+    static constexpr int rm_elems() { return rm_off(NH + 1); }
+};
+
+// fn(std::integral_constant<int, I>) for I = HI, HI - 1, .., LO (nothing if
+// HI < LO): a loop whose index is a compile-time constant in the body.
+template <int HI, int LO, class Fn>
+__device__ __forceinline__ void static_for_down(Fn &&fn)
 {
-    const int in0 = in_p < 32 ? 32 : in_p;
-    const int piece = in0 < kTransRows ? in0 : kTransRows;
-    return piece > hid_p ? piece : hid_p;
+    if constexpr (HI >= LO) {
+        fn(std::integral_constant<int, HI>{});
+        static_for_down<HI - 1, LO>(fn);
+    }
 }
 
-// Weight-image elements a training block stages in LDS: all of them, except
-// that with NPM-product inputs only the grid features' input gradient is
-// needed, so of W_0^T -- the last segment, its 32-row blocks in order --
-// only the first block is staged.
+// Rows [row0, row0 + 2 REGS) of the exchange buffer, at this wave's 32
+// columns, from a tile-layout vector of 2 REGS features.
+template <int REGS, int XS, typename XT>
+__device__ __forceinline__ void xch_put(XT *xb, int row0, int wave, const float *v, int lane)
+{
+    const int h = lane >> 5, j = lane & 31;
+    XT *p = xb + row0 * XS + 32 * wave + j;
+#pragma unroll
+    for (int a = 0; a < REGS; ++a) p[nf(h, a) * XS] = XT(v[a]);
+}
+
+// acc (a 32x32 dW block) += sum over the round's KV vertices of
+// delta[ro + row] input[ri + col], rows of the exchange buffer.  FP32:
+// 32x32x2 steps, the half-wave h supplying the vertices [KV/2 h, KV/2 (h+1))
+// in order, four per 16-byte read.  BF16: 32x32x16 steps, half h supplying
+// the vertices 16 s + 8 h + e.
+template <int KV, int XS>
+__device__ __forceinline__ void dw_block(const float *xb, int ro, int ri, f32x16 &acc, int lane)
+{
+    const int i = lane & 31, h = lane >> 5;
+    const float *pa = xb + (ro + i) * XS + (KV / 2) * h;
+    const float *pb = xb + (ri + i) * XS + (KV / 2) * h;
+#pragma unroll
+    for (int q = 0; q < KV / 8; ++q) {
+        const f32x4 A = *reinterpret_cast<const f32x4 *>(pa + 4 * q);
+        const f32x4 Bv = *reinterpret_cast<const f32x4 *>(pb + 4 * q);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[e], Bv[e], acc, 0, 0, 0);
+    }
+}
+template <int KV, int XS>
+__device__ __forceinline__ void dw_block(const __bf16 *xb, int ro, int ri, f32x16 &acc, int lane)
+{
+    const int i = lane & 31, h = lane >> 5;
+    const __bf16 *pa = xb + (ro + i) * XS + 8 * h;
+    const __bf16 *pb = xb + (ri + i) * XS + 8 * h;
+#pragma unroll
+    for (int s = 0; s < KV / 16; ++s) {
+        const bf16x8 A = *reinterpret_cast<const bf16x8 *>(pa + 16 * s);
+        const bf16x8 Bv = *reinterpret_cast<const bf16x8 *>(pb + 16 * s);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bv, acc, 0, 0, 0);
+    }
+}
+
+// Phase L of a round: put this wave's deltas dz and layer inputs hin into the
+// exchange buffer; after the barrier accumulate this wave's dW blocks of the
+// layer.  The caller runs the next chain step between this and the barrier
+// that ends the phase.
+template <class Plan, int L, int WV, int XS, typename XT, int NS>
+__device__ __forceinline__ void dw_phase(XT *xb, const float *dz, const float *hin, int wave,
+                                         f32x16 (&acc)[NS], int lane)
+{
+    constexpr int OUT = Plan::out_p(L), IN = Plan::in_p(L);
+    xch_put<OUT / 2, XS>(xb, 0, wave, dz, lane);
+    xch_put<IN / 2, XS>(xb, OUT, wave, hin, lane);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < Plan::blocks(L); ++b) {
+        constexpr int g0 = Plan::first(L);
+        if ((g0 + b) % WV == wave) {
+            const int bo = b / Plan::nbi(L), bi = b % Plan::nbi(L);
+            dw_block<32 * WV, XS>(xb, 32 * bo, OUT + 32 * bi, acc[(g0 + b) / WV], lane);
+        }
+    }
+}
+
+// This wave's dW blocks into the flat layout of the MLP weights at dst
+// (entries outside the real shapes dropped).
+template <class Plan, int NH, int WV, int NS>
+__device__ __forceinline__ void dw_write(float *dst, int n_in, int width, int wave,
+                                         f32x16 (&acc)[NS], int lane)
+{
+    const int h = lane >> 5, j = lane & 31;
+    static_for_down<NH, 0>([&](auto LC) {
+        constexpr int L = decltype(LC)::value;
+        const int out_r = L == NH ? 32 : width, in_r = L == 0 ? n_in : width;
+        float *d = dst + (L == 0 ? 0 : width * n_in + (L - 1) * width * width);
+#pragma unroll
+        for (int b = 0; b < Plan::blocks(L); ++b) {
+            const int g = Plan::first(L) + b;
+            if (g % WV != wave) continue;
+            const int bo = b / Plan::nbi(L), bi = b % Plan::nbi(L);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 32 * bo + nf(h, r), col = 32 * bi + j;
+                if (row < out_r && col < in_r) d[row * in_r + col] = acc[g / WV][r];
+            }
+        }
+    });
+}
+
+// Weight-image elements a BF16 training block stages in LDS: the forward and
+// backward images, except that with NPM-product inputs only the grid
+// features' input gradient is needed, so of W_0^T -- the last segment, its
+// 32-row blocks in order -- only the first block is staged.
 static int64_t staged_elems(const FusedArgs &a, int in_p, int hid_p, int pg)
 {
     const int in0 = in_p < 32 ? 32 : in_p;
@@ -109,44 +258,120 @@ static int64_t staged_elems(const FusedArgs &a, int in_p, int hid_p, int pg)
     return (int64_t)a.fwd_elems + a.bwd_elems - (int64_t)(in0 - dg_rows) * hid_p;
 }
 
-template <int IN_P, int HID_P, int NH, int F, bool BF, int PG>
-__global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_weights)
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG, int WV>
+__global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp_weights,
+                                                           int tiles_per_block, int img_bytes)
 {
+    using Plan = BlockPlan<IN_P, HID_P, NH, WV>;
+    using XT = typename std::conditional<BF, __bf16, float>::type;
+    constexpr int IN0 = Plan::IN0;
+    constexpr int XS = Plan::xs(BF);
+    constexpr int NS = Plan::slots();
+    constexpr int ESZ = BF ? 2 : 4;
+    constexpr int DGR = PG > 0 ? 32 : IN0;      // input-gradient rows (grid features only with PG)
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ uint32_t s_off[NPM_MAX_LEVELS];
     __shared__ int s_res[NPM_MAX_LEVELS];
-    __shared__ double red[256];
-    constexpr int ESZ = BF ? 2 : 4;
-    constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
-    const int img_bytes =
-        (a.fwd_elems + a.bwd_elems - (PG > 0 ? (IN0 - 32) * HID_P : 0)) * ESZ;
+    __shared__ double red[64 * WV];
+    // weights: BF16 the packed forward and backward images, FP32 the
+    // row-major image (both directions)
     for (int i = threadIdx.x; i < img_bytes / 16; i += blockDim.x)
         reinterpret_cast<f32x4 *>(smem)[i] = reinterpret_cast<const f32x4 *>(a.img)[i];
     stage_levels(a.g, s_off, s_res);
     __syncthreads();
+    XT *xb = reinterpret_cast<XT *>(smem + ((size_t)img_bytes + 15) / 16 * 16);
     const GridView gv = grid_view(a.g, s_off, s_res, a.grid32, a.grid16);
     const TrainIO io{a.n, a.pos, a.dir, a.rad, a.spdf, a.grad, a.invN, a.perm, a.rec, a.aux,
                      a.rec_stride};
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, h = lane >> 5;
+    const float *rm = reinterpret_cast<const float *>(smem);
     const char *fwd = smem;
     const char *bwd = smem + (size_t)a.fwd_elems * ESZ;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float *tbuf = reinterpret_cast<float *>(smem + (((size_t)img_bytes + 15) / 16) * 16) +
-                  wave * trans_rows(IN_P, HID_P) * kStride;
-    DwAcc<IN_P, HID_P, NH> dw;
-    dw.zero();
+    f32x16 acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[k][v] = 0.0f;
     double lacc = 0.0;
-    // Each wave takes a contiguous run of tiles: in a spatially ordered batch
-    // the waves resident at one time then work on distant regions (no two
-    // contending for the same grid lines) while each wave's consecutive tiles
-    // reuse the lines its previous tile brought into L2.
-    const int64_t ntiles = (a.n + 31) / 32;
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
-    const int64_t gwave = blockIdx.x * (int64_t)(blockDim.x / 64) + wave;
-    const int64_t per = (ntiles + nwaves - 1) / nwaves;
-    const int64_t t_end = (gwave + 1) * per < ntiles ? (gwave + 1) * per : ntiles;
-    for (int64_t t = gwave * per; t < t_end; ++t)
-        backward_tile<IN_P, HID_P, NH, F, BF, true, PG>(gv, fwd, bwd, tbuf, io, t, lane, dw,
-                                                        lacc, a.dg_tiles);
+    const int64_t n = a.n;
+    const int64_t ntiles = (n + 31) / 32;
+    const int64_t t_first = blockIdx.x * (int64_t)tiles_per_block;
+    const int64_t t_end = t_first + tiles_per_block < ntiles ? t_first + tiles_per_block : ntiles;
+    for (int64_t t0 = t_first; t0 < t_end; t0 += WV) {
+        // every wave of the block runs every round (the phases synchronise);
+        // a wave past the run's end takes a tile with no valid vertex
+        const int64_t t = t0 + wave;
+        const int64_t v = t * 32 + (lane & 31);
+        const bool valid = t < t_end && v < n;
+        const int64_t vs = valid ? v : n - 1;
+        const int64_t vv = visit(io.perm, vs);
+        const TrainInputs in = train_inputs(io, vs, vv);
+        float x[IN0 / 2];
+        tile_input<IN_P, F, BF, PG>(gv, io, in, vs, vv, h, x);
+        float acts[NH][HID_P / 2];
+        float o[16];
+        if constexpr (BF) {
+            mlp_forward<IN_P, HID_P, NH, true, true>(fwd, x, acts, o, lane);
+        } else {
+            mfma_layer_rm<IN_P, HID_P, Plan::rm_stride(0), false>(rm, x, acts[0], lane);
+#pragma unroll
+            for (int i = 0; i < HID_P / 2; ++i) acts[0][i] = fmaxf(acts[0][i], 0.0f);
+#pragma unroll
+            for (int li = 1; li < NH; ++li) {
+                // the hidden layers' rows have one stride, HID_P + 1
+                mfma_layer_rm<HID_P, HID_P, Plan::rm_stride(1), false>(
+                    rm + Plan::rm_off(1) + (li - 1) * HID_P * Plan::rm_stride(1), acts[li - 1],
+                    acts[li], lane);
+#pragma unroll
+                for (int i = 0; i < HID_P / 2; ++i) acts[li][i] = fmaxf(acts[li][i], 0.0f);
+            }
+            mfma_layer_rm<HID_P, 32, Plan::rm_stride(NH), false>(rm + Plan::rm_off(NH),
+                                                                  acts[NH - 1], o, lane);
+        }
+        float d[16];
+        kl_head(o, in, valid, io.invN, h, d, lacc);
+        if (!a.grad) continue;      // loss only (uniform over the grid)
+        // ---- output layer: its dW, then the first delta of the chain
+        float dh[HID_P / 2];
+        dw_phase<Plan, NH, WV, XS>(xb, d, acts[NH - 1], wave, acc, lane);
+        if constexpr (BF) layer<true, 32, HID_P>(bwd, d, dh, lane);
+        else mfma_layer_rm<32, HID_P, Plan::rm_stride(NH), true>(rm + Plan::rm_off(NH), d, dh, lane);
+        __syncthreads();
+        // ---- hidden layers NH-1 .. 1
+        const char *im = bwd + (size_t)HID_P * 32 * ESZ;
+        static_for_down<NH - 1, 1>([&](auto LC) {
+            constexpr int li = decltype(LC)::value;
+#pragma unroll
+            for (int i = 0; i < HID_P / 2; ++i) dh[i] = acts[li][i] > 0.0f ? dh[i] : 0.0f;
+            dw_phase<Plan, li, WV, XS>(xb, dh, acts[li - 1], wave, acc, lane);
+            float nd[HID_P / 2];
+            if constexpr (BF) {
+                layer<true, HID_P, HID_P>(im, dh, nd, lane);
+                im += (size_t)HID_P * HID_P * ESZ;
+            } else {
+                mfma_layer_rm<HID_P, HID_P, Plan::rm_stride(li), true>(rm + Plan::rm_off(li), dh, nd,
+                                                                        lane);
+            }
+#pragma unroll
+            for (int i = 0; i < HID_P / 2; ++i) dh[i] = nd[i];
+            __syncthreads();
+        });
+        // ---- first layer: its dW and the input gradient dG (the grid
+        // features' rows only with NPM-product inputs), stored per tile for
+        // the scatter kernels
+#pragma unroll
+        for (int i = 0; i < HID_P / 2; ++i) dh[i] = acts[0][i] > 0.0f ? dh[i] : 0.0f;
+        dw_phase<Plan, 0, WV, XS>(xb, dh, x, wave, acc, lane);
+        float dG[DGR / 2];
+        if constexpr (BF) layer<true, HID_P, DGR>(im, dh, dG, lane);
+        else mfma_layer_rm<HID_P, DGR, Plan::rm_stride(0), true>(rm, dh, dG, lane);
+        if (t < t_end) {
+            float *dst = a.dg_tiles + (size_t)t * IN0 * 32 + (lane & 31);
+#pragma unroll
+            for (int q = 0; q < DGR / 2; ++q) dst[nf(h, q) * 32] = dG[q];
+        }
+        __syncthreads();
+    }
     // ---- loss partial of the block (FP64)
     red[threadIdx.x] = lacc;
     __syncthreads();
@@ -156,18 +381,8 @@ __global__ __launch_bounds__(256) void k_backward_fused(FusedArgs a, int mlp_wei
     }
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
     if (!a.grad) return;
-    // ---- the block's weight-gradient partial: the waves add theirs in turn
-    // into LDS (the weight images are no longer needed), then one store
-    float *acc = reinterpret_cast<float *>(smem);
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-        if (wave == w) {
-            if (w == 0) dw_flush<IN_P, HID_P, NH, DW_STORE>(acc, a.n_in, a.width, dw, lane);
-            else dw_flush<IN_P, HID_P, NH, DW_ADD>(acc, a.n_in, a.width, dw, lane);
-        }
-        __syncthreads();
-    }
-    float *dst = a.dw_part + (int64_t)blockIdx.x * mlp_weights;
-    for (int i = threadIdx.x; i < mlp_weights; i += blockDim.x) dst[i] = acc[i];
+    dw_write<Plan, NH, WV>(a.dw_part + (int64_t)blockIdx.x * mlp_weights, a.n_in, a.width, wave,
+                           acc, lane);
 }
 
 // Aggregated grid scatter of the per-tile dG (stride `rows` rows of 32 per
@@ -322,38 +537,41 @@ static hipError_t run_query(npm_ctx *ctx, FusedArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
-// Number of waves the backward kernel runs (one partial each).
-static int backward_waves(int64_t n)
+// Blocks of the training kernel: one per compute unit at most (the weight
+// image and the exchange buffer take most of its LDS), WV waves each.
+constexpr int kTrainWaves = 4;
+constexpr int kTrainMaxBlocks = 256;
+static int backward_blocks(int64_t n)
 {
     const int64_t tiles = (n + 31) / 32;
-    return (int)std::max<int64_t>(4, std::min<int64_t>(((tiles + 3) / 4) * 4, 1024));
+    return (int)std::max<int64_t>(1, std::min<int64_t>((tiles + kTrainWaves - 1) / kTrainWaves,
+                                                       kTrainMaxBlocks));
 }
 
-// Dynamic LDS a backward block may take: gfx950's 160 KB per workgroup less
+// Dynamic LDS a training block may take: gfx950's 160 KB per workgroup less
 // room for the kernel's static arrays (level table, FP64 loss partials).
 constexpr size_t kLdsBytes = 160 * 1024 - 4096;
-
-// Waves per block of the backward kernel: four, or two when the staged
-// weight images and four waves' transpose buffers exceed the LDS.
-static int backward_wpb(const FusedArgs &a, int in_p, int hid_p, bool bf, int pg)
-{
-    const size_t img = ((size_t)staged_elems(a, in_p, hid_p, pg) * (bf ? 2 : 4) + 15) / 16 * 16;
-    return img + (size_t)4 * trans_rows(in_p, hid_p) * kStride * sizeof(float) <= kLdsBytes ? 4 : 2;
-}
 
 template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0>
 static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
 {
-    const int waves = backward_waves(a.n);
-    const int wpb = backward_wpb(a, IN_P, HID_P, BF, PG);
-    const int blocks = waves / wpb;
-    const size_t img = ((size_t)staged_elems(a, IN_P, HID_P, PG) * (BF ? 2 : 4) + 15) / 16 * 16;
-    const size_t lds = img + (size_t)wpb * trans_rows(IN_P, HID_P) * kStride * sizeof(float);
+    using Plan = BlockPlan<IN_P, HID_P, NH, kTrainWaves>;
+    const int blocks = backward_blocks(a.n);
+    const int64_t tiles = (a.n + 31) / 32;
+    // a contiguous run of tiles per block, whole rounds of kTrainWaves tiles
+    const int64_t per = (tiles + blocks - 1) / blocks;
+    const int tpb = (int)((per + kTrainWaves - 1) / kTrainWaves * kTrainWaves);
+    const size_t img = BF ? (size_t)staged_elems(a, IN_P, HID_P, PG) * 2
+                          : (size_t)Plan::rm_elems() * 4;
+    if (!BF && (int64_t)Plan::rm_elems() != ctx->net.mlp.rm_elems) return hipErrorInvalidValue;
+    const size_t lds = (img + 15) / 16 * 16 +
+                       (size_t)Plan::max_rows() * Plan::xs(BF) * (BF ? 2 : 4);
     const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
-    if (lds > kLdsBytes || (size_t)count * sizeof(float) > lds) return hipErrorInvalidValue;
-    auto k = k_backward_fused<IN_P, HID_P, NH, F, BF, PG>;
+    if (lds > kLdsBytes) return hipErrorInvalidValue;
+    if (!BF) a.img = ctx->mlp_img + ctx->net.mlp.fwd_elems + ctx->net.mlp.bwd_elems;
+    auto k = k_backward_fused<IN_P, HID_P, NH, F, BF, PG, kTrainWaves>;
     hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * wpb), lds, s, a, count);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * kTrainWaves), lds, s, a, count, tpb, (int)img);
     return hipGetLastError();
 }
 
@@ -513,9 +731,7 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
             if (e != hipSuccess) return e;
         }
     }
-    const int blocks = backward_waves(n) / backward_wpb(a, ctx->net.mlp.in_p, ctx->net.mlp.hid_p,
-                                                        ctx->net.cfg.precision == NPM_PREC_BF16,
-                                                        ctx->net.mlp.sh_degree > 0 ? 1 : 0);
+    const int blocks = backward_blocks(n);
     if (grad) {
         const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
         timed_begin(ctx, "fused_dw_sum", s, &tok);

@@ -36,6 +36,11 @@ struct MlpDesc {
     int64_t fwd_off[NPM_MAX_LAYERS];  // offset of each layer's image in the packed
     int64_t bwd_off[NPM_MAX_LAYERS];  //   forward / backward weight images (elements)
     int64_t fwd_elems, bwd_elems;
+    // Row-major FP32 image of the training kernel: layer L as its padded
+    // out_p x c_L matrix (c_0 = max(in_p, 32), c_L = hid_p otherwise) with
+    // rows c_L + 1 floats apart, read as W (forward) and as W^T (backward)
+    int64_t rm_off[NPM_MAX_LAYERS];
+    int64_t rm_elems;
 };
 
 struct Net {
@@ -73,7 +78,7 @@ struct npm_ctx {
     // Low-precision copies (NPM_PREC_BF16): FP16 grid, BF16 packed MLP images
     void *grid16 = nullptr;
     // Packed MLP weight images (forward and backward), FP32 and BF16
-    float *mlp_img = nullptr;          // [fwd_elems + bwd_elems] FP32
+    float *mlp_img = nullptr;          // [fwd_elems + bwd_elems + rm_elems] FP32
     void *mlp_img16 = nullptr;         // [fwd_elems + bwd_elems] BF16
     // Exponential moving average of the parameters (ema_decay > 0): FP32
     // master, its packed images and (NPM_PREC_BF16) its FP16 grid

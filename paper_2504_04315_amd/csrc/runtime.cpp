@@ -157,9 +157,17 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
         bo += (int64_t)std::max(in_p, 32) * out_p;
     }
     m.bwd_elems = bo;
+    int64_t ro = 0;   // row-major image, layers in order
+    for (int i = 0; i < L.n_layers; ++i) {
+        const int cols = i == 0 ? std::max(m.in_p, 32) : m.hid_p;
+        const int rows = i == L.n_layers - 1 ? 32 : m.hid_p;
+        m.rm_off[i] = ro;
+        ro += (int64_t)rows * (cols + 1);
+    }
+    m.rm_elems = ro;
     const int64_t img = m.fwd_elems + m.bwd_elems;
     const int64_t lowp_grid = c.precision == NPM_PREC_BF16 ? 2 * L.grid_params : 0;
-    L.device_bytes = 16 * L.n_params + 6 * img + (int64_t)kPartials * 8 + 64 + lowp_grid +
+    L.device_bytes = 16 * L.n_params + 6 * img + 4 * m.rm_elems + (int64_t)kPartials * 8 + 64 + lowp_grid +
                      (c.ema_decay > 0.0f ? 4 * L.n_params + 6 * img + lowp_grid : 0);
     if (c.exec_mode == NPM_EXEC_FUSED && !fused_shape_supported(n))
         return bad("no fused kernels for this network shape (fused: F 1, 2 or 4; 16 or 32 grid "
@@ -330,7 +338,7 @@ npm_status npm_create(const npm_config *cfg, npm_ctx **out)
     alloc((void **)&ctx->grads, np * 4);
     alloc((void **)&ctx->adam_m, np * 4);
     alloc((void **)&ctx->adam_v, np * 4);
-    alloc((void **)&ctx->mlp_img, img * 4);
+    alloc((void **)&ctx->mlp_img, (img + net.mlp.rm_elems) * 4);
     alloc((void **)&ctx->mlp_img16, img * 2);
     alloc((void **)&ctx->partials, kPartials * 8);
     alloc((void **)&ctx->stats, 64);
