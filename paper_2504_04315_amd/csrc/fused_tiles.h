@@ -128,6 +128,107 @@ __device__ __forceinline__ void encode_tile(const GridView &gv, int h, float px,
     for (int a = 4 * GROUPS; a < IN_P / 2; ++a) x[a] = 0.0f;
 }
 
+// The grid encoding of a tile split in two, for software pipelining: the
+// corner loads of every level of this half-wave are issued for one tile
+// (encode_issue) and consumed one round later (encode_finish), so that they
+// are in flight while the previous tile's MLP runs.  The loaded words are
+// kept as loaded (FP16 pairs in the precision form) and converted when
+// consumed, so that nothing waits on them early.
+template <int F, bool BF> struct CornerRaw;
+template <> struct CornerRaw<1, false> { using T = float; };
+template <> struct CornerRaw<2, false> { using T = float2; };
+template <> struct CornerRaw<4, false> { using T = float4; };
+template <> struct CornerRaw<1, true> { using T = __half; };
+template <> struct CornerRaw<2, true> { using T = __half2; };
+template <> struct CornerRaw<4, true> { using T = uint2; };
+
+template <int IN_G, int F, bool BF>
+struct TileGather {
+    static constexpr int GROUPS = (IN_G + 7) / 8;
+    static constexpr int PER = 4 / F;
+    static constexpr int NLV = GROUPS * PER;
+    typename CornerRaw<F, BF>::T raw[NLV][8];
+    float fr[NLV][3];
+};
+
+template <int IN_G, int F, bool BF>
+__device__ __forceinline__ void encode_issue(const GridView &gv, int h, float px, float py,
+                                             float pz, TileGather<IN_G, F, BF> &g)
+{
+    using TG = TileGather<IN_G, F, BF>;
+    using RT = typename CornerRaw<F, BF>::T;
+#pragma unroll
+    for (int q = 0; q < TG::NLV; ++q) {
+        const int l = (8 * (q / TG::PER) + 4 * h) / F + q % TG::PER;
+        const int lc = l < gv.n_levels ? l : 0;      // a missing level reads level 0 (weight 0)
+        const int D = gv.res[lc];
+        int cx, cy, cz;
+        lattice_cell(px, D, cx, g.fr[q][0]);
+        lattice_cell(py, D, cy, g.fr[q][1]);
+        lattice_cell(pz, D, cz, g.fr[q][2]);
+        const uint32_t d1 = (uint32_t)D + 1u;
+        const bool hashed = (gv.hashed_mask >> lc) & 1u;
+        const uint32_t off = gv.off[lc];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint32_t X = cx + (b & 1), Y = cy + ((b >> 1) & 1), Z = cz + ((b >> 2) & 1);
+            const uint32_t e = off + (hashed ? ((X ^ (Y * 2654435761u) ^ (Z * 805459861u)) & gv.table_mask)
+                                             : X + d1 * (Y + d1 * Z));
+            if constexpr (BF) g.raw[q][b] = *reinterpret_cast<const RT *>(gv.g16 + (size_t)e * F);
+            else g.raw[q][b] = *reinterpret_cast<const RT *>(gv.g32 + (size_t)e * F);
+        }
+    }
+}
+
+template <int IN_P, int IN_G, int F, bool BF>
+__device__ __forceinline__ void encode_finish(const GridView &gv, int h,
+                                              const TileGather<IN_G, F, BF> &g, float *x)
+{
+    using TG = TileGather<IN_G, F, BF>;
+#pragma unroll
+    for (int q = 0; q < TG::NLV; ++q) {
+        const int l = (8 * (q / TG::PER) + 4 * h) / F + q % TG::PER;
+        const float fx = g.fr[q][0], fy = g.fr[q][1], fz = g.fr[q][2];
+        const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+        float acc[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[f] = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const float w = wx[b & 1] * wy[(b >> 1) & 1] * wz[(b >> 2) & 1];
+            float v[F];
+            const auto &r = g.raw[q][b];
+            if constexpr (BF) {
+                if constexpr (F == 1) {
+                    v[0] = __half2float(r);
+                } else if constexpr (F == 2) {
+                    v[0] = __low2float(r); v[1] = __high2float(r);
+                } else {
+                    const __half2 lo = *reinterpret_cast<const __half2 *>(&r.x);
+                    const __half2 hi = *reinterpret_cast<const __half2 *>(&r.y);
+                    v[0] = __low2float(lo); v[1] = __high2float(lo);
+                    v[2] = __low2float(hi); v[3] = __high2float(hi);
+                }
+            } else {
+                if constexpr (F == 1) {
+                    v[0] = r;
+                } else if constexpr (F == 2) {
+                    v[0] = r.x; v[1] = r.y;
+                } else {
+                    v[0] = r.x; v[1] = r.y; v[2] = r.z; v[3] = r.w;
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < F; ++f) acc[f] += w * v[f];
+        }
+        const bool live = l < gv.n_levels;
+#pragma unroll
+        for (int f = 0; f < F; ++f) x[4 * (q / TG::PER) + (q % TG::PER) * F + f] = live ? acc[f] : 0.0f;
+    }
+#pragma unroll
+    for (int a = 4 * TG::GROUPS; a < IN_P / 2; ++a) x[a] = 0.0f;
+}
+
 // NPM-product inputs (Sec. 4.3) of the tile vertex into the feature
 // registers: features GF .. GF + 2 SHD^2 hold the spherical harmonics of the
 // outgoing direction, then of the normal, then the roughness (a7 = omega_o,

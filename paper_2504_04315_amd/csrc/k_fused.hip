@@ -297,17 +297,49 @@ __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp
     const int64_t ntiles = (n + 31) / 32;
     const int64_t t_first = blockIdx.x * (int64_t)tiles_per_block;
     const int64_t t_end = t_first + tiles_per_block < ntiles ? t_first + tiles_per_block : ntiles;
+    // the visiting slot of this lane in tile tt (the last vertex for a tile
+    // past the run or a lane past the batch)
+    auto slot = [&](int64_t tt) {
+        const int64_t v = tt * 32 + (lane & 31);
+        return tt < t_end && v < n ? v : n - 1;
+    };
+    // Software pipeline over the rounds: a round's grid gathers are issued
+    // during the round before (one wave per SIMD leaves the registers for
+    // them: 8 levels x 8 corners x F = 2 per half-wave on the production
+    // grid), and its inputs are loaded two rounds ahead.  Shapes whose
+    // gathers would not fit beside the rest (F = 1, NPM-product's wide
+    // first layer) gather in the round itself.
+    constexpr bool PIPE = IN_P <= 32 && F >= 2 && PG == 0;
+    constexpr int ING = PG > 0 ? ProductShape<PG>::GF : IN_P;   // grid features
+    TileGather<ING, F, BF> gath;
+    TrainInputs in_next = train_inputs(io, slot(t_first + wave), visit(io.perm, slot(t_first + wave)));
+    TrainInputs in_after = train_inputs(io, slot(t_first + WV + wave),
+                                        visit(io.perm, slot(t_first + WV + wave)));
+    if (PIPE && t_first < t_end)
+        encode_issue<ING, F, BF>(gv, h, in_next.px, in_next.py, in_next.pz, gath);
     for (int64_t t0 = t_first; t0 < t_end; t0 += WV) {
         // every wave of the block runs every round (the phases synchronise);
         // a wave past the run's end takes a tile with no valid vertex
         const int64_t t = t0 + wave;
         const int64_t v = t * 32 + (lane & 31);
         const bool valid = t < t_end && v < n;
-        const int64_t vs = valid ? v : n - 1;
+        const int64_t vs = slot(t);
         const int64_t vv = visit(io.perm, vs);
-        const TrainInputs in = train_inputs(io, vs, vv);
+        const TrainInputs in = in_next;
+        in_next = in_after;
+        const int64_t s2 = slot(t + 2 * WV);
+        in_after = train_inputs(io, s2, visit(io.perm, s2));
         float x[IN0 / 2];
-        tile_input<IN_P, F, BF, PG>(gv, io, in, vs, vv, h, x);
+        if constexpr (PIPE) {
+            encode_finish<IN_P, ING, F, BF>(gv, h, gath, x);
+#pragma unroll
+            for (int i = IN_P / 2; i < IN0 / 2; ++i) x[i] = 0.0f;
+            // the next round's gathers, in flight while this round's MLP runs
+            if (t0 + WV < t_end)
+                encode_issue<ING, F, BF>(gv, h, in_next.px, in_next.py, in_next.pz, gath);
+        } else {
+            tile_input<IN_P, F, BF, PG>(gv, io, in, vs, vv, h, x);
+        }
         float acts[NH][HID_P / 2];
         float o[16];
         if constexpr (BF) {
