@@ -82,8 +82,9 @@ enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
  * NPM_SCATTER_ATOMIC adds each corner's contribution with an FP32 atomic
  * (through a tile's LDS window where its corners fall together);
  * NPM_SCATTER_BINNED first bins the contributions of the hashed levels by
- * table slice and sums each slice in one block (in FP64, rounded once to
- * FP32), then adds it to the gradient.  Device scratch: 16 (1 + 2 F) n bytes
+ * table slice and sums each slice in one block (in FP64, or in 64-bit fixed
+ * point in the precision form; rounded once to FP32), then adds it to the
+ * gradient.  Device scratch: 16 (1 + 2 F) n bytes
  * per binned level (80 n at F = 2), kept in the context.  In a spatially
  * ordered batch only the hashed levels with D_l >= 100 are binned; the others
  * keep the atomic path.  NPM_SCATTER_AUTO bins training batches of 2^15
@@ -96,10 +97,14 @@ enum { NPM_ORDER_AUTO = 0, NPM_ORDER_NONE = 1, NPM_ORDER_SPATIAL = 2 };
 enum { NPM_SCATTER_AUTO = 0, NPM_SCATTER_ATOMIC = 1, NPM_SCATTER_BINNED = 2 };
 
 /* Network configuration (copied at create).
- * Grid (Sec. 5.1): n_levels uniform grids over the unit cube with
- *   resolutions D_l = floor(base * b^l + 1e-6), b = (max/base)^(1/(L-1)),
- *   the last level exactly max_resolution; level l has (D_l+1)^3 lattice
- *   points with feat_per_level features each.  With NPM_GRID_HASH a level
+ * Grid (Sec. 5.1): n_levels uniform grids over the unit cube whose
+ *   resolution grows exponentially from base_resolution to max_resolution:
+ *   D_l = floor(base * b^l + 1e-6), b = (max/base)^(1/(L-1)), the last level
+ *   exactly max_resolution -- or, when resolution[0] != 0, the explicit
+ *   integer table resolution[0 .. n_levels-1] (each 1..65535,
+ *   non-decreasing; entries from n_levels on must be 0; base and max are
+ *   then not used), e.g. a table quoted with the network.  Level l has
+ *   (D_l+1)^3 lattice points with feat_per_level features each.  With NPM_GRID_HASH a level
  *   with more than 2^log2_table_size points stores a 2^log2_table_size
  *   table addressed by the spatial hash (x * 1) ^ (y * 2654435761) ^
  *   (z * 805459861) mod 2^log2_table_size; other levels are dense.
@@ -151,6 +156,7 @@ typedef struct {
     float ema_decay;
     int32_t sh_degree;
     int32_t scatter_mode;
+    int32_t resolution[32];       /* explicit D_l table, or all 0: derive    */
     uint64_t seed;
 } npm_config;
 
@@ -185,9 +191,15 @@ npm_status npm_config_default(npm_config *cfg);
 /* Validates *cfg and fills *out; needs no device.                          */
 npm_status npm_get_layout(const npm_config *cfg, npm_layout *out);
 
-/* Creates a context on the current HIP device: allocates parameters,
+/* Creates a guiding network on the current HIP device: the multiresolution
+ * grid of Sec. 5.1 and the decoder MLP of Sec. 5.3 (with NPM-product inputs,
+ * Sec. 4.3), laid out as npm_get_layout reports.  Allocates parameters,
  * gradients, Adam moments (zero) and initialises the parameters from
- * cfg->seed.  Returns NPM_ERR_NO_DEVICE without a gfx950 device.           */
+ * cfg->seed (grid as grid_init, weights Xavier-uniform).  *out receives the
+ * context, owned by the caller until npm_destroy.  Returns
+ * NPM_ERR_INVALID_ARG for an invalid configuration (nothing allocated),
+ * NPM_ERR_NO_DEVICE without a gfx950 device, NPM_ERR_OOM when device memory
+ * runs out (everything allocated so far is freed).                          */
 npm_status npm_create(const npm_config *cfg, npm_ctx **out);
 
 /* Waits for the context's outstanding work and frees it.  NULL is a no-op. */

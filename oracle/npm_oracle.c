@@ -118,6 +118,29 @@ static void oracle_layers(npmo_net *net)
 /* ------------------------------------------------------------------------ */
 /* Level layout: Sec. 5.1, "D_l grows exponentially".                       */
 /* ------------------------------------------------------------------------ */
+/* Sizes and offsets of the levels from their resolutions: level l has
+ * (D_l+1)^3 lattice points, stored densely unless they outnumber the table
+ * (then the table of 2^log2T entries, addressed by the hash).              */
+static void oracle_levels(npmo_net *net)
+{
+    net->grid_entries = 0;
+    for (int l = 0; l < net->n_levels; ++l) {
+        const int D = net->res[l];
+        double pts = (double)(D + 1) * (double)(D + 1) * (double)(D + 1);
+        if (net->dense_only || pts <= ldexp(1.0, net->log2_table)) {
+            net->hashed[l] = 0;
+            net->size[l] = (int64_t)(D + 1) * (D + 1) * (D + 1);
+        } else {
+            net->hashed[l] = 1;
+            net->size[l] = (int64_t)1 << net->log2_table;
+        }
+        net->offset[l] = net->grid_entries;
+        net->grid_entries += net->size[l];
+    }
+    net->grid_params = net->grid_entries * net->feat;
+    oracle_layers(net);
+}
+
 int npmo_net_init(npmo_net *net, int L, int F, int base_res, int max_res,
                   int log2T, int dense_only, int n_hidden, int width, int K)
 {
@@ -139,21 +162,25 @@ int npmo_net_init(npmo_net *net, int L, int F, int base_res, int max_res,
             D = (int)floor((double)base_res * pow(b, (double)l) + 1e-6);
         }
         net->res[l] = D;
-        double pts = (double)(D + 1) * (double)(D + 1) * (double)(D + 1);
-        if (dense_only || pts <= ldexp(1.0, log2T)) {
-            net->hashed[l] = 0;
-            net->size[l] = (int64_t)(D + 1) * (D + 1) * (D + 1);
-        } else {
-            net->hashed[l] = 1;
-            net->size[l] = (int64_t)1 << log2T;
-        }
-        net->offset[l] = net->grid_entries;
-        net->grid_entries += net->size[l];
     }
-    net->grid_params = net->grid_entries * F;
     net->width = width; net->n_hidden = n_hidden;
     net->n_lobes = K; net->n_out = 4 * K; net->n_layers = n_hidden + 1;
-    oracle_layers(net);
+    oracle_levels(net);
+    return 0;
+}
+
+/* An explicit resolution table res[0 .. n_levels-1] (each 1..65535,
+ * non-decreasing) in place of the exponential growth; the level layout and
+ * the flat offsets follow.                                                 */
+int npmo_net_set_resolution(npmo_net *net, const int32_t *res)
+{
+    if (!net || !res) return -1;
+    for (int l = 0; l < net->n_levels; ++l)
+        if (res[l] < 1 || res[l] > 65535 || (l > 0 && res[l] < res[l - 1])) return -1;
+    for (int l = 0; l < net->n_levels; ++l) net->res[l] = res[l];
+    net->base_res = res[0];
+    net->max_res = res[net->n_levels - 1];
+    oracle_levels(net);
     return 0;
 }
 

@@ -54,6 +54,8 @@ def lib():
         L.npmo_philox.argtypes = [P, P, P]
         L.npmo_uniforms.argtypes = [i64, P, u64, u32, u32, P]
         L.npmo_corners.argtypes = [P, i64, P, P, P]
+        L.npmo_net_set_resolution.argtypes = [P, P]
+        L.npmo_net_set_resolution.restype = i32
         L.npmo_net_set_inputs.argtypes = [P, i32]
         L.npmo_net_set_inputs.restype = i32
         L.npmo_sh.argtypes = [i32, C.c_double, C.c_double, C.c_double, P, P]
@@ -118,10 +120,15 @@ class Net:
     rules (Sec. 5.1 level resolutions; Sec. 5.3 MLP)."""
 
     def __init__(self, n_levels, feat, base_res, max_res, log2_table, dense_only,
-                 n_hidden, width, n_lobes=8, sh_degree=0):
+                 n_hidden, width, n_lobes=8, sh_degree=0, resolution=None):
         self.s = NpmoNet()
         rc = lib().npmo_net_init(C.byref(self.s), n_levels, feat, base_res, max_res,
                                  log2_table, int(dense_only), n_hidden, width, n_lobes)
+        if rc == 0 and resolution:
+            if len(resolution) != n_levels:
+                raise ValueError("oracle: one resolution per level")
+            r = np.ascontiguousarray(resolution, dtype=np.int32)
+            rc = lib().npmo_net_set_resolution(C.byref(self.s), _p(r))
         if rc == 0 and sh_degree:
             rc = lib().npmo_net_set_inputs(C.byref(self.s), sh_degree)
         if rc != 0:

@@ -46,6 +46,9 @@ void npm::set_error(const char *msg) { g_err = msg ? msg : ""; }
 // --------------------------------------------------------------------------
 // Configuration and layout (Sec. 5.1 grid levels, Sec. 5.3 MLP)
 // --------------------------------------------------------------------------
+static_assert(sizeof(((npm_config *)nullptr)->resolution) / sizeof(int32_t) == NPM_MAX_LEVELS,
+              "one resolution per level");
+
 npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
 {
     auto bad = [&](const char *m) { *err = m; return NPM_ERR_INVALID_ARG; };
@@ -58,9 +61,24 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     if (c.n_levels * c.feat_per_level > 32) return bad("n_levels * feat_per_level must be <= 32");
     if (c.grid_kind == NPM_GRID_HASH && (c.log2_table_size < 4 || c.log2_table_size > 26))
         return bad("log2_table_size must be 4..26");
-    if (c.base_resolution < 1 || c.max_resolution < c.base_resolution ||
-        c.max_resolution > 65535)
-        return bad("resolutions must satisfy 1 <= base <= max <= 65535");
+    const bool table = c.resolution[0] != 0;
+    if (table) {
+        for (int l = 0; l < NPM_MAX_LEVELS; ++l) {
+            const int D = c.resolution[l];
+            if (l >= c.n_levels) {
+                if (D != 0) return bad("resolution[] entries from n_levels on must be 0");
+            } else if (D < 1 || D > 65535 || (l > 0 && D < c.resolution[l - 1])) {
+                return bad("resolution[] must hold n_levels values in 1..65535, non-decreasing");
+            }
+        }
+    } else {
+        for (int l = 1; l < NPM_MAX_LEVELS; ++l)
+            if (c.resolution[l] != 0)
+                return bad("resolution[]: a table starts at resolution[0]; all 0 derives it");
+        if (c.base_resolution < 1 || c.max_resolution < c.base_resolution ||
+            c.max_resolution > 65535)
+            return bad("resolutions must satisfy 1 <= base <= max <= 65535");
+    }
     if (c.mlp_width < 1 || c.mlp_width > 64) return bad("mlp_width must be 1..64");
     if (c.mlp_hidden_layers < 1 || c.mlp_hidden_layers > 4) return bad("mlp_hidden_layers must be 1..4");
     if (c.n_lobes != kLobes) return bad("n_lobes must be 8");
@@ -93,7 +111,8 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     const double ratio = (double)c.max_resolution / (double)c.base_resolution;
     for (int l = 0; l < nl; ++l) {
         int D;
-        if (l == nl - 1) D = c.max_resolution;
+        if (table) D = c.resolution[l];
+        else if (l == nl - 1) D = c.max_resolution;
         else if (l == 0) D = c.base_resolution;
         else {
             const double b = std::exp(std::log(ratio) / (double)(nl - 1));

@@ -35,7 +35,8 @@ class npm_config(C.Structure):
         ("exec_mode", C.c_int32), ("grid_init", C.c_int32), ("grid_init_scale", C.c_float),
         ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
         ("batch_order", C.c_int32), ("ema_decay", C.c_float), ("sh_degree", C.c_int32),
-        ("scatter_mode", C.c_int32), ("seed", C.c_uint64),
+        ("scatter_mode", C.c_int32), ("resolution", C.c_int32 * MAX_LEVELS),
+        ("seed", C.c_uint64),
     ]
 
 
@@ -144,6 +145,8 @@ def make_config(net, exec_mode=EXEC_STAGED, precision=None, lr=None, seed=None,
     c.scatter_mode = scatter_mode
     c.ema_decay = ema_decay
     c.sh_degree = getattr(net, "sh_degree", 0) if sh_degree is None else sh_degree
+    for l, d in enumerate(getattr(net, "resolution", None) or ()):
+        c.resolution[l] = d
     return c
 
 

@@ -48,6 +48,7 @@ class NetConfig:
     precision: str = "fp32"      # "fp32" or "bf16" (BF16 MLP + FP16 grid)
     seed: int = 1
     sh_degree: int = 0           # NPM-product: SH bands of omega_o and the normal
+    resolution: tuple = ()       # explicit per-level resolutions (empty: grow base..max)
 
     @property
     def n_in(self):

@@ -117,6 +117,30 @@ def test_invalid_configs_rejected_without_device():
     assert lib.npm_get_layout(C.byref(c), C.byref(out)) == 0
 
 
+def test_explicit_resolution_table_matches_oracle(O):
+    """npm_config.resolution: an explicit integer table (Sec. 5.1 leaves the
+    growth rule open) gives the oracle's layout for the same table; invalid
+    tables are rejected."""
+    from dataclasses import replace
+    table = (5, 7, 13, 13, 40, 97)
+    net = replace(W.TINY, n_levels=6, log2_table=12, width=64, resolution=table)
+    L = B.layout_of(B.make_config(net, exec_mode=B.EXEC_FUSED))
+    on = O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table, net.dense_only,
+               net.n_hidden, net.width, net.n_lobes, resolution=table)
+    assert [L.resolution[l] for l in range(6)] == list(table) == on.res
+    assert [L.hashed[l] for l in range(6)] == on.hashed
+    assert [L.level_offset[l] for l in range(6)] == on.level_offset
+    assert L.n_params == on.n_params
+    lib = B.lib()
+    out = B.npm_layout()
+    for bad in ((5, 4, 13, 13, 40, 97), (0, 7, 13, 13, 40, 97), (5, 7, 13, 13, 40, 70000)):
+        c = B.make_config(replace(net, resolution=bad))
+        assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1, bad
+    c = B.make_config(net)
+    c.resolution[6] = 9                         # an entry past n_levels
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+
+
 def test_moving_average_adds_its_buffers_to_the_layout():
     """A kept moving average (Sec. 5.3's inference weights) costs an FP32
     copy of the parameters, its packed images and, in the precision form,

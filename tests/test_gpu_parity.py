@@ -43,7 +43,8 @@ def adam_hp(net):
 
 def oracle_net(O, net):
     return O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table,
-                 net.dense_only, net.n_hidden, net.width, net.n_lobes, sh_degree=net.sh_degree)
+                 net.dense_only, net.n_hidden, net.width, net.n_lobes, sh_degree=net.sh_degree,
+                 resolution=net.resolution or None)
 
 
 def randomize(model, on, rng, grid_sd=1.0, mlp_gain=2.0):
@@ -453,3 +454,31 @@ def test_query_order_is_invisible(torch, net):
         assert torch.equal(qa["sample_dir"], qb["sample_dir"])
     a.close()
     b.close()
+
+
+# resolutions given as an explicit integer table: not geometric, one level
+# repeated, levels 4 and 5 hashed (T = 2^12)
+TABLE_NET = W.NetConfig(n_levels=6, feat=2, base_res=5, max_res=97, log2_table=12,
+                        dense_only=False, n_hidden=2, width=64, grid_init="uniform",
+                        grid_init_scale=0.1, seed=16, resolution=(5, 7, 13, 13, 40, 97))
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_explicit_resolution_table_parity(O, torch, mode):
+    """npm_config.resolution (Sec. 5.1 leaves the growth of the resolutions
+    open): corner indices bit-exact on random and lattice positions of every
+    level, encoding, raw outputs, the query and the gradient against the
+    oracle given the same table."""
+    model = B.NPM(B.make_config(TABLE_NET, exec_mode=MODES[mode], batch_order=B.ORDER_SPATIAL))
+    on = oracle_net(O, TABLE_NET)
+    assert on.res == list(TABLE_NET.resolution)
+    rng = np.random.default_rng(17)
+    params = randomize(model, on, rng, grid_sd=0.5)
+    batch = W.make_batch("surface", 6001, seed=63)
+    msgs = check_stages(O, torch, model, on, params, batch.pos)
+    msgs += check_stages(O, torch, model, on, params, W.edge_positions(rng, 4096, on.res))
+    m2, _ = check_query(O, torch, model, on, params, batch)
+    m3, _, _ = check_backward(O, torch, model, on, params, W.make_batch("surface", 5003, seed=64),
+                              "table")
+    print("\n".join(msgs + m2 + m3))
+    model.close()

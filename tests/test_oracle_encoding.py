@@ -31,6 +31,41 @@ def test_level_tables(O):
     assert paper.res[0] == 8 and paper.res[-1] == 86 and sorted(paper.res) == paper.res
 
 
+@pytest.mark.parametrize("L,base,mx", [(4, 8, 64), (16, 16, 2048), (8, 8, 86), (12, 5, 700)])
+def test_level_resolutions_are_floors_of_the_exact_exponential(O, L, base, mx):
+    """The reading of "grows exponentially": D_l = floor(base (max/base)^(l/(L-1)))
+    of the exact real value (evaluated with 50 significant digits here), the
+    last level forced to max.  Where that value is an integer (power-of-two
+    ratios) the floating-point evaluation must not fall below it."""
+    import mpmath
+    mpmath.mp.dps = 50
+    net = O.Net(L, 2, base, mx, 19, True, 1, 8)
+    exact = [int(mpmath.floor(mpmath.mpf(base) * (mpmath.mpf(mx) / base) ** (mpmath.mpf(l) / (L - 1))
+                              + mpmath.mpf(10) ** -30)) for l in range(L - 1)] + [mx]
+    assert net.res == exact
+
+
+def test_explicit_resolution_table(O):
+    """An explicit table replaces the growth rule; the layout follows it
+    (dense while (D+1)^3 fits the table, offsets the running sums), and the
+    table equal to the derived one gives the derived layout."""
+    table = [5, 7, 13, 13, 40, 97]
+    net = O.Net(6, 2, 4, 64, 12, False, 2, 16, resolution=table)
+    assert net.res == table
+    for d, h, sz in zip(net.res, net.hashed, net.level_size):
+        assert h == int((d + 1) ** 3 > 2 ** 12)
+        assert sz == (2 ** 12 if h else (d + 1) ** 3)
+    assert net.level_offset == list(np.cumsum([0] + net.level_size[:-1]))
+    assert net.grid_params == 2 * sum(net.level_size)
+    derived = O.Net(16, 2, 16, 2048, 19, False, 3, 64)
+    again = O.Net(16, 2, 16, 2048, 19, False, 3, 64, resolution=derived.res)
+    assert (again.res, again.level_offset, again.n_params) == \
+           (derived.res, derived.level_offset, derived.n_params)
+    for bad in ([5, 4, 13, 13, 40, 97], [0, 7, 13, 13, 40, 97], [5, 7, 13, 13, 40, 70000]):
+        with pytest.raises(ValueError):
+            O.Net(6, 2, 4, 64, 12, False, 2, 16, resolution=bad)
+
+
 def _grid_net(O):
     # two dense power-of-two levels plus a hashed one (T = 2^9 < 33^3)
     return O.Net(3, 2, 4, 32, 9, False, 1, 8)
