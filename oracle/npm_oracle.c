@@ -32,6 +32,8 @@
  *     direction and the surface normal, encoded with spherical harmonics, and
  *     the roughness, as extra inputs after G(x); and the moving average of
  *     the weights used for inference (Sec. 5.3).
+ *   - Sec. 6.3 "Discussion", path-guiding extensions: the BSDF-selection
+ *     probability learned by the network.
  *
  * Readings where the paper is silent (all of them documented in the design
  * notes of the repository, and fixed identically by the library):
@@ -58,12 +60,18 @@
  *     (vertex lo, vertex hi, stream, sample) and key (seed lo, seed hi),
  *     u = (word >> 8) * 2^-24; lobe selection takes the first k with
  *     u0*S < C_k over the inclusive prefix sums C of lambda (S = C_{K-1}),
- *     falling back to K-1.
+ *     falling back to K-1;
+ *   - the learned selection probability (the paper names the extension and
+ *     gives no formula) is one more raw output c', c = sigmoid(c'), trained
+ *     by the Sec. 4.2 KL estimator applied to the renderer's one-sample
+ *     mixture c p_bsdf + (1 - c) V with V held fixed in that term, the
+ *     samples weighted as in the mixture's term.
  *
  * Flat parameter layout (the one interface shared with the library): the
  * grid tables first, level after level, entry-major with F features per entry
  * (entry e of level l, feature f at (offset_l + e)*F + f); then the weight
- * matrices W_0 .. W_{n_hidden}, each row-major [out][in].
+ * matrices W_0 .. W_{n_hidden}, each row-major [out][in]; with the selection
+ * output the last matrix has 4K + 1 rows, the selection logit's last.
  *
  * Parity pins: every function here is pinned by a CPU test against the
  * mathematics (closed forms, quadrature, finite differences, invariants,
@@ -80,6 +88,7 @@
 #define NPMO_MAX_LAYERS 8
 #define NPMO_MAX_WIDTH 256
 #define NPMO_MAX_LOBES 16
+#define NPMO_MAX_OUT (4 * NPMO_MAX_LOBES + 1)   /* lobe outputs, selection logit */
 
 typedef struct {
     int64_t size[NPMO_MAX_LEVELS];    /* table entries of each level          */
@@ -97,6 +106,7 @@ typedef struct {
     int32_t n_in, width, n_hidden, n_lobes, n_layers, n_out;
     int32_t sh_degree;                /* NPM-product: SH bands of omega_o, n   */
     int32_t n_aux;                    /* extra inputs after G(x) (0: radiance) */
+    int32_t select;                   /* 1: output 4K is the selection logit  */
 } npmo_net;
 
 static const double PI = 3.14159265358979323846264338327950288;
@@ -165,6 +175,7 @@ int npmo_net_init(npmo_net *net, int L, int F, int base_res, int max_res,
     }
     net->width = width; net->n_hidden = n_hidden;
     net->n_lobes = K; net->n_out = 4 * K; net->n_layers = n_hidden + 1;
+    net->select = 0;
     oracle_levels(net);
     return 0;
 }
@@ -181,6 +192,20 @@ int npmo_net_set_resolution(npmo_net *net, const int32_t *res)
     net->base_res = res[0];
     net->max_res = res[net->n_levels - 1];
     oracle_levels(net);
+    return 0;
+}
+
+/* Learned BSDF-selection probability (Sec. 6.3, Discussion, first of the
+ * path-guiding extensions): one more raw output c' after the 4K lobe
+ * outputs (one more row of the last weight matrix); the probability that
+ * the renderer samples the BSDF rather than the mixture is
+ * c = 1 / (1 + e^{-c'}).  on = 0 restores the plain network.               */
+int npmo_net_set_selection(npmo_net *net, int on)
+{
+    if (!net) return -1;
+    net->select = on ? 1 : 0;
+    net->n_out = 4 * net->n_lobes + net->select;
+    oracle_layers(net);
     return 0;
 }
 
@@ -598,12 +623,13 @@ void npmo_query(const npmo_net *net, int64_t n, const float *pos, const float *a
                 double *G_out /* [n][n_in] or NULL */, double *raw_out /* [n][4K] or NULL */,
                 double *lobes /* [n][K][4] or NULL */, double *logpdf /* [n] or NULL */,
                 double *sdir /* [n][3] or NULL */, double *slogpdf /* [n] or NULL */,
-                int32_t *slobe /* [n] or NULL */, double *smargin /* [n] or NULL */)
+                int32_t *slobe /* [n] or NULL */, double *smargin /* [n] or NULL */,
+                double *sel /* [n] selection probability c, or NULL */)
 {
     int K = net->n_lobes;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double G[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES];
+        double G[NPMO_MAX_WIDTH], raw[NPMO_MAX_OUT];
         double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
         oracle_lobe lob[NPMO_MAX_LOBES];
         float a7[7];
@@ -614,6 +640,7 @@ void npmo_query(const npmo_net *net, int64_t n, const float *pos, const float *a
         oracle_map(net, raw, lob);
         if (G_out) for (int j = 0; j < net->n_in; ++j) G_out[i * net->n_in + j] = G[j];
         if (raw_out) for (int j = 0; j < net->n_out; ++j) raw_out[i * net->n_out + j] = raw[j];
+        if (sel && net->select) sel[i] = 1.0 / (1.0 + exp(-raw[4 * K]));
         if (lobes)
             for (int k = 0; k < K; ++k) {
                 double *o = lobes + (i * K + k) * 4;
@@ -700,6 +727,57 @@ static double oracle_loss_grad_one(const npmo_net *net, const double *raw, const
     return g * lv;
 }
 
+/* Learned selection probability (Sec. 6.3): the renderer draws a direction
+ * from the BSDF with probability c and from the mixture otherwise, so its
+ * one-sample MIS density is p_c(w) = c p_bsdf(w) + (1 - c) V(w).  The KL
+ * divergence of Sec. 4.2 from the target D to p_c, estimated with the same
+ * samples and weights w_j = D_j / p~_j, gives the loss term
+ * -(w_j / N) log p_c(w_j) and
+ *   d / dc' = -(w_j / N) c (1 - c) (p_bsdf - V) / p_c,
+ * with V held fixed: the mixture keeps its own term, and this one moves
+ * only c.  A sample whose BSDF density is not finite and >= 0 (a delta
+ * lobe, a missing value) contributes nothing to it.                       */
+static double oracle_select_weight(double wgt, float bsdf)
+{
+    return (isfinite(bsdf) && bsdf >= 0.0f) ? wgt : 0.0;
+}
+
+static double softplus(double x) { return x > 0.0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
+
+/* Returns the sample's selection loss term; writes d/dc' to *dsel.         */
+static double oracle_select_one(const npmo_net *net, const double *raw, const double w3[3],
+                                double wsel, float bsdf, double invN, double *dsel)
+{
+    *dsel = 0.0;
+    if (wsel == 0.0) return 0.0;
+    oracle_lobe lob[NPMO_MAX_LOBES];
+    oracle_map(net, raw, lob);
+    double lv = oracle_logpdf(net, lob, w3, NULL);
+    double cp = raw[4 * net->n_lobes];
+    double c = 1.0 / (1.0 + exp(-cp));
+    double lp = log((double)bsdf);                       /* -inf for p_bsdf = 0 */
+    double a = lp - softplus(-cp), b = lv - softplus(cp);  /* log c p_bsdf, log (1-c) V */
+    double m = a > b ? a : b;
+    double lq = m + log(exp(a - m) + exp(b - m));        /* log p_c */
+    double g = -wsel * invN;
+    *dsel = g * c * (1.0 - c) * (exp(lp - lq) - exp(lv - lq));
+    return g * lq;
+}
+
+/* d loss / d raw of one sample: the mixture's term, then the selection
+ * output's (when the network has one).                                    */
+static double oracle_draw_all(const npmo_net *net, const double *raw, const double w3[3],
+                              double wgt, float bsdf, double invN, double *draw, double *lsel)
+{
+    double l = oracle_loss_grad_one(net, raw, w3, wgt, invN, draw);
+    double s = 0.0;
+    if (net->select)
+        s = oracle_select_one(net, raw, w3, oracle_select_weight(wgt, bsdf), bsdf, invN,
+                              &draw[4 * net->n_lobes]);
+    if (lsel) *lsel = s;
+    return l;
+}
+
 /* Condition scale of d loss / d raw for one sample: the first-order bound on
  * the error of an FP32 evaluation, in units of the unit roundoff, from two
  * independent sources, which add:
@@ -714,9 +792,15 @@ static double oracle_loss_grad_one(const npmo_net *net, const double *raw, const
  *   - the raw outputs' own rounding (condition rawcond_i from the MLP
  *     forward), carried through the head's Jacobian:
  *     sum_i |d draw_j / d raw_i| rawcond_i, the Jacobian taken by central
- *     differences of oracle_loss_grad_one in FP64.                         */
+ *     differences of oracle_draw_all in FP64.
+ * The selection output's head rounding: its few products and the sigmoid
+ * (a small multiple of |d draw / dc'|), plus the error of the log-ratio
+ * t = log p_bsdf - log V through d draw / dt = g c (1 - c) p_bsdf V / p_c^2;
+ * t's error (in units of the roundoff) is |log p_bsdf| + |log V| + |t| plus
+ * the r-weighted sizes of the log terms that log V sums.                   */
 static void oracle_head_cond(const npmo_net *net, const double *raw, const double *rawcond,
-                             const double w3[3], double wgt, double invN, double *cdraw)
+                             const double w3[3], double wgt, float bsdf, double invN,
+                             double *cdraw)
 {
     int K = net->n_lobes;
     for (int j = 0; j < net->n_out; ++j) cdraw[j] = 0.0;
@@ -743,15 +827,36 @@ static void oracle_head_cond(const npmo_net *net, const double *raw, const doubl
         cdraw[4 * k + 2] = g * r * (1.0 + 2.0 * kap / expm1(2.0 * kap) + kap * (am + 1.0)) * resp;
         cdraw[4 * k + 3] = g * (r + b->lambda) * resp;
     }
-    double rp[4 * NPMO_MAX_LOBES], dp[4 * NPMO_MAX_LOBES], dm[4 * NPMO_MAX_LOBES];
+    double wsel = net->select ? oracle_select_weight(wgt, bsdf) : 0.0;
+    if (wsel != 0.0) {
+        double cp = raw[4 * K], c = 1.0 / (1.0 + exp(-cp)), dsel;
+        oracle_select_one(net, raw, w3, wsel, bsdf, invN, &dsel);
+        double tsum = 4.0 + fabs(lv);
+        for (int k = 0; k < K; ++k) {
+            double d = lob[k].mu[0] * w3[0] + lob[k].mu[1] * w3[1] + lob[k].mu[2] * w3[2];
+            tsum += exp(terms[k] - lv) * (fabs(lob[k].loglambda) +
+                                          fabs(log_vmf_norm(lob[k].kappa)) +
+                                          lob[k].kappa * (fabs(d) + 1.0));
+        }
+        double tterm = 0.0;
+        if (bsdf > 0.0f) {
+            double lp = log((double)bsdf);
+            double a = lp - softplus(-cp), b = lv - softplus(cp), m = a > b ? a : b;
+            double lq = m + log(exp(a - m) + exp(b - m));
+            tterm = fabs(wsel * invN) * c * (1.0 - c) * exp(lp + lv - 2.0 * lq) *
+                    (tsum + fabs(lp) + fabs(lp - lv));
+        }
+        cdraw[4 * K] = 8.0 * fabs(dsel) + tterm;
+    }
+    double rp[NPMO_MAX_OUT], dp[NPMO_MAX_OUT], dm[NPMO_MAX_OUT];
     for (int i = 0; i < net->n_out; ++i) {
         if (rawcond[i] == 0.0) continue;
         double h = 1e-5 * (fabs(raw[i]) > 1.0 ? fabs(raw[i]) : 1.0);
         for (int j = 0; j < net->n_out; ++j) rp[j] = raw[j];
         rp[i] = raw[i] + h;
-        oracle_loss_grad_one(net, rp, w3, wgt, invN, dp);
+        oracle_draw_all(net, rp, w3, wgt, bsdf, invN, dp, NULL);
         rp[i] = raw[i] - h;
-        oracle_loss_grad_one(net, rp, w3, wgt, invN, dm);
+        oracle_draw_all(net, rp, w3, wgt, bsdf, invN, dm, NULL);
         for (int j = 0; j < net->n_out; ++j)
             cdraw[j] += fabs(dp[j] - dm[j]) / (2.0 * h) * rawcond[i];
     }
@@ -759,14 +864,17 @@ static void oracle_head_cond(const npmo_net *net, const double *raw, const doubl
 
 double npmo_loss_grad(const npmo_net *net, int64_t n, int64_t n_total, const double *raw,
                       const float *dir /* [3][n] */, const float *rad, const float *spdf,
-                      double *draw /* [n][4K] */)
+                      const float *bsdf /* [n] or NULL */, double *draw /* [n][n_out] */,
+                      double *loss_sel /* or NULL */)
 {
-    double invN = 1.0 / (double)n_total, loss = 0.0;
+    double invN = 1.0 / (double)n_total, loss = 0.0, lsel = 0.0;
     for (int64_t i = 0; i < n; ++i) {
-        double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
-        loss += oracle_loss_grad_one(net, raw + i * net->n_out, w3, oracle_weight(rad[i], spdf[i]),
-                                     invN, draw + i * net->n_out);
+        double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]}, ls;
+        loss += oracle_draw_all(net, raw + i * net->n_out, w3, oracle_weight(rad[i], spdf[i]),
+                                bsdf ? bsdf[i] : NAN, invN, draw + i * net->n_out, &ls);
+        lsel += ls;
     }
+    if (loss_sel) *loss_sel = lsel;
     return loss;
 }
 
@@ -782,12 +890,12 @@ double npmo_loss_grad(const npmo_net *net, int64_t n, int64_t n_total, const dou
  * cond(dW_ok) += cond(dz_o) |h_k| + |dz_o| cond(h_k); the grid entry of a
  * corner gets w_c cond(dG).                                               */
 static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, const float *aux7,
-                                     const double w3[3], double wgt, double invN,
+                                     const double w3[3], double wgt, float bsdf, double invN,
                                      const double *params, double *gcond)
 {
     int L = net->n_levels, F = net->feat;
-    double G[NPMO_MAX_WIDTH], Gc[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES], rawc[4 * NPMO_MAX_LOBES];
-    double draw[4 * NPMO_MAX_LOBES], cdraw[4 * NPMO_MAX_LOBES];
+    double G[NPMO_MAX_WIDTH], Gc[NPMO_MAX_WIDTH], raw[NPMO_MAX_OUT], rawc[NPMO_MAX_OUT];
+    double draw[NPMO_MAX_OUT], cdraw[NPMO_MAX_OUT];
     double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH], cacts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
     double delta[NPMO_MAX_WIDTH], cdelta[NPMO_MAX_WIDTH], prev[NPMO_MAX_WIDTH], cprev[NPMO_MAX_WIDTH];
     int64_t idx[NPMO_MAX_LEVELS * 8];
@@ -796,8 +904,8 @@ static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, con
     oracle_encode_one(net, pos3[0], pos3[1], pos3[2], params, G, Gc);
     oracle_aux_one(net, aux7, G, Gc);
     oracle_mlp_cond_one(net, G, Gc, params, acts, cacts, raw, rawc);
-    oracle_loss_grad_one(net, raw, w3, wgt, invN, draw);
-    oracle_head_cond(net, raw, rawc, w3, wgt, invN, cdraw);
+    oracle_draw_all(net, raw, w3, wgt, bsdf, invN, draw, NULL);
+    oracle_head_cond(net, raw, rawc, w3, wgt, bsdf, invN, cdraw);
     for (int j = 0; j < net->n_out; ++j) { delta[j] = draw[j]; cdelta[j] = cdraw[j]; }
     for (int li = net->n_layers - 1; li >= 0; --li) {
         const double *W = params + net->layer_offset[li];
@@ -860,7 +968,8 @@ static void oracle_add_copies(int T, int m, double *const *acc, const double *bu
 
 void npmo_backward_cond(const npmo_net *net, int64_t n, int64_t n_total, const float *pos,
                         const float *aux /* [7][n] or NULL */, const float *dir, const float *rad,
-                        const float *spdf, const double *params,
+                        const float *spdf, const float *bsdf /* [n] or NULL */,
+                        const double *params,
                         double *gcond /* [n_params], accumulated */)
 {
     double invN = 1.0 / (double)n_total;
@@ -876,8 +985,8 @@ void npmo_backward_cond(const npmo_net *net, int64_t n, int64_t n_total, const f
             float p3[3] = {pos[i], pos[n + i], pos[2 * n + i]}, a7[7];
             double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
             oracle_aux_fetch(aux, n, i, a7);
-            oracle_backward_cond_one(net, p3, a7, w3, oracle_weight(rad[i], spdf[i]), invN,
-                                     params, gc);
+            oracle_backward_cond_one(net, p3, a7, w3, oracle_weight(rad[i], spdf[i]),
+                                     bsdf ? bsdf[i] : NAN, invN, params, gc);
         }
     }
     if (T > 1) {
@@ -891,11 +1000,12 @@ void npmo_backward_cond(const npmo_net *net, int64_t n, int64_t n_total, const f
  * contributions (and their magnitudes) into grad (gabs). */
 static double oracle_backward_one(const npmo_net *net, int64_t n, int64_t i, const float *pos,
                                   const float *aux, const float *dir, const float *rad,
-                                  const float *spdf, const double *params, double invN,
-                                  double *grad, double *gabs, double *draw_out, double *dG_out)
+                                  const float *spdf, const float *bsdf, const double *params,
+                                  double invN, double *grad, double *gabs, double *draw_out,
+                                  double *dG_out, double *lsel)
 {
     int L = net->n_levels, F = net->feat;
-    double G[NPMO_MAX_WIDTH], raw[4 * NPMO_MAX_LOBES], draw[4 * NPMO_MAX_LOBES];
+    double G[NPMO_MAX_WIDTH], raw[NPMO_MAX_OUT], draw[NPMO_MAX_OUT];
     double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
     double delta[NPMO_MAX_WIDTH], prev[NPMO_MAX_WIDTH];
     int64_t idx[NPMO_MAX_LEVELS * 8];
@@ -906,7 +1016,8 @@ static double oracle_backward_one(const npmo_net *net, int64_t n, int64_t i, con
     oracle_aux_one(net, a7, G, NULL);
     oracle_mlp_one(net, G, params, acts, raw, NULL);
     double w3[3] = {dir[i], dir[n + i], dir[2 * n + i]};
-    double loss = oracle_loss_grad_one(net, raw, w3, oracle_weight(rad[i], spdf[i]), invN, draw);
+    double loss = oracle_draw_all(net, raw, w3, oracle_weight(rad[i], spdf[i]),
+                                  bsdf ? bsdf[i] : NAN, invN, draw, lsel);
     if (draw_out) for (int j = 0; j < net->n_out; ++j) draw_out[i * net->n_out + j] = draw[j];
     /* delta holds dLoss/d(output of layer i), i from last to first.        */
     for (int j = 0; j < net->n_out; ++j) delta[j] = draw[j];
@@ -945,15 +1056,16 @@ static double oracle_backward_one(const npmo_net *net, int64_t n, int64_t i, con
 
 double npmo_backward(const npmo_net *net, int64_t n, int64_t n_total, const float *pos,
                      const float *aux /* [7][n] or NULL */, const float *dir, const float *rad,
-                     const float *spdf, const double *params,
+                     const float *spdf, const float *bsdf /* [n] or NULL */, const double *params,
                      double *grad /* [n_params] */, double *gabs /* [n_params] or NULL */,
-                     double *draw_out /* [n][4K] or NULL */, double *dG_out /* [n][n_in] or NULL */)
+                     double *draw_out /* [n][n_out] or NULL */,
+                     double *dG_out /* [n][n_in] or NULL */, double *loss_sel /* or NULL */)
 {
     double invN = 1.0 / (double)n_total;
     int64_t np = net->n_params;
     int m = gabs ? 2 : 1;
     int T = oracle_threads(n, np, m);
-    double tloss[256];
+    double tloss[256], tsel[256];
     if (T > 256) T = 256;
     double *buf = T > 1 ? calloc((size_t)m * (T - 1) * np, sizeof(double)) : NULL;
     if (!buf) T = 1;
@@ -962,14 +1074,18 @@ double npmo_backward(const npmo_net *net, int64_t n, int64_t n_total, const floa
         int t = omp_get_thread_num();
         double *g = t == 0 ? grad : buf + (size_t)(t - 1) * np;
         double *a = !gabs ? NULL : (t == 0 ? gabs : buf + (size_t)(T - 1 + t - 1) * np);
-        double l = 0.0;
-        for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i)
-            l += oracle_backward_one(net, n, i, pos, aux, dir, rad, spdf, params, invN, g, a,
-                                     draw_out, dG_out);
+        double l = 0.0, ls = 0.0, s;
+        for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i) {
+            l += oracle_backward_one(net, n, i, pos, aux, dir, rad, spdf, bsdf, params, invN, g,
+                                     a, draw_out, dG_out, &s);
+            ls += s;
+        }
         tloss[t] = l;
+        tsel[t] = ls;
     }
-    double loss = 0.0;
-    for (int t = 0; t < T; ++t) loss += tloss[t];
+    double loss = 0.0, lsel = 0.0;
+    for (int t = 0; t < T; ++t) { loss += tloss[t]; lsel += tsel[t]; }
+    if (loss_sel) *loss_sel = lsel;
     if (T > 1) {
         double *acc[2] = {grad, gabs};
         oracle_add_copies(T, m, acc, buf, np);

@@ -35,7 +35,7 @@ class NpmoNet(C.Structure):
         ("dense_only", C.c_int32), ("base_res", C.c_int32), ("max_res", C.c_int32),
         ("n_in", C.c_int32), ("width", C.c_int32), ("n_hidden", C.c_int32),
         ("n_lobes", C.c_int32), ("n_layers", C.c_int32), ("n_out", C.c_int32),
-        ("sh_degree", C.c_int32), ("n_aux", C.c_int32),
+        ("sh_degree", C.c_int32), ("n_aux", C.c_int32), ("select", C.c_int32),
     ]
 
 
@@ -58,18 +58,20 @@ def lib():
         L.npmo_net_set_resolution.restype = i32
         L.npmo_net_set_inputs.argtypes = [P, i32]
         L.npmo_net_set_inputs.restype = i32
+        L.npmo_net_set_selection.argtypes = [P, i32]
+        L.npmo_net_set_selection.restype = i32
         L.npmo_sh.argtypes = [i32, C.c_double, C.c_double, C.c_double, P, P]
         L.npmo_encode.argtypes = [P, i64, P, P, P, P, P]
         L.npmo_mlp_forward.argtypes = [P, i64, P, P, P, P]
         L.npmo_head.argtypes = [P, i64, P, P]
         L.npmo_logpdf.argtypes = [P, i64, P, P, P]
-        L.npmo_query.argtypes = [P, i64, P, P, P, P, u64, u32, P, P, P, P, P, P, P, P, P]
+        L.npmo_query.argtypes = [P, i64, P, P, P, P, u64, u32, P, P, P, P, P, P, P, P, P, P]
         L.npmo_sample_raw.argtypes = [P, i64, P, P, P, P]
-        L.npmo_loss_grad.argtypes = [P, i64, i64, P, P, P, P, P]
+        L.npmo_loss_grad.argtypes = [P, i64, i64, P, P, P, P, P, P, P]
         L.npmo_loss_grad.restype = C.c_double
-        L.npmo_backward.argtypes = [P, i64, i64, P, P, P, P, P, P, P, P, P, P]
+        L.npmo_backward.argtypes = [P, i64, i64, P, P, P, P, P, P, P, P, P, P, P, P]
         L.npmo_backward.restype = C.c_double
-        L.npmo_backward_cond.argtypes = [P, i64, i64, P, P, P, P, P, P, P]
+        L.npmo_backward_cond.argtypes = [P, i64, i64, P, P, P, P, P, P, P, P]
         L.npmo_adam.argtypes = [i64, P, P, P, P, i64, C.c_double, C.c_double, C.c_double,
                                 C.c_double]
         L.npmo_ema.argtypes = [i64, P, P, C.c_double]
@@ -120,7 +122,7 @@ class Net:
     rules (Sec. 5.1 level resolutions; Sec. 5.3 MLP)."""
 
     def __init__(self, n_levels, feat, base_res, max_res, log2_table, dense_only,
-                 n_hidden, width, n_lobes=8, sh_degree=0, resolution=None):
+                 n_hidden, width, n_lobes=8, sh_degree=0, resolution=None, select=False):
         self.s = NpmoNet()
         rc = lib().npmo_net_init(C.byref(self.s), n_levels, feat, base_res, max_res,
                                  log2_table, int(dense_only), n_hidden, width, n_lobes)
@@ -131,9 +133,12 @@ class Net:
             rc = lib().npmo_net_set_resolution(C.byref(self.s), _p(r))
         if rc == 0 and sh_degree:
             rc = lib().npmo_net_set_inputs(C.byref(self.s), sh_degree)
+        if rc == 0 and select:
+            rc = lib().npmo_net_set_selection(C.byref(self.s), 1)
         if rc != 0:
             raise ValueError("oracle: invalid network shape")
         self.sh_degree, self.n_aux = self.s.sh_degree, self.s.n_aux
+        self.select = bool(self.s.select)
         s = self.s
         self.n_levels, self.feat, self.n_in = s.n_levels, s.feat, s.n_in
         self.n_out, self.n_lobes, self.n_params = s.n_out, s.n_lobes, s.n_params
@@ -230,7 +235,8 @@ def sample_raw(net, raw, u):
 
 def query(net, pos, params, dirs=None, seed=0, stream=0, vid=None, aux=None):
     """Full query: returns a dict of G, raw, lobes [n][K][4], logpdf (if dirs),
-    sample dir [n][3], sample logpdf, sampled lobe and CDF margin."""
+    sample dir [n][3], sample logpdf, sampled lobe, CDF margin and, on a
+    network with the selection output, the selection probability sel [n]."""
     n = pos.shape[1]
     pos = _f32soa(pos, n)
     ax = _aux(net, aux, n)
@@ -241,29 +247,53 @@ def query(net, pos, params, dirs=None, seed=0, stream=0, vid=None, aux=None):
                lobes=np.zeros((n, net.n_lobes, 4)),
                logpdf=np.zeros(n) if d is not None else None,
                sdir=np.zeros((n, 3)), slogpdf=np.zeros(n), slobe=np.zeros(n, dtype=np.int32),
-               margin=np.zeros(n))
+               margin=np.zeros(n), sel=np.zeros(n) if net.select else None)
     lib().npmo_query(net.ref, n, _p(pos), _p(ax), _p(d), _p(v), seed, stream, _p(params),
                      _p(out["G"]), _p(out["raw"]), _p(out["lobes"]), _p(out["logpdf"]),
-                     _p(out["sdir"]), _p(out["slogpdf"]), _p(out["slobe"]), _p(out["margin"]))
+                     _p(out["sdir"]), _p(out["slogpdf"]), _p(out["slobe"]), _p(out["margin"]),
+                     _p(out["sel"]))
     return out
 
 
+def _bsdf(bsdf, n):
+    if bsdf is None:
+        return None
+    b = np.ascontiguousarray(bsdf, dtype=np.float32)
+    assert b.shape == (n,), b.shape
+    return b
+
+
 def loss_grad(net, raw, dirs, rad, spdf, n_total=None):
+    """Mixture loss and d loss / d raw [n][n_out] from raw outputs."""
+    loss, _, draw = loss_grad_select(net, raw, dirs, rad, spdf, None, n_total)
+    return loss, draw
+
+
+def loss_grad_select(net, raw, dirs, rad, spdf, bsdf, n_total=None):
+    """The mixture's loss, the selection term's loss and d loss / d raw
+    [n][n_out] (the selection logit's column last) from raw outputs; bsdf
+    [n] is the BSDF density of each sample's direction (None: no selection
+    term)."""
     raw = np.ascontiguousarray(raw, dtype=np.float64)
     n = raw.shape[0]
     dirs = _f32soa(dirs, n)
     rad = np.ascontiguousarray(rad, dtype=np.float32)
     spdf = np.ascontiguousarray(spdf, dtype=np.float32)
+    b = _bsdf(bsdf, n)
     draw = np.zeros((n, net.n_out))
+    lsel = C.c_double(0.0)
     loss = lib().npmo_loss_grad(net.ref, n, n if n_total is None else n_total, _p(raw), _p(dirs),
-                                _p(rad), _p(spdf), _p(draw))
-    return loss, draw
+                                _p(rad), _p(spdf), _p(b), _p(draw), C.byref(lsel))
+    return loss, lsel.value, draw
 
 
 def backward(net, pos, dirs, rad, spdf, params, n_total=None, with_abs=True, with_vertex=False,
-             aux=None):
+             aux=None, bsdf=None):
     """Gradient of the surrogate loss w.r.t. the flat parameters (float64),
-    the sum of |contributions| per parameter, and the loss value."""
+    the sum of |contributions| per parameter, and the loss value (loss: the
+    mixture's term; loss_sel: the selection term, with bsdf [n] the BSDF
+    density of each sample's direction on a network with the selection
+    output)."""
     n = pos.shape[1]
     pos = _f32soa(pos, n)
     ax = _aux(net, aux, n)
@@ -275,15 +305,18 @@ def backward(net, pos, dirs, rad, spdf, params, n_total=None, with_abs=True, wit
     gabs = np.zeros(net.n_params) if with_abs else None
     draw = np.zeros((n, net.n_out)) if with_vertex else None
     dG = np.zeros((n, net.n_in)) if with_vertex else None
-    loss = lib().npmo_backward(net.ref, n, n if n_total is None else n_total, _p(pos), _p(ax), _p(dirs),
-                               _p(rad), _p(spdf), _p(params), _p(grad), _p(gabs), _p(draw), _p(dG))
-    out = dict(grad=grad, gabs=gabs, loss=loss)
+    b = _bsdf(bsdf, n)
+    lsel = C.c_double(0.0)
+    loss = lib().npmo_backward(net.ref, n, n if n_total is None else n_total, _p(pos), _p(ax),
+                               _p(dirs), _p(rad), _p(spdf), _p(b), _p(params), _p(grad), _p(gabs),
+                               _p(draw), _p(dG), C.byref(lsel))
+    out = dict(grad=grad, gabs=gabs, loss=loss, loss_sel=lsel.value)
     if with_vertex:
         out.update(draw=draw, dG=dG)
     return out
 
 
-def backward_cond(net, pos, dirs, rad, spdf, params, n_total=None, aux=None):
+def backward_cond(net, pos, dirs, rad, spdf, params, n_total=None, aux=None, bsdf=None):
     """Condition scale of every gradient entry (float64): the sum of the
     absolute sizes of the terms an FP32 evaluation of the backward rounds,
     propagated from the KL-gradient head through the MLP and the scatter.
@@ -295,9 +328,10 @@ def backward_cond(net, pos, dirs, rad, spdf, params, n_total=None, aux=None):
     rad = np.ascontiguousarray(rad, dtype=np.float32)
     spdf = np.ascontiguousarray(spdf, dtype=np.float32)
     params = np.ascontiguousarray(params, dtype=np.float64)
+    b = _bsdf(bsdf, n)
     out = np.zeros(net.n_params)
-    lib().npmo_backward_cond(net.ref, n, n if n_total is None else n_total, _p(pos), _p(ax), _p(dirs),
-                             _p(rad), _p(spdf), _p(params), _p(out))
+    lib().npmo_backward_cond(net.ref, n, n if n_total is None else n_total, _p(pos), _p(ax),
+                             _p(dirs), _p(rad), _p(spdf), _p(b), _p(params), _p(out))
     return out
 
 

@@ -274,6 +274,27 @@ def make_aux(batch, seed):
     return np.ascontiguousarray(out.astype(np.float32))
 
 
+def make_bsdf(batch, seed):
+    """BSDF sampling density [n] float32 at each sample's direction, for the
+    learned selection probability: half the vertices diffuse (cos / pi about
+    the normal, 0 below it), half glossy (the normalised Phong lobe
+    (m + 1) / (2 pi) max(0, r . w)^m about a random unit r, with m
+    log-uniform in [1, 1000], so near-specular densities reach ~160)."""
+    rng = np.random.default_rng(70000 + seed)
+    n = batch.n
+    nrm = batch.meta.get("normal")
+    if nrm is None:
+        nrm = uniform_sphere(rng, n)
+    w = batch.dir.T.astype(np.float64)
+    diffuse = rng.random(n) < 0.5
+    r = uniform_sphere(rng, n)
+    m = np.exp(rng.uniform(0.0, math.log(1000.0), n))
+    cos_n = np.maximum(0.0, np.sum(nrm * w, axis=1))
+    cos_r = np.maximum(0.0, np.sum(r * w, axis=1))
+    p = np.where(diffuse, cos_n / math.pi, (m + 1) / (2 * math.pi) * cos_r ** m)
+    return np.ascontiguousarray(p.astype(np.float32))
+
+
 def edge_positions(rng, n, res_list):
     """Positions that stress the lattice: exact lattice points of the given
     resolutions, 0, 1, values just inside/outside [0,1], and NaN-free randoms."""

@@ -17,6 +17,10 @@ delta chain, float32 scatter -- and compares it with the FP64 oracle:
   64-wide layers and sums over ~100 vertices per grid entry keep the
   first-order worst case above the errors' random walk.
 
+The same holds with the learned selection output (one more row of the last
+layer, its head derivative in the t = log p_bsdf - log V form an FP32
+implementation takes), for the whole gradient and for that row alone.
+
 Before the head's condition factor was derived as a sum of independent
 first-order sources (it multiplied them), the spread case reached only
 1/2,500 of the bound.
@@ -69,8 +73,9 @@ def corner_entries(on, pos):
     return idx, wts
 
 
-def fp32_backward(on, pos, dirs, rad, spdf, params):
-    """The gradient of the surrogate loss, every step in float32."""
+def fp32_backward(on, pos, dirs, rad, spdf, params, bsdf=None):
+    """The gradient of the surrogate loss, every step in float32 (with the
+    selection output's term when the network has one and bsdf is given)."""
     n = pos.shape[1]
     P = params.astype(f32)
     L, F, K = on.n_levels, on.feat, on.n_lobes
@@ -88,7 +93,7 @@ def fp32_backward(on, pos, dirs, rad, spdf, params):
             z = np.maximum(z, f32(0))
             acts.append(z)
         h = z
-    r4 = h.reshape(n, K, 4)
+    r4 = h[:, :4 * K].reshape(n, K, 4)
     th = f32(1) / (f32(1) + np.exp(-r4[..., 0]))
     ph = f32(1) / (f32(1) + np.exp(-r4[..., 1]))
     kap = np.exp(np.clip(r4[..., 2], f32(-80), f32(80))).astype(f32)
@@ -120,6 +125,21 @@ def fp32_backward(on, pos, dirs, rad, spdf, params):
         dka = f32(1) - f32(2) * kap / np.expm1(f32(2) * kap) + kap * (d - f32(1))
     delta = np.stack([g * r * dth, g * r * dph, g * r * dka, g * (r - lam)],
                      -1).reshape(n, 4 * K).astype(f32)
+    if on.select:
+        dsel = np.zeros((n, 1), f32)
+        if bsdf is not None:
+            with np.errstate(over="ignore", divide="ignore", invalid="ignore"):
+                cp = h[:, 4 * K]
+                c = f32(1) / (f32(1) + np.exp(-cp))
+                c1 = f32(1) / (f32(1) + np.exp(cp))
+                b32 = bsdf.astype(f32)
+                t = (np.log(b32) - lv[:, 0]).astype(f32)
+                x = np.expm1(np.minimum(t, f32(0)))
+                y = -np.expm1(-np.maximum(t, f32(0)))
+                E = np.where(t <= 0, x / (f32(1) + c * x), y / (np.exp(-t) + c * y)).astype(f32)
+                use = ok & np.isfinite(b32) & (b32 >= 0)
+                dsel[:, 0] = np.where(use, (g[:, 0] * c * c1 * E).astype(f32), f32(0))
+        delta = np.concatenate([delta, dsel], 1)
     grad = np.zeros(on.n_params, f32)
     for i in range(nl - 1, -1, -1):
         if i < nl - 1:
@@ -184,3 +204,36 @@ def test_condition_scale_is_sized_to_fp32_error(O, case, kind):
               f"p99.9 {q[2]:.4f}, max {ratio.max():.4f}; max err / (1e-5 cond) "
               f"{(e[nz] / (1e-5 * c[nz])).max():.2e}")
         assert ratio.max() >= FLOOR[kind], (part, ratio.max())
+
+
+SEL_FLOOR = {"init": 1.0 / 25.0, "spread": 1.0 / 250.0}
+
+
+@pytest.mark.parametrize("kind", ["init", "spread"])
+@pytest.mark.parametrize("case", ["tiny", "cfg1"])
+def test_selection_condition_scale(O, case, kind):
+    """The same bound with the learned selection output (Sec. 6.3): the
+    condition of its head derivative and of the extra row, through the
+    network; BSDF densities from the diffuse / glossy mix, zeros included."""
+    net, n = (W.TINY, 4000) if case == "tiny" else (W.CFG1, 16384)
+    on = O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table,
+               net.dense_only, net.n_hidden, net.width, net.n_lobes, select=True)
+    rng = np.random.default_rng(13)
+    p = init_params(on, rng) if kind == "init" else spread_params(on, rng)
+    b = W.make_batch("cube", n, seed=15)
+    bsdf = W.make_bsdf(b, 15)
+    ref = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, p, bsdf=bsdf)
+    cond = O.backward_cond(on, b.pos, b.dir, b.radiance, b.pdf, p, bsdf=bsdf)
+    g32 = fp32_backward(on, b.pos, b.dir, b.radiance, b.pdf, p, bsdf=bsdf).astype(np.float64)
+    err = np.abs(g32 - ref["grad"])
+    last = on.layer_offset[-1]
+    width = on.layer_shape[-1][1]
+    row = slice(last + 4 * on.n_lobes * width, last + (4 * on.n_lobes + 1) * width)
+    for part, sl in (("all", slice(0, on.n_params)), ("selection row", row)):
+        c, e = cond[sl], err[sl]
+        assert np.all(e <= 1e-5 * c + 1e-30), part
+        nz = c > 0
+        ratio = e[nz] / (U * c[nz])
+        print(f"{case} {kind} {part}: err / (2^-24 cond) median {np.median(ratio):.4f}, "
+              f"max {ratio.max():.4f}")
+        assert ratio.max() >= SEL_FLOOR[kind], (part, ratio.max())
