@@ -464,11 +464,19 @@ static void oracle_mlp_one(const npmo_net *net, const double *G, const double *p
  * sum of |terms| that an FP32 evaluation rounds, propagated through the
  * layers (cond(z_o) = sum_k |W_ok| cond(h_k); ReLU passes it where z > 0).
  * The tolerance of a float evaluation of z is proportional to cond(z), not
- * to |z|, which cancellation can make arbitrarily small.                   */
+ * to |z|, which cancellation can make arbitrarily small.
+ * A hidden pre-activation within 2^-20 cond(z) of zero has a sign that an
+ * FP32 evaluation does not determine (its rounding error reaches a fraction
+ * of 2^-24 cond(z)), so either side of the ReLU is a correct FP32 result:
+ * such a unit is flagged in amb (its output's condition stays cond(z), as
+ * FP32 may pass z through), and the backward widens its derivative's
+ * condition to cover the other choice.                                     */
+#define NPMO_KINK (1.0 / 1048576.0)
 static void oracle_mlp_cond_one(const npmo_net *net, const double *G, const double *Gcond,
                                 const double *params,
                                 double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH],
                                 double cacts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH],
+                                unsigned char amb[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH],
                                 double *raw, double *rawcond)
 {
     for (int j = 0; j < net->n_in; ++j) { acts[0][j] = G[j]; cacts[0][j] = Gcond[j]; }
@@ -483,7 +491,12 @@ static void oracle_mlp_cond_one(const npmo_net *net, const double *G, const doub
                 c += fabs(W[(int64_t)o * nin + k]) * cacts[i][k];
             }
             if (last) { raw[o] = s; rawcond[o] = c; }
-            else { acts[i + 1][o] = s > 0.0 ? s : 0.0; cacts[i + 1][o] = s > 0.0 ? c : 0.0; }
+            else {
+                int a = fabs(s) <= NPMO_KINK * c;
+                amb[i + 1][o] = (unsigned char)a;
+                acts[i + 1][o] = s > 0.0 ? s : 0.0;
+                cacts[i + 1][o] = (s > 0.0 || a) ? c : 0.0;
+            }
         }
     }
 }
@@ -897,13 +910,14 @@ static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, con
     double G[NPMO_MAX_WIDTH], Gc[NPMO_MAX_WIDTH], raw[NPMO_MAX_OUT], rawc[NPMO_MAX_OUT];
     double draw[NPMO_MAX_OUT], cdraw[NPMO_MAX_OUT];
     double acts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH], cacts[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
+    unsigned char amb[NPMO_MAX_LAYERS][NPMO_MAX_WIDTH];
     double delta[NPMO_MAX_WIDTH], cdelta[NPMO_MAX_WIDTH], prev[NPMO_MAX_WIDTH], cprev[NPMO_MAX_WIDTH];
     int64_t idx[NPMO_MAX_LEVELS * 8];
     double cw[NPMO_MAX_LEVELS * 8];
     if (wgt == 0.0) return;
     oracle_encode_one(net, pos3[0], pos3[1], pos3[2], params, G, Gc);
     oracle_aux_one(net, aux7, G, Gc);
-    oracle_mlp_cond_one(net, G, Gc, params, acts, cacts, raw, rawc);
+    oracle_mlp_cond_one(net, G, Gc, params, acts, cacts, amb, raw, rawc);
     oracle_draw_all(net, raw, w3, wgt, bsdf, invN, draw, NULL);
     oracle_head_cond(net, raw, rawc, w3, wgt, bsdf, invN, cdraw);
     for (int j = 0; j < net->n_out; ++j) { delta[j] = draw[j]; cdelta[j] = cdraw[j]; }
@@ -912,8 +926,14 @@ static void oracle_backward_cond_one(const npmo_net *net, const float *pos3, con
         double *cW = gcond + net->layer_offset[li];
         int nin = net->layer_in[li], nout = net->layer_out[li];
         if (li < net->n_layers - 1)
-            for (int o = 0; o < nout; ++o)
-                if (!(acts[li + 1][o] > 0.0)) { delta[o] = 0.0; cdelta[o] = 0.0; }
+            for (int o = 0; o < nout; ++o) {
+                /* a unit at an undetermined kink: the other choice of the
+                 * ReLU derivative moves dz by |dh| (2^24 |dh| in units of
+                 * the roundoff)                                          */
+                if (amb[li + 1][o]) cdelta[o] += 16777216.0 * fabs(delta[o]);
+                else if (!(acts[li + 1][o] > 0.0)) cdelta[o] = 0.0;
+                if (!(acts[li + 1][o] > 0.0)) delta[o] = 0.0;
+            }
         for (int o = 0; o < nout; ++o)
             for (int k = 0; k < nin; ++k)
                 cW[(int64_t)o * nin + k] += cdelta[o] * fabs(acts[li][k]) + fabs(delta[o]) * cacts[li][k];

@@ -237,3 +237,43 @@ def test_selection_condition_scale(O, case, kind):
         print(f"{case} {kind} {part}: err / (2^-24 cond) median {np.median(ratio):.4f}, "
               f"max {ratio.max():.4f}")
         assert ratio.max() >= SEL_FLOOR[kind], (part, ratio.max())
+
+
+def test_condition_scale_covers_relu_kinks(O):
+    """A hidden pre-activation within 2^-20 of its condition scale has a sign
+    FP32 does not determine, and an FP32 evaluation may take either side of
+    the ReLU: the backward's condition scale covers both (the unit's
+    derivative may move by its whole size).  The case: the paper's network
+    with the selection output, 2^18 surface samples, widely spread
+    parameters, where vertex 82,506 has a second-layer pre-activation at
+    2e-8 of its scale and the FP32 transcription takes the other side; every
+    entry of its gradient stays within 1e-5 of the condition scale."""
+    net = W.PAPERS
+    on = O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table,
+               net.dense_only, net.n_hidden, net.width, net.n_lobes, select=True)
+    rng = np.random.default_rng(25)
+    p = np.zeros(on.n_params, dtype=np.float32)
+    p[:on.grid_params] = rng.normal(0, 0.5, on.grid_params)
+    for i, (o, k) in enumerate(on.layer_shape):
+        a = 2.0 * math.sqrt(6.0 / (o + k)) / math.sqrt(k / 8.0)
+        off = on.layer_offset[i]
+        p[off:off + o * k] = rng.uniform(-a, a, o * k)
+    p = p.astype(np.float64)
+    b = W.make_batch("surface", W.N_PAPER_TRAIN, seed=26)
+    bsdf = W.make_bsdf(b, 26)
+    # the kink: FP64 and FP32 disagree on the sign of one pre-activation
+    v = 82506
+    h64 = O.encode(on, b.pos[:, v:v + 1], p)[0]
+    h32 = h64.astype(f32)
+    for i in range(2):
+        Wm = on.weights(p, i)
+        z64, z32 = Wm @ h64, (Wm.astype(f32) @ h32).astype(f32)
+        scale = np.abs(Wm) @ np.abs(h64)
+        h64, h32 = np.maximum(z64, 0), np.maximum(z32, f32(0))
+    j = int(np.argmin(np.abs(z64) / scale))
+    assert abs(z64[j]) <= 2.0 ** -20 * scale[j]
+    ref = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, p, bsdf=bsdf, with_abs=False)
+    cond = O.backward_cond(on, b.pos, b.dir, b.radiance, b.pdf, p, bsdf=bsdf)
+    g32 = fp32_backward(on, b.pos, b.dir, b.radiance, b.pdf, p, bsdf=bsdf).astype(np.float64)
+    err = np.abs(g32 - ref["grad"])
+    assert np.all(err <= 1e-5 * cond + 1e-30)
