@@ -9,7 +9,8 @@ the batch: npm_query (encode + MLP + mappings + pdf at dir + one sample and
 its pdf per vertex) followed by npm_train_step (forward, KL gradient,
 backward, grid scatter, weight gradients, Adam over all parameters).  The
 default run also reports the serving form, the paper's own network on its
-batch sizes, NPM-product, and the FP64 oracle on the host cores.
+batch sizes, NPM-product, the learned BSDF-selection probability (on the
+paper's network, staged), and the FP64 oracle on the host cores.
 
 Prints one JSON line.  `value` is vertices per second through a full step
 (query + train on the same batch), inputs resident in HBM.  The roofline
@@ -253,6 +254,23 @@ def serving_bench(n_sessions=32, per_session=6, load=0.7, sweep=(0.3, 0.9)):
     return out
 
 
+def _median_ms(fn, reps, warm):
+    """Median HIP-event time of fn(i) on the current stream over reps calls,
+    after warm untimed ones."""
+    import torch
+    for i in range(warm):
+        fn(i)
+    ms = []
+    for i in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn(100 + i)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return float(np.median(ms))
+
+
 def _time_forms(net, nq, nt, seeds, reps, warm, product=False):
     """Median HIP-event times of fused queries of nq vertices (dir given;
     lobes, pdf, sample, sample pdf) and training steps of nt vertices, FP32
@@ -274,18 +292,7 @@ def _time_forms(net, nq, nt, seeds, reps, warm, product=False):
                  sample_dir=torch.empty((3, nq), device="cuda"),
                  sample_pdf=torch.empty(nq, device="cuda"))
 
-        def timed(fn):
-            for i in range(warm):
-                fn(i)
-            ms = []
-            for i in range(reps):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record()
-                fn(100 + i)
-                b.record()
-                b.synchronize()
-                ms.append(a.elapsed_time(b))
-            return float(np.median(ms))
+        timed = lambda fn: _median_ms(fn, reps, warm)
         lib = B.lib()
         q_ms = timed(lambda i: B.check(lib.npm_query_aux(
             m.handle, nq, B._ptr(qa[0]), B._ptr(qx), B._ptr(qa[1]), i, 0, B._ptr(o["lobes"]),
@@ -319,6 +326,62 @@ def product_bench(reps=20, warm=5):
     out = {"network": "16-level hash grid T=2^19 F=2 + SH4(omega_o) + SH4(normal) + roughness, "
                       "MLP 65-64-64-64-32, K=8", "query_batch": 1 << 20, "train_batch": 1 << 20}
     out.update(_time_forms(W.CFG2P, 1 << 20, 1 << 20, (81, 82), reps, warm, product=True))
+    return out
+
+
+def selection_bench(reps=20, warm=5):
+    """The learned BSDF-selection probability (the Sec. 6.3 extension) on the
+    paper's network with its extra output, on the staged FP32 path that
+    carries it: queries of one 1280x720 wavefront returning the selection
+    probability, and training steps of 2^18 vertices with the selection
+    term; the same network without the output on the same path gives the
+    extension's cost; per-kernel times of the selection training step."""
+    import torch
+    from paper_2504_04315_amd import npm as B
+    from paper_2504_04315_amd import workload as W
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nq, nt = W.N_PAPER_QUERY, W.N_PAPER_TRAIN
+    qb = W.make_batch("surface", nq, seed=73)
+    tb = W.make_batch("surface", nt, seed=74)
+    qa = [t(qb.pos), t(qb.dir)]
+    ta = [t(tb.pos), t(tb.dir), t(tb.radiance), t(tb.pdf)]
+    bsdf = t(W.make_bsdf(tb, 74))
+    lib = B.lib()
+    out = {"network": "8 dense levels 8..86 x F=4, MLP 32-64-64-33 (32 lobe outputs + the "
+                      "selection logit), K=8, staged FP32",
+           "query_batch": nq, "train_batch": nt}
+    for label, net in (("selection", W.PAPERS), ("without_output", W.PAPER)):
+        m = B.NPM(B.make_config(net, exec_mode=B.EXEC_STAGED))
+        o = [torch.empty((4, 8, nq), device="cuda"), torch.empty(nq, device="cuda"),
+             torch.empty((3, nq), device="cuda"), torch.empty(nq, device="cuda")]
+        sel = torch.empty(nq, device="cuda")
+        if label == "selection":
+            q = lambda i: B.check(lib.npm_query_select(
+                m.handle, nq, B._ptr(qa[0]), None, B._ptr(qa[1]), i, 0, *map(B._ptr, o),
+                B._ptr(sel), B._stream()))
+            tr = lambda i: m.train_step_select(*ta, bsdf)
+        else:
+            q = lambda i: B.check(lib.npm_query_aux(
+                m.handle, nq, B._ptr(qa[0]), None, B._ptr(qa[1]), i, 0, *map(B._ptr, o),
+                B._stream()))
+            tr = lambda i: m.train_step(*ta)
+        q_ms, t_ms = _median_ms(q, reps, warm), _median_ms(tr, reps, warm)
+        out[label] = {"query_ms": q_ms, "train_ms": t_ms,
+                      "query_vertices_per_s": nq / (q_ms / 1e3),
+                      "train_vertices_per_s": nt / (t_ms / 1e3)}
+        if label == "selection":
+            m.set_timing(True)
+            m.reset_timing()
+            for i in range(reps):
+                tr(i)
+            torch.cuda.synchronize()
+            out[label]["train_kernels_ms"] = {k: round(v[1] / v[0], 4)
+                                              for k, v in m.kernel_times().items() if v[0]}
+            m.set_timing(False)
+        m.close()
+    w, s0 = out["selection"], out["without_output"]
+    out["cost"] = {"query": round(w["query_ms"] / s0["query_ms"] - 1.0, 4),
+                   "train": round(w["train_ms"] / s0["train_ms"] - 1.0, 4)}
     return out
 
 
@@ -490,6 +553,8 @@ def main():
         line["paper_config"] = paper_config_bench()
         print("NPM-product ...", file=sys.stderr, flush=True)
         line["product"] = product_bench()
+        print("learned selection probability ...", file=sys.stderr, flush=True)
+        line["selection"] = selection_bench()
     if not (args.no_cpu_baseline or args.profile):
         print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(netcfg, batch, params0, args.cpu_seconds)

@@ -33,7 +33,8 @@
  * tables first, level after level, entry-major with F features per entry
  * (feature f of entry e of level l at (offset_l + e) * F + f); then the MLP
  * weight matrices W_0 .. W_{hidden}, each row-major [out][in].  The MLP has
- * no biases.
+ * no biases.  With learn_selection the last matrix has 4K + 1 rows, the
+ * selection logit's last.
  */
 #ifndef NPM_H
 #define NPM_H
@@ -133,7 +134,16 @@ enum { NPM_SCATTER_AUTO = 0, NPM_SCATTER_ATOMIC = 1, NPM_SCATTER_BINNED = 2 };
  *   ema <- d * ema + (1 - d) * p (after the step, initialised to the
  *   initial parameters), and npm_query, npm_encode and npm_forward_raw
  *   evaluate the network with the averaged weights, as the paper does for
- *   inference (Sec. 5.3); training always uses the current weights.       */
+ *   inference (Sec. 5.3); training always uses the current weights.
+ * learn_selection: 0, or 1 for the learned BSDF-selection probability
+ *   (Sec. 6.3, Discussion: an extension the paper proposes without a
+ *   formula).  The last layer gets one more output c' (n_out = 4K + 1), and
+ *   c = 1 / (1 + e^{-c'}) is the probability with which the renderer
+ *   samples the BSDF rather than the mixture; it is returned by
+ *   npm_query_select and trained by npm_backward_select /
+ *   npm_train_step_select.  Runs on the staged path (NPM_EXEC_STAGED, FP32);
+ *   the plain calls work on such a network and leave the selection row's
+ *   gradient 0.                                                            */
 typedef struct {
     int32_t grid_kind;
     int32_t n_levels;
@@ -157,6 +167,7 @@ typedef struct {
     int32_t sh_degree;
     int32_t scatter_mode;
     int32_t resolution[32];       /* explicit D_l table, or all 0: derive    */
+    int32_t learn_selection;      /* 0 or 1                                  */
     uint64_t seed;
 } npm_config;
 
@@ -306,12 +317,47 @@ npm_status npm_backward_static(npm_ctx *ctx, int64_t n, const float *pos, const 
                                const float *dir, const float *radiance, const float *sampling_pdf,
                                float *grad_out, double *loss_out, void *stream);
 
+/* Learned BSDF-selection probability (learn_selection = 1; Sec. 6.3
+ * extension).  The renderer samples the BSDF with probability c and the
+ * mixture V otherwise, so its one-sample MIS density is
+ *   p_c(w) = c p_bsdf(w) + (1 - c) V(w).
+ * npm_query_select: npm_query_aux plus
+ *   select_prob [n] out: c at each vertex, or NULL.
+ * npm_backward_select: the gradient of the mixture's loss (npm_backward)
+ *   plus that of the selection term, the Sec. 4.2 KL estimator applied to
+ *   p_c with V held fixed (it moves c only):
+ *     loss_sel = -(1/n) sum_i w_i log p_c(dir_i),
+ *     d loss_sel / d c'_i = -(w_i/n) c (1 - c) (p_bsdf - V) / p_c,
+ *   with the same weights w_i = radiance_i / sampling_pdf_i.
+ *   bsdf_pdf [n] (required): the BSDF's sampling density of dir_i; a sample
+ *   whose density is not finite and >= 0 (a delta lobe) has no selection
+ *   term.  loss_out: device pointer to two doubles (the mixture's loss,
+ *   loss_sel), or NULL.
+ * npm_train_step_select: npm_backward_select into the context's buffer,
+ *   then npm_optimizer_step; stats_out: three doubles (loss, loss_sel,
+ *   squared gradient norm), or NULL.
+ * All three fail with NPM_ERR_STATE on a network without the selection
+ * output; aux as in the *_aux calls.                                        */
+npm_status npm_query_select(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                            const float *dir, uint64_t rng_seed, uint32_t rng_stream,
+                            float *lobes, float *pdf, float *sample_dir, float *sample_pdf,
+                            float *select_prob, void *stream);
+npm_status npm_backward_select(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                               const float *dir, const float *radiance,
+                               const float *sampling_pdf, const float *bsdf_pdf,
+                               float *grad_out, double *loss_out, void *stream);
+npm_status npm_train_step_select(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                                 const float *dir, const float *radiance,
+                                 const float *sampling_pdf, const float *bsdf_pdf,
+                                 double *stats_out, void *stream);
+
 /* Stage outputs, for checking each step of the path on its own.
  *   npm_corner_index: idx [L][8][n] global table entry of corner b of level
  *     l (corner b has offsets (b&1, b>>1&1, b>>2&1) in x, y, z).
  *   npm_encode: G [n_in][n], the MLP input: the concatenated embedding
  *     (Sec. 5.1), then the NPM-product inputs when sh_degree > 0.
- *   npm_forward_raw: raw [4K][n], the MLP output before the mappings.      */
+ *   npm_forward_raw: raw [n_out][n], the MLP output before the mappings
+ *     (4K lobe outputs, then the selection logit on a selection network).  */
 npm_status npm_corner_index(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *idx,
                             void *stream);
 npm_status npm_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, void *stream);

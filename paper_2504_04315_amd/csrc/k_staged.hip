@@ -10,6 +10,12 @@
 //   mlp_bwd     backprop of the MLP (delta chain and dG)
 //   mlp_dw      weight gradients, batch as the MFMA reduction dimension
 //   scatter     dG into the eight corners of every level (FP32 atomics)
+//
+// With the learned BSDF-selection probability (Sec. 6.3, Discussion) the last
+// layer has one more row: its output c' is a dot product of the last hidden
+// layer with that row, folded into mlp_fwd; its derivative is written by
+// loss_grad and added back by mlp_bwd, and mlp_dw treats the 33 rows as one
+// matrix.
 #include "device_math.h"
 
 namespace npm {
@@ -149,11 +155,14 @@ __device__ __forceinline__ void store_tile(float *__restrict__ dst, int rows, in
 // ============================================================= MLP forward
 // Wave tiles of 32 vertices in a grid-stride loop; all layer images in LDS.
 // acts (optional) receives every hidden layer's output [n_hidden][width][n].
+// wsel (or null): the selection row of the last layer, width weights; its
+// output goes to raw row kOut.
 template <int IN_P, int HID_P, int NH>
 __global__ __launch_bounds__(256) void k_mlp_fwd(int64_t n, int n_in, int width,
                                                  const float *__restrict__ img, int img_elems,
                                                  const float *__restrict__ G,
-                                                 float *__restrict__ acts, float *__restrict__ raw)
+                                                 float *__restrict__ acts, float *__restrict__ raw,
+                                                 const float *__restrict__ wsel)
 {
     extern __shared__ float lds[];
     stage_image(lds, img, img_elems);
@@ -181,6 +190,17 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(int64_t n, int n_in, int width,
         float o[16];
         mfma_layer_f32<HID_P, 32>(lds + L1 + (NH - 1) * HID_P * HID_P, a, o, lane);
         store_tile<16>(raw, 32, n, v, h, o);
+        if (wsel) {
+            // the two half-waves hold the two halves of a vertex's features
+            float part = 0.0f;
+#pragma unroll
+            for (int i = 0; i < HID_P / 2; ++i) {
+                const int f = nf(h, i);
+                if (f < width) part = fmaf(wsel[f], a[i], part);
+            }
+            part += __shfl_xor(part, 32);
+            if (h == 0 && v < n) raw[(int64_t)kOut * n + v] = part;
+        }
     }
 }
 
@@ -188,12 +208,15 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(int64_t n, int n_in, int width,
 // delta chain: d = draw; for the output layer dh = W^T d, then for each hidden
 // layer (from the last) dz = dh * [h > 0] (stored for the weight gradient) and
 // dh = W^T dz; finally dG = W_0^T dz_0.  Transposed images come packed.
+// wsel (or null): the selection row; its derivative (draw row kOut) adds
+// d c' / d h = wsel to the last hidden layer's delta.
 template <int IN_P, int HID_P, int NH>
 __global__ __launch_bounds__(256) void k_mlp_bwd(int64_t n, int n_in, int width,
                                                  const float *__restrict__ img, int img_elems,
                                                  const float *__restrict__ draw,
                                                  const float *__restrict__ acts,
-                                                 float *__restrict__ delta, float *__restrict__ dG)
+                                                 float *__restrict__ delta, float *__restrict__ dG,
+                                                 const float *__restrict__ wsel)
 {
     extern __shared__ float lds[];
     stage_image(lds, img, img_elems);
@@ -211,6 +234,14 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int64_t n, int n_in, int width,
         const float *im = lds;
         mfma_layer_f32<32, HID_P>(im, d, dh, lane);
         im += HID_P * 32;
+        if (wsel) {
+            const float ds = v < n ? draw[(int64_t)kOut * n + v] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < HID_P / 2; ++i) {
+                const int f = nf(h, i);
+                if (f < width) dh[i] = fmaf(ds, wsel[f], dh[i]);
+            }
+        }
 #pragma unroll
         for (int layer = NH - 1; layer >= 0; --layer) {
             load_tile<HID_P / 2>(acts + (int64_t)layer * width * n, width, n, v, h, hv);
@@ -311,15 +342,18 @@ __global__ void k_dw_reduce(const float *__restrict__ part, int nblocks, int cou
 }
 
 // ============================================================= head (query)
-// One thread per vertex over the 32 raw outputs in [32][n].
+// One thread per vertex over the 32 raw outputs in [32][n]; sel (or null)
+// receives the selection probability sigmoid(raw row kOut).
 __global__ __launch_bounds__(256) void k_head(int64_t n, const float *__restrict__ raw,
                                               const float *__restrict__ dir, uint64_t seed,
                                               uint32_t sid, float *__restrict__ lobes,
                                               float *__restrict__ pdf, float *__restrict__ sdir,
-                                              float *__restrict__ spdf)
+                                              float *__restrict__ spdf, float *__restrict__ sel)
 {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= n) return;
+    if (sel) sel[v] = 1.0f / (1.0f + expf(-raw[(int64_t)kOut * n + v]));
+    if (!lobes && !pdf && !sdir && !spdf) return;
     float r[32];
 #pragma unroll
     for (int j = 0; j < 32; ++j) r[j] = raw[(int64_t)j * n + v];
@@ -381,19 +415,53 @@ __global__ __launch_bounds__(256) void k_head(int64_t n, const float *__restrict
 }
 
 // ============================================================= loss gradient
-// draw[32][n] = d loss / d raw, loss partial sums of -w log V in FP64.
+// Selection term of one sample (the learned selection probability): the
+// renderer's one-sample density is p_c = c p_bsdf + (1 - c) V, c = sigmoid(c');
+// with V held fixed, d(-(w/N) log p_c)/dc' = g c (1 - c) (p_bsdf - V) / p_c,
+// g = -w/N.  With t = log p_bsdf - log V and c / (1 - c) = e^c' this is
+//   t <= 0:  g c expm1(t) sigmoid(-(c' + t)),
+//   t > 0:   g (1 - c) (-expm1(-t)) sigmoid(c' + t),
+// and log p_c = log V - softplus(c') + softplus(c' + t) (t <= 0), or
+// log p_bsdf - softplus(-c') + softplus(-c' - t) (t > 0): no cancellation,
+// no division, and p_bsdf = 0 (t = -inf) gives -g c and log V + log(1 - c).
+// Writes the derivative and returns log p_c.
+__device__ __forceinline__ float softplusf(float x)
+{
+    return x > 0.0f ? x + log1pf(expf(-x)) : log1pf(expf(x));
+}
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+__device__ __forceinline__ float select_term(float cp, float pb, float lv, float g, float &ds)
+{
+    const float lp = logf(pb);
+    const float t = lp - lv;
+    if (t <= 0.0f) {
+        ds = g * sigmoidf(cp) * expm1f(t) * sigmoidf(-(cp + t));
+        return lv - softplusf(cp) + softplusf(cp + t);
+    }
+    ds = g * sigmoidf(-cp) * -expm1f(-t) * sigmoidf(cp + t);
+    return lp - softplusf(-cp) + softplusf(-cp - t);
+}
+
+// draw[kOut (+1)][n] = d loss / d raw, loss partial sums of -w log V in FP64.
+// sel: the network has the selection output (draw row kOut is written: the
+// selection term's derivative where bsdf is given and the sample's density
+// is finite and >= 0, else 0); its loss partial sums go to partials_sel.
 __global__ __launch_bounds__(256) void k_loss_grad(int64_t n, const float *__restrict__ raw,
                                                    const float *__restrict__ dir,
                                                    const float *__restrict__ rad,
                                                    const float *__restrict__ spdf, float invN,
                                                    float *__restrict__ draw,
-                                                   double *__restrict__ partials)
+                                                   double *__restrict__ partials, int sel,
+                                                   const float *__restrict__ bsdf,
+                                                   double *__restrict__ partials_sel)
 {
-    double lacc = 0.0;
+    double lacc = 0.0, sacc = 0.0;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const float wgt = sample_weight(rad[v], spdf[v]);
-        float out[32];
+        float out[32], ds = 0.0f;
 #pragma unroll
         for (int j = 0; j < 32; ++j) out[j] = 0.0f;
         if (wgt != 0.0f) {
@@ -426,18 +494,33 @@ __global__ __launch_bounds__(256) void k_loss_grad(int64_t n, const float *__res
                 lobe_grad(L[k], r[4 * k], r[4 * k + 1], r[4 * k + 2], expf(lt[k] - lv),
                           expf(L[k].loglam), g, wx, wy, wz, out + 4 * k);
             lacc -= (double)wgt * (double)lv;
+            if (sel && bsdf) {
+                const float pb = bsdf[v];
+                if (isfinite(pb) && pb >= 0.0f) {
+                    const float lpc = select_term(raw[(int64_t)kOut * n + v], pb, lv, g, ds);
+                    sacc -= (double)wgt * (double)lpc;
+                }
+            }
         }
 #pragma unroll
         for (int j = 0; j < 32; ++j) draw[(int64_t)j * n + v] = out[j];
+        if (sel) draw[(int64_t)kOut * n + v] = ds;
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = lacc;
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = lacc;
+    red[1][threadIdx.x] = sacc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = red[0][0];
+        if (partials_sel) partials_sel[blockIdx.x] = red[1][0];
+    }
 }
 
 // ============================================================= scatter
@@ -516,7 +599,7 @@ __global__ __launch_bounds__(256) void k_scatter(GridDesc g, int64_t n, const fl
 template <int IN_P, int HID_P, int NH>
 struct MlpFwd {
     static void run(npm_ctx *ctx, int blocks, int64_t n, const float *G, float *acts, float *raw,
-                    hipStream_t s, const float *img)
+                    hipStream_t s, const float *img, const float *wsel)
     {
         const MlpDesc &m = ctx->net.mlp;
         const int elems = (int)m.fwd_elems;
@@ -524,14 +607,14 @@ struct MlpFwd {
                             hipFuncAttributeMaxDynamicSharedMemorySize, elems * sizeof(float));
         hipLaunchKernelGGL((k_mlp_fwd<IN_P, HID_P, NH>), dim3(blocks), dim3(256),
                            elems * sizeof(float), s, n, m.n_in, m.width, img, elems, G,
-                           acts, raw);
+                           acts, raw, wsel);
     }
 };
 
 template <int IN_P, int HID_P, int NH>
 struct MlpBwd {
     static void run(npm_ctx *ctx, int blocks, int64_t n, const float *draw, const float *acts,
-                    float *delta, float *dG, hipStream_t s)
+                    float *delta, float *dG, hipStream_t s, const float *wsel)
     {
         const MlpDesc &m = ctx->net.mlp;
         const int elems = (int)m.bwd_elems;
@@ -539,9 +622,18 @@ struct MlpBwd {
                             hipFuncAttributeMaxDynamicSharedMemorySize, elems * sizeof(float));
         hipLaunchKernelGGL((k_mlp_bwd<IN_P, HID_P, NH>), dim3(blocks), dim3(256),
                            elems * sizeof(float), s, n, m.n_in, m.width,
-                           ctx->mlp_img + m.fwd_elems, elems, draw, acts, delta, dG);
+                           ctx->mlp_img + m.fwd_elems, elems, draw, acts, delta, dG, wsel);
     }
 };
+
+// The selection row of the last layer within the flat parameters `flat`, or
+// null when the network has no selection output.
+static const float *selection_row(const npm_ctx *ctx, const float *flat)
+{
+    const npm_layout &L = ctx->net.lay;
+    if (!ctx->net.cfg.learn_selection) return nullptr;
+    return flat + L.layer_offset[L.n_layers - 1] + (int64_t)kOut * ctx->net.mlp.width;
+}
 
 static int tile_blocks(int64_t n)
 {
@@ -555,9 +647,10 @@ hipError_t staged_mlp_fwd(npm_ctx *ctx, int64_t n, const float *G, float *acts, 
 {
     const int blocks = tile_blocks(n);
     const float *img = w ? w->img : ctx->mlp_img;
+    const float *wsel = selection_row(ctx, w ? w->grid32 : ctx->params);
     int tok;
     timed_begin(ctx, acts ? "staged_mlp_fwd_train" : "staged_mlp_fwd", s, &tok);
-    NPM_MLP_DISPATCH(MlpFwd, ::run(ctx, blocks, n, G, acts, raw, s, img));
+    NPM_MLP_DISPATCH(MlpFwd, ::run(ctx, blocks, n, G, acts, raw, s, img, wsel));
     timed_end(ctx, tok, s);
     return hipGetLastError();
 }
@@ -568,7 +661,8 @@ hipError_t staged_mlp_bwd(npm_ctx *ctx, int64_t n, const float *draw, const floa
     const int blocks = tile_blocks(n);
     int tok;
     timed_begin(ctx, "staged_mlp_bwd", s, &tok);
-    NPM_MLP_DISPATCH(MlpBwd, ::run(ctx, blocks, n, draw, acts, delta, dG, s));
+    const float *wsel = selection_row(ctx, ctx->params);
+    NPM_MLP_DISPATCH(MlpBwd, ::run(ctx, blocks, n, draw, acts, delta, dG, s, wsel));
     timed_end(ctx, tok, s);
     return hipGetLastError();
 }
@@ -587,7 +681,7 @@ hipError_t staged_mlp_dw(npm_ctx *ctx, int64_t n, const float *G, const float *a
         const int out_r = L.layer_out[i], in_r = L.layer_in[i];
         const float *dz = (i == L.n_layers - 1) ? draw : delta + (int64_t)i * m.width * n;
         const float *x = (i == 0) ? G : acts + (int64_t)(i - 1) * m.width * n;
-        const int out_p = (i == L.n_layers - 1) ? 32 : m.hid_p;
+        const int out_p = (i == L.n_layers - 1) ? (out_r > 32 ? 64 : 32) : m.hid_p;
         const int in_p = (i == 0) ? std::max(m.in_p, 32) : m.hid_p;   // at least one 32 block
         float *part = ctx->s_dw_part;
 #define NPM_DW(OP, IP) hipLaunchKernelGGL((k_dw<OP, IP>), dim3(blocks), dim3(256), 0, s, n, out_r, in_r, dz, x, part)
@@ -608,29 +702,34 @@ hipError_t staged_mlp_dw(npm_ctx *ctx, int64_t n, const float *G, const float *a
 
 hipError_t staged_head(npm_ctx *ctx, int64_t n, const float *raw, const float *dir,
                        uint64_t seed, uint32_t stream_id, float *lobes, float *pdf, float *sdir,
-                       float *spdf, hipStream_t s)
+                       float *spdf, hipStream_t s, float *sel)
 {
     int tok;
     timed_begin(ctx, "staged_head", s, &tok);
     hipLaunchKernelGGL(k_head, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, raw, dir,
-                       seed, stream_id, lobes, pdf, sdir, spdf);
+                       seed, stream_id, lobes, pdf, sdir, spdf, sel);
     timed_end(ctx, tok, s);
     return hipGetLastError();
 }
 
 hipError_t staged_loss_grad(npm_ctx *ctx, int64_t n, const float *raw, const float *dir,
                             const float *rad, const float *spdf, float *draw, double *loss_out,
-                            hipStream_t s)
+                            hipStream_t s, const float *bsdf)
 {
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
+    constexpr int kMaxBlocks = kPartials / 2;   // the second half holds the selection sums
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kMaxBlocks));
+    const int sel = ctx->net.cfg.learn_selection;
+    double *psel = (sel && bsdf) ? ctx->partials + kMaxBlocks : nullptr;
     int tok;
     timed_begin(ctx, "staged_loss_grad", s, &tok);
     hipLaunchKernelGGL(k_loss_grad, dim3(blocks), dim3(256), 0, s, n, raw, dir, rad, spdf,
-                       1.0f / (float)n, draw, ctx->partials);
+                       1.0f / (float)n, draw, ctx->partials, sel, sel ? bsdf : nullptr, psel);
     timed_end(ctx, tok, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !loss_out) return e;
-    return launch_reduce_scaled(ctx->partials, blocks, 1.0 / (double)n, loss_out, s);
+    e = launch_reduce_scaled(ctx->partials, blocks, 1.0 / (double)n, loss_out, s);
+    if (e != hipSuccess || !psel) return e;
+    return launch_reduce_scaled(psel, blocks, 1.0 / (double)n, loss_out + 1, s);
 }
 
 hipError_t staged_scatter(npm_ctx *ctx, int64_t n, const float *pos, const float *dG,

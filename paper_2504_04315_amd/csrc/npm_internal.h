@@ -13,7 +13,8 @@
 namespace npm {
 
 constexpr int kLobes = 8;             // K (Sec. 5.3)
-constexpr int kOut = 4 * kLobes;      // raw outputs per vertex
+constexpr int kOut = 4 * kLobes;      // lobe raw outputs per vertex (a selection
+                                      // network has one more, the logit, at kOut)
 constexpr int kWave = 64;             // CDNA wavefront
 constexpr int kTile = 32;             // vertices per wave tile (32x32 MFMA)
 
@@ -164,12 +165,15 @@ hipError_t staged_encode(npm_ctx *ctx, int64_t n, const float *pos, float *G, hi
                          const Weights *w = nullptr, const float *aux = nullptr);
 hipError_t staged_mlp_fwd(npm_ctx *ctx, int64_t n, const float *G, float *acts, float *raw,
                           hipStream_t s, const Weights *w = nullptr);
+// sel (or null): the selection probability of each vertex (selection networks)
 hipError_t staged_head(npm_ctx *ctx, int64_t n, const float *raw, const float *dir,
                        uint64_t seed, uint32_t stream_id, float *lobes, float *pdf,
-                       float *sdir, float *spdf, hipStream_t s);
+                       float *sdir, float *spdf, hipStream_t s, float *sel = nullptr);
+// bsdf (or null): the BSDF density of each sample, for the selection term of a
+// network with the selection output; its loss then goes to loss_out[1]
 hipError_t staged_loss_grad(npm_ctx *ctx, int64_t n, const float *raw, const float *dir,
                             const float *rad, const float *spdf, float *draw, double *loss_out,
-                            hipStream_t s);
+                            hipStream_t s, const float *bsdf = nullptr);
 hipError_t staged_mlp_bwd(npm_ctx *ctx, int64_t n, const float *draw, const float *acts,
                           float *delta, float *dG, hipStream_t s);
 hipError_t staged_mlp_dw(npm_ctx *ctx, int64_t n, const float *G, const float *acts,

@@ -97,6 +97,9 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     if (!(std::isfinite(c.eps) && c.eps > 0.0f)) return bad("eps must be > 0");
     if (!(c.ema_decay >= 0.0f && c.ema_decay < 1.0f)) return bad("ema_decay must be in [0, 1)");
     if (c.sh_degree < 0 || c.sh_degree > 4) return bad("sh_degree must be 0..4");
+    if (c.learn_selection != 0 && c.learn_selection != 1) return bad("learn_selection must be 0 or 1");
+    if (c.learn_selection && c.exec_mode != NPM_EXEC_STAGED)
+        return bad("the learned selection probability runs on the staged path (NPM_EXEC_STAGED)");
     if (c.sh_degree > 0 && c.exec_mode == NPM_EXEC_FUSED &&
         !((c.sh_degree == 4 && c.n_levels * c.feat_per_level == 32) ||
           (c.sh_degree == 2 && c.n_levels * c.feat_per_level == 4)))
@@ -131,7 +134,7 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     L.grid_params = entries * c.feat_per_level;
     const int n_aux = c.sh_degree ? 2 * c.sh_degree * c.sh_degree + 1 : 0;
     L.n_in = nl * c.feat_per_level + n_aux;
-    L.n_out = 4 * kLobes;
+    L.n_out = 4 * kLobes + (c.learn_selection ? 1 : 0);
     L.n_layers = c.mlp_hidden_layers + 1;
     int64_t off = L.grid_params;
     for (int i = 0; i < L.n_layers; ++i) {
@@ -409,10 +412,10 @@ static hipError_t ensure_scratch(npm_ctx *ctx, int64_t n)
         if (e == hipSuccess) e = hipMalloc((void **)p, (size_t)elems * f);
     };
     alloc(&ctx->s_G, (int64_t)m.n_in * n);
-    alloc(&ctx->s_raw, (int64_t)kOut * n);
+    alloc(&ctx->s_raw, (int64_t)ctx->net.lay.n_out * n);
     alloc(&ctx->s_acts, (int64_t)m.n_hidden * m.width * n);
     alloc(&ctx->s_delta, (int64_t)m.n_hidden * m.width * n);
-    alloc(&ctx->s_draw, (int64_t)kOut * n);
+    alloc(&ctx->s_draw, (int64_t)ctx->net.lay.n_out * n);
     alloc(&ctx->s_dG, (int64_t)m.n_in * n);
     if (e != hipSuccess) { free_scratch(ctx); return e; }
     ctx->scratch_n = n;
@@ -607,9 +610,10 @@ static hipError_t ensure_dgt(npm_ctx *ctx, int64_t n)
     return hipSuccess;
 }
 
+// bsdf: the selection term's BSDF densities (selection networks), or null
 static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                                 const float *dir, const float *rad, const float *spdf, float *grad,
-                                double *loss_out, hipStream_t s)
+                                double *loss_out, hipStream_t s, const float *bsdf = nullptr)
 {
     if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
         const uint32_t *perm = nullptr;
@@ -632,7 +636,7 @@ static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const
     NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
     NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, nullptr, aux), "encode");
     NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, ctx->s_acts, ctx->s_raw, s), "mlp forward");
-    NPM_HIP(staged_loss_grad(ctx, n, ctx->s_raw, dir, rad, spdf, ctx->s_draw, loss_out, s),
+    NPM_HIP(staged_loss_grad(ctx, n, ctx->s_raw, dir, rad, spdf, ctx->s_draw, loss_out, s, bsdf),
             "loss gradient");
     NPM_HIP(staged_mlp_bwd(ctx, n, ctx->s_draw, ctx->s_acts, ctx->s_delta, ctx->s_dG, s),
             "mlp backward");
@@ -792,6 +796,96 @@ npm_status npm_train_step_aux(npm_ctx *ctx, int64_t n, const float *pos, const f
         if (st != NPM_OK) return st;
     }
     return npm_optimizer_step(ctx, nullptr, stats_out ? stats_out + 1 : nullptr, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Learned BSDF-selection probability (staged path)
+static npm_status check_select(npm_ctx *ctx)
+{
+    if (!ctx) return fail(NPM_ERR_INVALID_ARG, "null context");
+    if (!ctx->net.cfg.learn_selection)
+        return fail(NPM_ERR_STATE, "the network has no selection output (learn_selection = 0)");
+    return NPM_OK;
+}
+
+npm_status npm_query_select(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                            const float *dir, uint64_t rng_seed, uint32_t rng_stream,
+                            float *lobes, float *pdf, float *sample_dir, float *sample_pdf,
+                            float *select_prob, void *stream)
+{
+    npm_status st = check_select(ctx);
+    if (st != NPM_OK) return st;
+    if ((st = check_batch(ctx, n, pos)) != NPM_OK) return st;
+    if ((st = check_aux(ctx, n, aux)) != NPM_OK) return st;
+    if (pdf && !dir) return fail(NPM_ERR_INVALID_ARG, "pdf needs dir");
+    for (const void *p : {(const void *)dir, (const void *)lobes, (const void *)pdf,
+                          (const void *)sample_dir, (const void *)sample_pdf,
+                          (const void *)select_prob})
+        if (p && !aligned4(p)) return fail(NPM_ERR_INVALID_ARG, "misaligned buffer");
+    if (n == 0) return NPM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
+        const Weights w = query_weights(ctx);
+        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w, aux), "encode");
+        NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s, &w), "mlp forward");
+        if (lobes || pdf || sample_dir || sample_pdf || select_prob)
+            NPM_HIP(staged_head(ctx, n, ctx->s_raw, dir, rng_seed, rng_stream, lobes, pdf,
+                                sample_dir, sample_pdf, s, select_prob), "head");
+    } catch (...) {
+        return fail(NPM_ERR_HIP, "unexpected exception");
+    }
+    return NPM_OK;
+}
+
+static npm_status check_train_select(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                                     const float *dir, const float *rad, const float *spdf,
+                                     const float *bsdf)
+{
+    npm_status st = check_select(ctx);
+    if (st != NPM_OK) return st;
+    if ((st = check_train(ctx, n, pos, dir, rad, spdf)) != NPM_OK) return st;
+    if ((st = check_aux(ctx, n, aux)) != NPM_OK) return st;
+    if (n > 0 && (!bsdf || !aligned4(bsdf)))
+        return fail(NPM_ERR_INVALID_ARG, "bsdf_pdf is a required device pointer");
+    return NPM_OK;
+}
+
+npm_status npm_backward_select(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                               const float *dir, const float *radiance,
+                               const float *sampling_pdf, const float *bsdf_pdf,
+                               float *grad_out, double *loss_out, void *stream)
+{
+    npm_status st = check_train_select(ctx, n, pos, aux, dir, radiance, sampling_pdf, bsdf_pdf);
+    if (st != NPM_OK) return st;
+    if (grad_out && !aligned4(grad_out)) return fail(NPM_ERR_INVALID_ARG, "misaligned grad_out");
+    if (n == 0) return NPM_OK;
+    try {
+        return backward_impl(ctx, n, pos, aux, dir, radiance, sampling_pdf,
+                             grad_out ? grad_out : ctx->grads, loss_out, (hipStream_t)stream,
+                             bsdf_pdf);
+    } catch (...) {
+        return fail(NPM_ERR_HIP, "unexpected exception");
+    }
+}
+
+npm_status npm_train_step_select(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                                 const float *dir, const float *radiance,
+                                 const float *sampling_pdf, const float *bsdf_pdf,
+                                 double *stats_out, void *stream)
+{
+    npm_status st = check_train_select(ctx, n, pos, aux, dir, radiance, sampling_pdf, bsdf_pdf);
+    if (st != NPM_OK) return st;
+    if (n > 0) {
+        try {
+            st = backward_impl(ctx, n, pos, aux, dir, radiance, sampling_pdf, ctx->grads,
+                               stats_out, (hipStream_t)stream, bsdf_pdf);
+        } catch (...) {
+            return fail(NPM_ERR_HIP, "unexpected exception");
+        }
+        if (st != NPM_OK) return st;
+    }
+    return npm_optimizer_step(ctx, nullptr, stats_out ? stats_out + 2 : nullptr, stream);
 }
 
 npm_status npm_corner_index(npm_ctx *ctx, int64_t n, const float *pos, uint32_t *idx, void *stream)

@@ -327,6 +327,8 @@ npm_status npm_session_create(npm_server *s, const npm_config *cfg, int32_t *sid
     npm_config c = *cfg;
     if (c.sh_degree != 0)
         return sfail(NPM_ERR_INVALID_ARG, "sessions take radiance-based networks (sh_degree 0)");
+    if (c.learn_selection != 0)
+        return sfail(NPM_ERR_INVALID_ARG, "sessions take networks without the selection output");
     const bool shared = s->cfg.plain_path == 0 && c.precision == NPM_PREC_BF16 &&
                         serve_supports(&c);
     if (s->cfg.plain_path) {

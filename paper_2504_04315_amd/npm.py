@@ -36,7 +36,7 @@ class npm_config(C.Structure):
         ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
         ("batch_order", C.c_int32), ("ema_decay", C.c_float), ("sh_degree", C.c_int32),
         ("scatter_mode", C.c_int32), ("resolution", C.c_int32 * MAX_LEVELS),
-        ("seed", C.c_uint64),
+        ("learn_selection", C.c_int32), ("seed", C.c_uint64),
     ]
 
 
@@ -85,6 +85,9 @@ SIGNATURES = {
     "npm_encode_aux": [_P, _i64, _P, _P, _P, _P],
     "npm_forward_raw_aux": [_P, _i64, _P, _P, _P, _P],
     "npm_backward_static": [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _P],
+    "npm_query_select": [_P, _i64, _P, _P, _P, _u64, _u32, _P, _P, _P, _P, _P, _P],
+    "npm_backward_select": [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "npm_train_step_select": [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _P],
 }
 STATIC_MAX_N = 32768
 
@@ -124,7 +127,8 @@ def check(status):
 
 
 def make_config(net, exec_mode=EXEC_STAGED, precision=None, lr=None, seed=None,
-                batch_order=ORDER_AUTO, ema_decay=0.0, sh_degree=None, scatter_mode=SCATTER_AUTO):
+                batch_order=ORDER_AUTO, ema_decay=0.0, sh_degree=None, scatter_mode=SCATTER_AUTO,
+                learn_selection=None):
     """npm_config from a workload.NetConfig (sizes of a workload)."""
     c = npm_config()
     check(lib().npm_config_default(C.byref(c)))
@@ -147,6 +151,8 @@ def make_config(net, exec_mode=EXEC_STAGED, precision=None, lr=None, seed=None,
     c.sh_degree = getattr(net, "sh_degree", 0) if sh_degree is None else sh_degree
     for l, d in enumerate(getattr(net, "resolution", None) or ()):
         c.resolution[l] = d
+    sel = getattr(net, "select", False) if learn_selection is None else learn_selection
+    c.learn_selection = int(bool(sel))
     return c
 
 
@@ -246,6 +252,40 @@ class NPM:
         check(lib().npm_train_step_aux(self._ctx, pos.shape[1], _ptr(pos), _ptr(aux), _ptr(dir),
                                        _ptr(radiance), _ptr(pdf), _ptr(stats), _stream(stream)))
 
+    # -- learned BSDF-selection probability (learn_selection networks)
+    def query_select(self, pos, dir=None, seed=0, stream_id=0, lobes=True, pdf=None, sample=True,
+                     stream=None, aux=None):
+        """query() plus "select_prob" [n], the probability of sampling the BSDF."""
+        import torch
+        n = pos.shape[1]
+        dev = pos.device
+        out = {}
+        out["lobes"] = torch.empty((4, 8, n), device=dev) if lobes else None
+        want_pdf = (dir is not None) if pdf is None else pdf
+        out["pdf"] = torch.empty(n, device=dev) if want_pdf else None
+        out["sample_dir"] = torch.empty((3, n), device=dev) if sample else None
+        out["sample_pdf"] = torch.empty(n, device=dev) if sample else None
+        out["select_prob"] = torch.empty(n, device=dev)
+        check(lib().npm_query_select(self._ctx, n, _ptr(pos), _ptr(aux), _ptr(dir), seed,
+                                     stream_id, _ptr(out["lobes"]), _ptr(out["pdf"]),
+                                     _ptr(out["sample_dir"]), _ptr(out["sample_pdf"]),
+                                     _ptr(out["select_prob"]), _stream(stream)))
+        return out
+
+    def backward_select(self, pos, dir, radiance, pdf, bsdf_pdf, grad=None, loss=None,
+                        stream=None, aux=None):
+        """npm_backward_select; loss: two doubles (mixture, selection) or None."""
+        check(lib().npm_backward_select(self._ctx, pos.shape[1], _ptr(pos), _ptr(aux), _ptr(dir),
+                                        _ptr(radiance), _ptr(pdf), _ptr(bsdf_pdf), _ptr(grad),
+                                        _ptr(loss), _stream(stream)))
+
+    def train_step_select(self, pos, dir, radiance, pdf, bsdf_pdf, stats=None, stream=None,
+                          aux=None):
+        """npm_train_step_select; stats: three doubles (loss, loss_sel, |g|^2) or None."""
+        check(lib().npm_train_step_select(self._ctx, pos.shape[1], _ptr(pos), _ptr(aux),
+                                          _ptr(dir), _ptr(radiance), _ptr(pdf), _ptr(bsdf_pdf),
+                                          _ptr(stats), _stream(stream)))
+
     # -- stage outputs
     def corner_index(self, pos, stream=None):
         import torch
@@ -264,7 +304,7 @@ class NPM:
     def forward_raw(self, pos, stream=None, aux=None):
         import torch
         n = pos.shape[1]
-        raw = torch.empty((32, n), device=pos.device)
+        raw = torch.empty((self.layout.n_out, n), device=pos.device)
         check(lib().npm_forward_raw_aux(self._ctx, n, _ptr(pos), _ptr(aux), _ptr(raw),
                                         _stream(stream)))
         return raw

@@ -49,6 +49,7 @@ class NetConfig:
     seed: int = 1
     sh_degree: int = 0           # NPM-product: SH bands of omega_o and the normal
     resolution: tuple = ()       # explicit per-level resolutions (empty: grow base..max)
+    select: bool = False         # learned BSDF-selection probability (one more output)
 
     @property
     def n_in(self):
@@ -83,6 +84,11 @@ PAPER = NetConfig(n_levels=8, feat=4, base_res=8, max_res=86, log2_table=19, den
 CFG2P = replace(CFG2, sh_degree=4, seed=8)
 PAPERP = replace(PAPER, sh_degree=4, seed=9)
 TINYP = replace(TINY, sh_degree=2, seed=10)
+
+# Learned BSDF-selection probability (Sec. 6.3 extension): one more output.
+TINYS = replace(TINY, select=True, seed=11)
+CFG1S = replace(CFG1, select=True, seed=12)
+PAPERS = replace(PAPER, select=True, seed=13)
 
 N_CFG1 = 16384
 N_CFG2 = 1 << 20

@@ -12,6 +12,16 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 BINARY = os.path.join(HERE, "npm_client")
 
 
+def up_to_date():
+    """Whether the in-tree binary exists and is newer than the header and
+    the client's source (a stale binary would pass the wrong structures)."""
+    if not os.path.exists(BINARY):
+        return False
+    t = os.path.getmtime(BINARY)
+    return all(os.path.getmtime(f) <= t for f in (os.path.join(ROOT, "include", "npm.h"),
+                                                   os.path.join(HERE, "npm_client.c")))
+
+
 def build(out=BINARY):
     cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROCM, "include"),

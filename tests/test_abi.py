@@ -32,7 +32,8 @@ def test_every_declared_symbol_is_exported():
     from paper_2504_04315_amd import serve as S
     assert set(S.SIGNATURES) <= names
     assert {"npm_server_create", "npm_submit_train", "npm_server_hold",
-            "npm_backward_static"} <= names
+            "npm_backward_static", "npm_query_select", "npm_backward_select",
+            "npm_train_step_select"} <= names
 
 
 def test_version_and_last_error():
@@ -139,6 +140,43 @@ def test_explicit_resolution_table_matches_oracle(O):
     c = B.make_config(net)
     c.resolution[6] = 9                         # an entry past n_levels
     assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+
+
+@pytest.mark.parametrize("net", ["TINYS", "CFG1S", "PAPERS"])
+def test_selection_layout_matches_oracle(O, net):
+    """learn_selection (the Sec. 6.3 extension): the last layer gets one more
+    row, 4K + 1 outputs, as in the oracle."""
+    net = getattr(W, net)
+    L = B.layout_of(B.make_config(net))
+    on = O.Net(net.n_levels, net.feat, net.base_res, net.max_res, net.log2_table, net.dense_only,
+               net.n_hidden, net.width, net.n_lobes, select=True)
+    plain = B.layout_of(B.make_config(net, learn_selection=False))
+    assert L.n_out == on.n_out == 4 * net.n_lobes + 1 and plain.n_out == 4 * net.n_lobes
+    assert L.n_params == on.n_params == plain.n_params + net.width
+    for i in range(L.n_layers):
+        assert L.layer_offset[i] == on.layer_offset[i]
+        assert (L.layer_out[i], L.layer_in[i]) == on.layer_shape[i]
+
+
+def test_selection_config_rules():
+    """The selection output runs on the staged path; the flag is 0 or 1; the
+    selection calls refuse a null context."""
+    lib = B.lib()
+    out = B.npm_layout()
+    c = B.make_config(W.TINYS)
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == 0
+    c.exec_mode = B.EXEC_FUSED
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+    assert b"staged path" in lib.npm_last_error()
+    c = B.make_config(W.TINYS)
+    c.learn_selection = 2
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+    assert lib.npm_query_select(None, 4, None, None, None, 0, 0, None, None, None, None, None,
+                                None) == -1
+    assert lib.npm_backward_select(None, 4, None, None, None, None, None, None, None, None,
+                                   None) == -1
+    assert lib.npm_train_step_select(None, 4, None, None, None, None, None, None, None,
+                                     None) == -1
 
 
 def test_moving_average_adds_its_buffers_to_the_layout():

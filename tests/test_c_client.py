@@ -33,7 +33,7 @@ def test_client_builds_and_reports_no_device(tmp_path):
 
 @pytest.mark.gpu
 def test_client_matches_the_oracle(O, tmp_path):
-    exe = cbuild.BINARY if os.path.exists(cbuild.BINARY) else cbuild.build(str(tmp_path / "c"))
+    exe = cbuild.BINARY if cbuild.up_to_date() else cbuild.build(str(tmp_path / "c"))
     r = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     print(r.stdout.strip())

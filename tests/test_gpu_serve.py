@@ -351,4 +351,6 @@ def test_product_sessions_are_refused(torch):
     srv = S.Server(budget_bytes=4 << 30, max_sessions=2)
     with pytest.raises(B.NPMError):
         srv.create_session(B.make_config(W.TINYP, exec_mode=B.EXEC_FUSED))
+    with pytest.raises(B.NPMError, match="selection"):
+        srv.create_session(B.make_config(W.TINYS))
     srv.close()
