@@ -119,6 +119,9 @@ def parse():
                    help="few steps, no CPU baseline, for rocprofv3 runs")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy (counter calibration)")
+    p.add_argument("--only", choices=["selection", "serving"],
+                   help="run one extra leg alone (a short version, for rocprofv3 runs) and "
+                        "print its JSON instead of the step benchmark")
     return p.parse_args()
 
 
@@ -211,9 +214,11 @@ def serving_bench(n_sessions=32, per_session=6, load=0.7, sweep=(0.3, 0.9)):
     FP16 hash grid, T = 2^17, MLP 32-64-64-64-32), each a Poisson stream of
     query batches with sizes log-uniform in 2^10..2^18 and a training batch
     after every 4 queries.  First the saturation throughput (everything
-    submitted at once), then the same plan offered at `load` times it (the
-    reported latency) and at the `sweep` loads; both for the shared
-    persistent kernels (BF16) and the per-session plain FP32 path."""
+    submitted at once), the plan's queries alone and its training batches
+    alone at saturation (the query and the training rates), then the mixed
+    plan offered at `load` times its saturation rate (the reported latency)
+    and at the `sweep` loads; both for the shared persistent kernels (BF16)
+    and the per-session plain FP32 path."""
     from paper_2504_04315_amd import npm as B
     from paper_2504_04315_amd import serve as S
     from paper_2504_04315_amd import workload as W
@@ -232,6 +237,9 @@ def serving_bench(n_sessions=32, per_session=6, load=0.7, sweep=(0.3, 0.9)):
             r["t"] = 0.0
         S.run_load(srv, sids, plan[:n_sessions])
         sat = S.run_load(srv, sids, plan)
+        # each kind alone at saturation: the query and the training rates
+        sat_q = S.run_load(srv, sids, [r for r in plan if r["kind"] == 0])
+        sat_t = S.run_load(srv, sids, [r for r in plan if r["kind"] == 1])
         def offered(f, seed):
             rate = f * sat["vertices_per_s"] / (n_sessions * mean_n * 1.25)
             plan2 = S.plan_requests(n_sessions, per_session, rate_hz=rate, train_every=4,
@@ -241,6 +249,8 @@ def serving_bench(n_sessions=32, per_session=6, load=0.7, sweep=(0.3, 0.9)):
         res = offered(load, 2)
         out[name] = {"saturation_vertices_per_s": sat["vertices_per_s"],
                      "saturation_latency_ms": sat["latency_ms"],
+                     "query_only_vertices_per_s": sat_q["vertices_per_s"],
+                     "train_only_vertices_per_s": sat_t["vertices_per_s"],
                      "offered_vertices_per_s": load * sat["vertices_per_s"],
                      "vertices_per_s": res["vertices_per_s"], "latency_ms": res["latency_ms"],
                      "query_latency_ms": res["query_latency_ms"],
@@ -385,8 +395,10 @@ def selection_bench(reps=20, warm=5):
     return out
 
 
-def load_traffic(workload, sha):
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+def load_profile(kind, workload, sha):
+    """A counter summary under profiles/ (traffic_* or counters_*), if it was
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}.json")
     if not os.path.exists(path):
         return {}
     d = json.load(open(path))
@@ -404,6 +416,14 @@ def main():
     from paper_2504_04315_amd import workload as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only:
+        torch.cuda.set_device(0)
+        if args.only == "selection":
+            leg = selection_bench(reps=3, warm=1)
+        else:
+            leg = serving_bench(n_sessions=8, per_session=4, sweep=())
+        print(json.dumps({"leg": args.only, args.only: leg}), flush=True)
+        return
     torch.cuda.set_device(0)
     netcfg = W.CFG2 if args.precision == "fp32" else W.CFG3
     n = args.n
@@ -464,7 +484,8 @@ def main():
 
     # ---- roofline of the dominant kernel
     sha = kernel_sources_sha()
-    traffic = load_traffic(f"cfg2_{args.precision}_{args.mode}", sha)
+    traffic = load_profile("traffic", f"cfg2_{args.precision}_{args.mode}", sha)
+    measured = load_profile("counters", f"cfg2_{args.precision}_{args.mode}", sha)
     np_params = model.n_params
     work = dict(WORK)
     if "bin_reduce" in kt:
@@ -505,6 +526,12 @@ def main():
             # (copy-calibrated), null when the kernels changed since
             "traffic": None if tr is None else tr["fetch_bytes"] + tr["write_bytes"],
             "traffic_fetch_write": (None if tr is None else [tr["fetch_bytes"], tr["write_bytes"]])}
+    mc = measured.get("kernels", {}).get(dom)
+    if mc is not None:
+        # counter evidence beside the time-derived fraction (rocprofv3 --pmc):
+        # MFMA, VALU and LDS busy fractions of the SIMDs, the L2 hit rate
+        roof["measured"] = {k: round(v, 4) for k, v in mc.items()
+                            if k in ("mfma_busy", "valu_busy", "lds_busy", "l2_hit")}
     if tr is not None and tr.get("atomic_requests"):
         # the FP32 grid-gradient atomics are executed at the memory side, one
         # request per 64-byte line and wave instruction; their rate, not the

@@ -502,15 +502,9 @@ __device__ __forceinline__ GridView grid_view(const GridDesc &g, const uint32_t 
 }
 
 // ------------------------------------------------------------------ backward
-// Per tile: forward with activations in registers, the KL-gradient head, the
-// delta chain (backward images: W^T as the A operand), the grid scatter, and
-// the weight gradients.  For the weight gradients the tile's deltas and layer
-// inputs are transposed through a per-wave LDS buffer (rows = features,
-// 36-float stride) so that the 32 vertices become the MFMA reduction
-// dimension; each wave accumulates dW over all its tiles in registers and
-// writes one partial at the end.
-constexpr int kStride = 36;   // LDS row stride (floats) of the transpose buffer
-constexpr int kTransRows = 64;   // rows of a wave's transpose buffer (T32 registers 0..31)
+// A wave's LDS buffer for the in-kernel grid scatter: the tile's dG as rows =
+// features (36-float stride), then the aggregation window.
+constexpr int kStride = 36;   // LDS row stride (floats) of the buffer
 
 // Writes a T32-layout vector of width 2*REGS into the wave's LDS buffer.
 template <int REGS>
@@ -521,133 +515,11 @@ __device__ __forceinline__ void t32_to_lds(float *buf, const float *x, int lane)
     for (int a = 0; a < REGS; ++a) buf[nf(h, a) * kStride + j] = x[a];
 }
 
-// Reads rows [32 b, 32 b + 32) of the buffer transposed: lane l gets row
-// 32 b + l % 32 at vertices 16 (l / 32) + s, s = 0..15.
-__device__ __forceinline__ void lds_rows(const float *buf, int b, int lane, float *r)
-{
-    const float *p = buf + (32 * b + (lane & 31)) * kStride + 16 * (lane >> 5);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const f32x4 t = *reinterpret_cast<const f32x4 *>(p + 4 * q);
-        r[4 * q] = t[0]; r[4 * q + 1] = t[1]; r[4 * q + 2] = t[2]; r[4 * q + 3] = t[3];
-    }
-}
-
 __device__ __forceinline__ void wave_lds_fence()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
-
-// dW (OUT_P x IN_P, in 32x32 blocks) += sum over the tile's 32 vertices of
-// dz x^T.  FP32: 16 steps of 32x32x2 per block pair, lane l supplying vertex
-// 16 (l/32) + s.  BF16: 2 steps of 32x32x16, lane l supplying the 8 vertices
-// 16 (l/32) + 8 s + e, rounded to BF16 (FP32 accumulation).
-template <int OUT_P, int IN_P, bool BF>
-__device__ __forceinline__ void dw_tile(float *buf, const float *dz, const float *xin,
-                                        f32x16 (*acc)[IN_P / 32], int lane)
-{
-    constexpr int NBO = OUT_P / 32, NBI = IN_P / 32;
-    static_assert(OUT_P <= kTransRows, "the transpose buffer holds kTransRows rows");
-    float A[NBO][16], Bv[NBI][16];
-    wave_lds_fence();
-    t32_to_lds<OUT_P / 2>(buf, dz, lane);
-    wave_lds_fence();
-#pragma unroll
-    for (int b = 0; b < NBO; ++b) lds_rows(buf, b, lane, A[b]);
-    // the layer input in pieces of at most kTransRows rows: registers
-    // [32, 48) of a T32 vector hold its rows [64, 96)
-    constexpr int P0R = IN_P < kTransRows ? IN_P : kTransRows;
-    wave_lds_fence();
-    t32_to_lds<P0R / 2>(buf, xin, lane);
-    wave_lds_fence();
-#pragma unroll
-    for (int b = 0; b < P0R / 32; ++b) lds_rows(buf, b, lane, Bv[b]);
-    if constexpr (IN_P > kTransRows) {
-        constexpr int P1R = IN_P - kTransRows;
-        static_assert(P1R <= kTransRows, "layer inputs are at most 2 kTransRows wide");
-        wave_lds_fence();
-        t32_to_lds<P1R / 2>(buf, xin + kTransRows / 2, lane);
-        wave_lds_fence();
-#pragma unroll
-        for (int b = 0; b < P1R / 32; ++b) lds_rows(buf, b, lane, Bv[kTransRows / 32 + b]);
-    }
-    if constexpr (BF) {
-        // step s2 takes the vertices 16 (l/32) + 8 s2 + e: the lane's own values
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-            bf16x8 a8[NBO], b8[NBI];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-#pragma unroll
-                for (int b = 0; b < NBO; ++b) a8[b][e] = (__bf16)A[b][8 * s2 + e];
-#pragma unroll
-                for (int b = 0; b < NBI; ++b) b8[b][e] = (__bf16)Bv[b][8 * s2 + e];
-            }
-#pragma unroll
-            for (int bo = 0; bo < NBO; ++bo)
-#pragma unroll
-                for (int bi = 0; bi < NBI; ++bi)
-                    acc[bo][bi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8[bo], b8[bi], acc[bo][bi], 0, 0, 0);
-        }
-    } else {
-#pragma unroll
-        for (int s = 0; s < 16; ++s)
-#pragma unroll
-            for (int bo = 0; bo < NBO; ++bo)
-#pragma unroll
-                for (int bi = 0; bi < NBI; ++bi)
-                    acc[bo][bi] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[bo][s], Bv[bi][s], acc[bo][bi], 0, 0, 0);
-    }
-}
-
-// How dw_store writes: plain store, add to what is there (the caller makes
-// the writes exclusive), or FP32 atomic add.
-enum { DW_STORE = 0, DW_ADD = 1, DW_ATOMIC = 2 };
-
-template <int OUT_P, int IN_P, int MODE>
-__device__ __forceinline__ void dw_store(float *dst, int out_r, int in_r, f32x16 (*acc)[IN_P / 32],
-                                         int lane)
-{
-    const int h = lane >> 5, j = lane & 31;
-#pragma unroll
-    for (int bo = 0; bo < OUT_P / 32; ++bo)
-#pragma unroll
-        for (int bi = 0; bi < IN_P / 32; ++bi)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = 32 * bo + nf(h, r), col = 32 * bi + j;
-                if (row < out_r && col < in_r) {
-                    if (MODE == DW_ATOMIC) unsafeAtomicAdd(dst + row * in_r + col, acc[bo][bi][r]);
-                    else if (MODE == DW_ADD) dst[row * in_r + col] += acc[bo][bi][r];
-                    else dst[row * in_r + col] = acc[bo][bi][r];
-                }
-            }
-}
-
-// Weight-gradient accumulators of one wave, in 32x32 MFMA blocks: layer 0
-// (HID x IN0), the hidden layers (HID x HID), the output layer (32 x HID).
-template <int IN_P, int HID_P, int NH>
-struct DwAcc {
-    static constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
-    static constexpr int NHH = NH > 1 ? NH - 1 : 1;
-    f32x16 l0[HID_P / 32][IN0 / 32];
-    f32x16 hid[NHH][HID_P / 32][HID_P / 32];
-    f32x16 last[1][HID_P / 32];
-    __device__ __forceinline__ void zero()
-    {
-#pragma unroll
-        for (int i = 0; i < HID_P / 32; ++i) {
-#pragma unroll
-            for (int j = 0; j < IN0 / 32; ++j) l0[i][j] = 0.0f;
-#pragma unroll
-            for (int li = 0; li < NHH; ++li)
-#pragma unroll
-                for (int j = 0; j < HID_P / 32; ++j) hid[li][i][j] = 0.0f;
-            last[0][i] = 0.0f;
-        }
-    }
-};
 
 struct TrainIO {
     int64_t n;
@@ -902,94 +774,165 @@ __device__ __forceinline__ void tile_input(const GridView &gv, const TrainIO &io
     }
 }
 
-template <int IN_P, int HID_P, int NH, int F, bool BF, bool STORE_DG = false, int PG = 0>
-__device__ __forceinline__ void backward_tile(const GridView &gv, const char *fwd, const char *bwd,
-                                              float *tbuf, const TrainIO &io, int64_t t, int lane,
-                                              DwAcc<IN_P, HID_P, NH> &dw, double &lacc,
-                                              float *dg_tiles = nullptr)
-{
-    constexpr int ESZ = BF ? 2 : 4;
-    constexpr int IN0 = IN_P < 32 ? 32 : IN_P;       // layer-0 input rows padded to a 32 block
-    constexpr int OUT0 = IN0;
-    const int h = lane >> 5;
-    const int64_t n = io.n;
-    const int64_t v = t * 32 + (lane & 31);
-    const bool valid = v < n;
-    const int64_t vs = valid ? v : n - 1;
-    const int64_t vv = visit(io.perm, vs);
-    const TrainInputs in = train_inputs(io, vs, vv);
-    const float px = in.px, py = in.py, pz = in.pz;
-    float x[IN0 / 2];
-    tile_input<IN_P, F, BF, PG>(gv, io, in, vs, vv, h, x);
-    float acts[NH][HID_P / 2];
-    float o[16];
-    mlp_forward<IN_P, HID_P, NH, BF, true>(fwd, x, acts, o, lane);
-    float d[16];
-    kl_head(o, in, valid, io.invN, h, d, lacc);
-    if (!io.grad) return;          // loss only
-    // ---- weight gradient of the output layer, then the delta chain
-    dw_tile<32, HID_P, BF>(tbuf, d, acts[NH - 1], dw.last, lane);
-    float dh[HID_P / 2];
-    layer<BF, 32, HID_P>(bwd, d, dh, lane);
-    const char *im = bwd + (size_t)HID_P * 32 * ESZ;
-#pragma unroll
-    for (int li = NH - 1; li >= 0; --li) {
-#pragma unroll
-        for (int i = 0; i < HID_P / 2; ++i) dh[i] = acts[li][i] > 0.0f ? dh[i] : 0.0f;
-        if (li > 0) {
-            dw_tile<HID_P, HID_P, BF>(tbuf, dh, acts[li - 1], dw.hid[li - 1], lane);
-            float nd[HID_P / 2];
-            layer<BF, HID_P, HID_P>(im, dh, nd, lane);
-            im += (size_t)HID_P * HID_P * ESZ;
-#pragma unroll
-            for (int i = 0; i < HID_P / 2; ++i) dh[i] = nd[i];
-        } else {
-            dw_tile<HID_P, IN0, BF>(tbuf, dh, x, dw.l0, lane);
-        }
+// ------------------------------------------------------------------ block-cooperative weight gradients
+// The training kernel splits the weight gradients of a block among its WV
+// waves.  In every round each wave runs encode, forward, KL-gradient head and
+// delta chain for its own 32-vertex tile (the block takes a contiguous run of
+// tiles, WV at a time); per layer, from the output layer back, the waves put
+// the layer's deltas and inputs into a shared LDS exchange buffer, transposed
+// (rows = features, one column per vertex of the round), and each wave
+// accumulates its own share of that layer's 32x32 weight-gradient blocks
+// over all 32 WV vertices of the round (the MFMA reduction dimension).  Each
+// dW block belongs to one wave, which keeps ceil(blocks / WV) accumulators in
+// registers instead of all of them and writes them straight to the block's
+// partial at the end: no register spills, no per-wave partial sums.
+//
+// Layers are numbered 0 (the first, IN0 inputs) to NH (the output layer, 32
+// outputs); the phases run from NH down to 0, and the dW blocks are numbered
+// in that order, block g belonging to wave g % WV in its slot g / WV.
+template <int IN_P, int HID_P, int NH, int WV>
+struct BlockPlan {
+    static constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
+    static constexpr int out_p(int L) { return L == NH ? 32 : HID_P; }
+    static constexpr int in_p(int L) { return L == 0 ? IN0 : HID_P; }
+    static constexpr int nbi(int L) { return in_p(L) / 32; }
+    static constexpr int blocks(int L) { return (out_p(L) / 32) * nbi(L); }
+    // the first block of layer L in phase order
+    static constexpr int first(int L)
+    {
+        int g = 0;
+        for (int l = NH; l > L; --l) g += blocks(l);
+        return g;
     }
-    // input gradient: of the grid features only with NPM-product inputs (the
-    // first 32 rows; the caller stages only that block of W_0^T)
-    constexpr int DGR = PG > 0 ? 32 : OUT0;
-    static_assert(PG == 0 || STORE_DG, "NPM-product tiles store dG for the scatter kernels");
-    float dG[DGR / 2];
-    layer<BF, HID_P, DGR>(im, dh, dG, lane);
-    if constexpr (STORE_DG) {
-        float *dst = dg_tiles + (size_t)t * OUT0 * 32 + (lane & 31);
-#pragma unroll
-        for (int a = 0; a < DGR / 2; ++a) dst[nf(h, a) * 32] = dG[a];
-    } else {
-        // ---- grid scatter, coalesced: dG through the wave's LDS buffer, the
-        // rows above it as the aggregation window: FP64 sums (LDS FP64 atomic
-        // adds run several times faster than FP32 ones on this chip), or in
-        // the precision form 32-bit fixed point (no FP64)
-        using WinT = typename std::conditional<BF, int, double>::type;
-        constexpr int WIN_PTS = (HID_P - OUT0) * kStride / (2 * F);
-        float lo[3], hi[3];
-        if constexpr (WIN_PTS > 0) tile_bbox(px, py, pz, lo, hi);
-        wave_lds_fence();
-        t32_to_lds<OUT0 / 2>(tbuf, dG, lane);
-        wave_lds_fence();
-        scatter_tile<F, WIN_PTS, WinT>(gv, tbuf, io.pos, io.perm, n, t, lane, io.grad, lo, hi,
-                                       reinterpret_cast<WinT *>(tbuf + OUT0 * kStride), io.rec,
-                                       io.rec_stride);
+    static constexpr int total() { return first(-1); }
+    static constexpr int slots() { return (total() + WV - 1) / WV; }
+    // rows of the exchange buffer in phase L: the deltas, then the inputs
+    static constexpr int rows(int L) { return out_p(L) + in_p(L); }
+    static constexpr int max_rows()
+    {
+        int r = 0;
+        for (int l = 0; l <= NH; ++l) r = rows(l) > r ? rows(l) : r;
+        return r;
+    }
+    // row stride of the exchange buffer (elements): the round's 32 WV
+    // vertices plus a pad that puts consecutive rows 4 banks apart, so that
+    // the 16-byte reads of 16 lanes on 16 rows hit distinct banks
+    static constexpr int xs(bool bf) { return 32 * WV + (bf ? 8 : 4); }
+    // FP32 row-major image: layer L's rows are in_p(L) + 1 floats apart
+    static constexpr int rm_stride(int L) { return in_p(L) + 1; }
+    static constexpr int rm_off(int L)
+    {
+        int o = 0;
+        for (int l = 0; l < L; ++l) o += out_p(l) * rm_stride(l);
+        return o;
+    }
+    static constexpr int rm_elems() { return rm_off(NH + 1); }
+};
+
+// fn(std::integral_constant<int, I>) for I = HI, HI - 1, .., LO (nothing if
+// HI < LO): a loop whose index is a compile-time constant in the body.
+template <int HI, int LO, class Fn>
+__device__ __forceinline__ void static_for_down(Fn &&fn)
+{
+    if constexpr (HI >= LO) {
+        fn(std::integral_constant<int, HI>{});
+        static_for_down<HI - 1, LO>(fn);
     }
 }
 
-// Writes (or atomically adds) a wave's weight gradients in the flat layer
-// layout of the MLP part of the parameters.
-template <int IN_P, int HID_P, int NH, int MODE>
-__device__ __forceinline__ void dw_flush(float *dst, int n_in, int width, DwAcc<IN_P, HID_P, NH> &dw,
-                                         int lane)
+// Rows [row0, row0 + 2 REGS) of the exchange buffer, at this wave's 32
+// columns, from a tile-layout vector of 2 REGS features.
+template <int REGS, int XS, typename XT>
+__device__ __forceinline__ void xch_put(XT *xb, int row0, int wave, const float *v, int lane)
 {
-    constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
-    dw_store<HID_P, IN0, MODE>(dst, width, n_in, dw.l0, lane);
-    dst += width * n_in;
+    const int h = lane >> 5, j = lane & 31;
+    XT *p = xb + row0 * XS + 32 * wave + j;
 #pragma unroll
-    for (int li = 0; li < NH - 1; ++li) {
-        dw_store<HID_P, HID_P, MODE>(dst, width, width, dw.hid[li], lane);
-        dst += width * width;
+    for (int a = 0; a < REGS; ++a) p[nf(h, a) * XS] = XT(v[a]);
+}
+
+// acc (a 32x32 dW block) += sum over the round's KV vertices of
+// delta[ro + row] input[ri + col], rows of the exchange buffer.  FP32:
+// 32x32x2 steps, the half-wave h supplying the vertices [KV/2 h, KV/2 (h+1))
+// in order, four per 16-byte read.  BF16: 32x32x16 steps, half h supplying
+// the vertices 16 s + 8 h + e.
+template <int KV, int XS>
+__device__ __forceinline__ void dw_block(const float *xb, int ro, int ri, f32x16 &acc, int lane)
+{
+    const int i = lane & 31, h = lane >> 5;
+    const float *pa = xb + (ro + i) * XS + (KV / 2) * h;
+    const float *pb = xb + (ri + i) * XS + (KV / 2) * h;
+#pragma unroll
+    for (int q = 0; q < KV / 8; ++q) {
+        const f32x4 A = *reinterpret_cast<const f32x4 *>(pa + 4 * q);
+        const f32x4 Bv = *reinterpret_cast<const f32x4 *>(pb + 4 * q);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[e], Bv[e], acc, 0, 0, 0);
     }
-    dw_store<32, HID_P, MODE>(dst, 32, width, dw.last, lane);
+}
+template <int KV, int XS>
+__device__ __forceinline__ void dw_block(const __bf16 *xb, int ro, int ri, f32x16 &acc, int lane)
+{
+    const int i = lane & 31, h = lane >> 5;
+    const __bf16 *pa = xb + (ro + i) * XS + 8 * h;
+    const __bf16 *pb = xb + (ri + i) * XS + 8 * h;
+#pragma unroll
+    for (int s = 0; s < KV / 16; ++s) {
+        const bf16x8 A = *reinterpret_cast<const bf16x8 *>(pa + 16 * s);
+        const bf16x8 Bv = *reinterpret_cast<const bf16x8 *>(pb + 16 * s);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bv, acc, 0, 0, 0);
+    }
+}
+
+// Phase L of a round: put this wave's deltas dz and layer inputs hin into the
+// exchange buffer; after the barrier accumulate this wave's dW blocks of the
+// layer.  The caller runs the next chain step between this and the barrier
+// that ends the phase.
+template <class Plan, int L, int WV, int XS, typename XT, int NS>
+__device__ __forceinline__ void dw_phase(XT *xb, const float *dz, const float *hin, int wave,
+                                         f32x16 (&acc)[NS], int lane)
+{
+    constexpr int OUT = Plan::out_p(L), IN = Plan::in_p(L);
+    xch_put<OUT / 2, XS>(xb, 0, wave, dz, lane);
+    xch_put<IN / 2, XS>(xb, OUT, wave, hin, lane);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < Plan::blocks(L); ++b) {
+        constexpr int g0 = Plan::first(L);
+        if ((g0 + b) % WV == wave) {
+            const int bo = b / Plan::nbi(L), bi = b % Plan::nbi(L);
+            dw_block<32 * WV, XS>(xb, 32 * bo, OUT + 32 * bi, acc[(g0 + b) / WV], lane);
+        }
+    }
+}
+
+// This wave's dW blocks into the flat layout of the MLP weights at dst
+// (entries outside the real shapes dropped): stored, or with ATOMIC added by
+// FP32 atomics (several blocks add into one buffer).
+template <class Plan, int NH, int WV, bool ATOMIC = false, int NS>
+__device__ __forceinline__ void dw_write(float *dst, int n_in, int width, int wave,
+                                         f32x16 (&acc)[NS], int lane)
+{
+    const int h = lane >> 5, j = lane & 31;
+    static_for_down<NH, 0>([&](auto LC) {
+        constexpr int L = decltype(LC)::value;
+        const int out_r = L == NH ? 32 : width, in_r = L == 0 ? n_in : width;
+        float *d = dst + (L == 0 ? 0 : width * n_in + (L - 1) * width * width);
+#pragma unroll
+        for (int b = 0; b < Plan::blocks(L); ++b) {
+            const int g = Plan::first(L) + b;
+            if (g % WV != wave) continue;
+            const int bo = b / Plan::nbi(L), bi = b % Plan::nbi(L);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 32 * bo + nf(h, r), col = 32 * bi + j;
+                if (row < out_r && col < in_r) {
+                    if constexpr (ATOMIC) unsafeAtomicAdd(d + row * in_r + col, acc[g / WV][r]);
+                    else d[row * in_r + col] = acc[g / WV][r];
+                }
+            }
+        }
+    });
 }
 
 }  // namespace npm

@@ -91,161 +91,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 }
 
 // ------------------------------------------------------------------ training
-// The training kernel splits the weight gradients of a block among its WV
-// waves.  In every round each wave runs encode, forward, KL-gradient head and
-// delta chain for its own 32-vertex tile (the block takes a contiguous run of
-// tiles, WV at a time); per layer, from the output layer back, the waves put
-// the layer's deltas and inputs into a shared LDS exchange buffer, transposed
-// (rows = features, one column per vertex of the round), and each wave
-// accumulates its own share of that layer's 32x32 weight-gradient blocks
-// over all 32 WV vertices of the round (the MFMA reduction dimension).  Each
-// dW block belongs to one wave, which keeps ceil(blocks / WV) accumulators in
-// registers instead of all of them and writes them straight to the block's
-// partial at the end: no register spills, no per-wave partial sums.
-//
-// Layers are numbered 0 (the first, IN0 inputs) to NH (the output layer, 32
-// outputs); the phases run from NH down to 0, and the dW blocks are numbered
-// in that order, block g belonging to wave g % WV in its slot g / WV.
-template <int IN_P, int HID_P, int NH, int WV>
-struct BlockPlan {
-    static constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
-    static constexpr int out_p(int L) { return L == NH ? 32 : HID_P; }
-    static constexpr int in_p(int L) { return L == 0 ? IN0 : HID_P; }
-    static constexpr int nbi(int L) { return in_p(L) / 32; }
-    static constexpr int blocks(int L) { return (out_p(L) / 32) * nbi(L); }
-    // the first block of layer L in phase order
-    static constexpr int first(int L)
-    {
-        int g = 0;
-        for (int l = NH; l > L; --l) g += blocks(l);
-        return g;
-    }
-    static constexpr int total() { return first(-1); }
-    static constexpr int slots() { return (total() + WV - 1) / WV; }
-    // rows of the exchange buffer in phase L: the deltas, then the inputs
-    static constexpr int rows(int L) { return out_p(L) + in_p(L); }
-    static constexpr int max_rows()
-    {
-        int r = 0;
-        for (int l = 0; l <= NH; ++l) r = rows(l) > r ? rows(l) : r;
-        return r;
-    }
-    // row stride of the exchange buffer (elements): the round's 32 WV
-    // vertices plus a pad that puts consecutive rows 4 banks apart, so that
-    // the 16-byte reads of 16 lanes on 16 rows hit distinct banks
-    static constexpr int xs(bool bf) { return 32 * WV + (bf ? 8 : 4); }
-    // FP32 row-major image: layer L's rows are in_p(L) + 1 floats apart
-    static constexpr int rm_stride(int L) { return in_p(L) + 1; }
-    static constexpr int rm_off(int L)
-    {
-        int o = 0;
-        for (int l = 0; l < L; ++l) o += out_p(l) * rm_stride(l);
-        return o;
-    }
-    static constexpr int rm_elems() { return rm_off(NH + 1); }
-};
-
-// fn(std::integral_constant<int, I>) for I = HI, HI - 1, .., LO (nothing if
-// HI < LO): a loop whose index is a compile-time constant in the body.
-template <int HI, int LO, class Fn>
-__device__ __forceinline__ void static_for_down(Fn &&fn)
-{
-    if constexpr (HI >= LO) {
-        fn(std::integral_constant<int, HI>{});
-        static_for_down<HI - 1, LO>(fn);
-    }
-}
-
-// Rows [row0, row0 + 2 REGS) of the exchange buffer, at this wave's 32
-// columns, from a tile-layout vector of 2 REGS features.
-template <int REGS, int XS, typename XT>
-__device__ __forceinline__ void xch_put(XT *xb, int row0, int wave, const float *v, int lane)
-{
-    const int h = lane >> 5, j = lane & 31;
-    XT *p = xb + row0 * XS + 32 * wave + j;
-#pragma unroll
-    for (int a = 0; a < REGS; ++a) p[nf(h, a) * XS] = XT(v[a]);
-}
-
-// acc (a 32x32 dW block) += sum over the round's KV vertices of
-// delta[ro + row] input[ri + col], rows of the exchange buffer.  FP32:
-// 32x32x2 steps, the half-wave h supplying the vertices [KV/2 h, KV/2 (h+1))
-// in order, four per 16-byte read.  BF16: 32x32x16 steps, half h supplying
-// the vertices 16 s + 8 h + e.
-template <int KV, int XS>
-__device__ __forceinline__ void dw_block(const float *xb, int ro, int ri, f32x16 &acc, int lane)
-{
-    const int i = lane & 31, h = lane >> 5;
-    const float *pa = xb + (ro + i) * XS + (KV / 2) * h;
-    const float *pb = xb + (ri + i) * XS + (KV / 2) * h;
-#pragma unroll
-    for (int q = 0; q < KV / 8; ++q) {
-        const f32x4 A = *reinterpret_cast<const f32x4 *>(pa + 4 * q);
-        const f32x4 Bv = *reinterpret_cast<const f32x4 *>(pb + 4 * q);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[e], Bv[e], acc, 0, 0, 0);
-    }
-}
-template <int KV, int XS>
-__device__ __forceinline__ void dw_block(const __bf16 *xb, int ro, int ri, f32x16 &acc, int lane)
-{
-    const int i = lane & 31, h = lane >> 5;
-    const __bf16 *pa = xb + (ro + i) * XS + 8 * h;
-    const __bf16 *pb = xb + (ri + i) * XS + 8 * h;
-#pragma unroll
-    for (int s = 0; s < KV / 16; ++s) {
-        const bf16x8 A = *reinterpret_cast<const bf16x8 *>(pa + 16 * s);
-        const bf16x8 Bv = *reinterpret_cast<const bf16x8 *>(pb + 16 * s);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bv, acc, 0, 0, 0);
-    }
-}
-
-// Phase L of a round: put this wave's deltas dz and layer inputs hin into the
-// exchange buffer; after the barrier accumulate this wave's dW blocks of the
-// layer.  The caller runs the next chain step between this and the barrier
-// that ends the phase.
-template <class Plan, int L, int WV, int XS, typename XT, int NS>
-__device__ __forceinline__ void dw_phase(XT *xb, const float *dz, const float *hin, int wave,
-                                         f32x16 (&acc)[NS], int lane)
-{
-    constexpr int OUT = Plan::out_p(L), IN = Plan::in_p(L);
-    xch_put<OUT / 2, XS>(xb, 0, wave, dz, lane);
-    xch_put<IN / 2, XS>(xb, OUT, wave, hin, lane);
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < Plan::blocks(L); ++b) {
-        constexpr int g0 = Plan::first(L);
-        if ((g0 + b) % WV == wave) {
-            const int bo = b / Plan::nbi(L), bi = b % Plan::nbi(L);
-            dw_block<32 * WV, XS>(xb, 32 * bo, OUT + 32 * bi, acc[(g0 + b) / WV], lane);
-        }
-    }
-}
-
-// This wave's dW blocks into the flat layout of the MLP weights at dst
-// (entries outside the real shapes dropped).
-template <class Plan, int NH, int WV, int NS>
-__device__ __forceinline__ void dw_write(float *dst, int n_in, int width, int wave,
-                                         f32x16 (&acc)[NS], int lane)
-{
-    const int h = lane >> 5, j = lane & 31;
-    static_for_down<NH, 0>([&](auto LC) {
-        constexpr int L = decltype(LC)::value;
-        const int out_r = L == NH ? 32 : width, in_r = L == 0 ? n_in : width;
-        float *d = dst + (L == 0 ? 0 : width * n_in + (L - 1) * width * width);
-#pragma unroll
-        for (int b = 0; b < Plan::blocks(L); ++b) {
-            const int g = Plan::first(L) + b;
-            if (g % WV != wave) continue;
-            const int bo = b / Plan::nbi(L), bi = b % Plan::nbi(L);
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = 32 * bo + nf(h, r), col = 32 * bi + j;
-                if (row < out_r && col < in_r) d[row * in_r + col] = acc[g / WV][r];
-            }
-        }
-    });
-}
+// The block-cooperative weight gradients (BlockPlan, dw_phase, dw_write) are
+// in fused_tiles.h, shared with the serving kernel.
 
 // Weight-image elements a BF16 training block stages in LDS: the forward and
 // backward images, except that with NPM-product inputs only the grid

@@ -44,8 +44,15 @@ struct RoundHdr {
 static_assert(sizeof(RoundHdr) <= 64, "the round header sits in the first 64 bytes");
 
 constexpr int kQueryChunkTiles = 4;    // one tile per wave
-constexpr int kTrainWaveTiles = 4;     // tiles per wave per training chunk
-constexpr int kTrainChunkTiles = 4 * kTrainWaveTiles;
+constexpr int kTrainChunkTiles = 16;   // four rounds of one tile per wave
+
+// Bytes of a training block's LDS exchange buffer (BF16, after the images).
+template <int IN_P, int HID_P, int NH>
+constexpr size_t serve_xch_bytes()
+{
+    using Plan = BlockPlan<IN_P, HID_P, NH, 4>;
+    return ((size_t)Plan::max_rows() * Plan::xs(true) * 2 + 15) / 16 * 16;
+}
 
 // Request of chunk c among [r0, r1): the last one whose chunk_begin <= c.
 __device__ __forceinline__ int find_request(const int *s_begin, int r0, int r1, int c)
@@ -101,31 +108,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
-// Training batches of requests [r0, r1): each wave runs kTrainWaveTiles
-// consecutive tiles of a chunk, then adds its weight gradients and loss into
-// the session's buffers with atomics.
+// Training batches of requests [r0, r1), the fused path's block-cooperative
+// scheme (fused_tiles.h): a chunk is kTrainChunkTiles tiles of one request,
+// run as rounds of one tile per wave; per layer the waves exchange deltas and
+// inputs in LDS and each wave accumulates its share of the weight-gradient
+// blocks over the round's 128 vertices.  The shares stay in registers while
+// the block's chunks belong to one request (its chunks are handed out in
+// order, so a block usually takes several in a row) and are added into that
+// session's gradient with FP32 atomics when the request changes and at the
+// end: per block and request, one add per weight.  Each tile's grid gradient
+// is scattered from the wave's LDS buffer, its coarse levels through a 32-bit
+// fixed-point window (no FP64 accumulator), the rest by FP32 atomics.
 template <int IN_P, int HID_P, int NH, int F>
 __global__ __launch_bounds__(256) void k_serve_train(RoundHdr *hdr, const DevReq *__restrict__ reqs,
                                                      int r0, int r1, int n_chunks, int which,
                                                      int img_bytes_max)
 {
+    constexpr int WV = 4;
+    using Plan = BlockPlan<IN_P, HID_P, NH, WV>;
+    constexpr int IN0 = Plan::IN0;
+    constexpr int XS = Plan::xs(true);
+    constexpr int NS = Plan::slots();
+    constexpr int WIN_PTS = (HID_P - IN0) * kStride / (2 * F);
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ uint32_t s_off[NPM_MAX_LEVELS];
     __shared__ int s_res[NPM_MAX_LEVELS];
     __shared__ int s_begin[kMaxRoundRequests];
     __shared__ int s_chunk;
     for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) s_begin[i] = reqs[i].chunk_begin;
-    int staged = -1;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float *tbuf = reinterpret_cast<float *>(smem + ((size_t)img_bytes_max + 15) / 16 * 16) +
+    int staged = -1, cur = -1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, h = lane >> 5;
+    const size_t img_al = ((size_t)img_bytes_max + 15) / 16 * 16;
+    __bf16 *xb = reinterpret_cast<__bf16 *>(smem + img_al);
+    float *tbuf = reinterpret_cast<float *>(smem + img_al + serve_xch_bytes<IN_P, HID_P, NH>()) +
                   wave * HID_P * kStride;
+    f32x16 acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[k][v] = 0.0f;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_chunk = (int)atomicAdd(&hdr->counter[which], 1u);
         __syncthreads();
         const int chunk = s_chunk;
+        const int r = chunk < n_chunks ? find_request(s_begin, r0, r1, chunk) : -1;
+        if (r != cur) {
+            if (cur >= 0) {
+                const DevReq &c = reqs[cur];
+                dw_write<Plan, NH, WV, true>(c.grad + c.mlp_off, c.n_in, c.width, wave, acc, lane);
+#pragma unroll
+                for (int k = 0; k < NS; ++k)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) acc[k][v] = 0.0f;
+            }
+            cur = r;
+        }
         if (chunk >= n_chunks) break;
-        const int r = find_request(s_begin, r0, r1, chunk);
         const DevReq &q = reqs[r];
         if (q.skey != staged) {
             stage_bytes(smem, q.img, (q.fwd_elems + q.bwd_elems) * 2);
@@ -133,26 +172,68 @@ __global__ __launch_bounds__(256) void k_serve_train(RoundHdr *hdr, const DevReq
             staged = q.skey;
             __syncthreads();
         }
-        const int64_t t0 = ((int64_t)(chunk - q.chunk_begin) * 4 + wave) * kTrainWaveTiles;
-        if (t0 * 32 < q.n) {
-            const GridView gv = grid_view(q.g, s_off, s_res, nullptr, q.grid16);
-            const TrainIO io{q.n, q.pos, q.dir, q.rad, q.spdf, q.grad, q.invN, nullptr};
-            const char *fwd = smem;
-            const char *bwd = smem + (size_t)q.fwd_elems * 2;
-            DwAcc<IN_P, HID_P, NH> dw;
-            dw.zero();
-            double lacc = 0.0;
-            for (int i = 0; i < kTrainWaveTiles; ++i) {
-                const int64_t t = t0 + i;
-                if (t * 32 >= q.n) break;
-                backward_tile<IN_P, HID_P, NH, F, true>(gv, fwd, bwd, tbuf, io, t, lane, dw, lacc);
+        const GridView gv = grid_view(q.g, s_off, s_res, nullptr, q.grid16);
+        const TrainIO io{q.n, q.pos, q.dir, q.rad, q.spdf, q.grad, q.invN, nullptr};
+        const char *fwd = smem;
+        const char *bwd = smem + (size_t)q.fwd_elems * 2;
+        const int64_t ntiles = (q.n + 31) / 32;
+        const int64_t c0 = (int64_t)(chunk - q.chunk_begin) * kTrainChunkTiles;
+        double lacc = 0.0;
+        for (int rr = 0; rr < kTrainChunkTiles / WV; ++rr) {
+            // every wave runs every round of the chunk (the phases
+            // synchronise); a wave past the batch takes a tile with no valid
+            // vertex
+            const int64_t t0 = c0 + (int64_t)rr * WV;
+            if (t0 >= ntiles) break;                    // uniform over the block
+            const int64_t t = t0 + wave;
+            const int64_t v = t * 32 + (lane & 31);
+            const bool valid = v < q.n;
+            const int64_t vs = valid ? v : q.n - 1;
+            const TrainInputs in = train_inputs(io, vs, vs);
+            float x[IN0 / 2];
+            tile_input<IN_P, F, true, 0>(gv, io, in, vs, vs, h, x);
+            float acts[NH][HID_P / 2], o[16], d[16];
+            mlp_forward<IN_P, HID_P, NH, true, true>(fwd, x, acts, o, lane);
+            kl_head(o, in, valid, io.invN, h, d, lacc);
+            // ---- output layer's dW, then the delta chain
+            float dh[HID_P / 2];
+            dw_phase<Plan, NH, WV, XS>(xb, d, acts[NH - 1], wave, acc, lane);
+            layer<true, 32, HID_P>(bwd, d, dh, lane);
+            __syncthreads();
+            const char *im = bwd + (size_t)HID_P * 32 * 2;
+            static_for_down<NH - 1, 1>([&](auto LC) {
+                constexpr int li = decltype(LC)::value;
+#pragma unroll
+                for (int i = 0; i < HID_P / 2; ++i) dh[i] = acts[li][i] > 0.0f ? dh[i] : 0.0f;
+                dw_phase<Plan, li, WV, XS>(xb, dh, acts[li - 1], wave, acc, lane);
+                float nd[HID_P / 2];
+                layer<true, HID_P, HID_P>(im, dh, nd, lane);
+                im += (size_t)HID_P * HID_P * 2;
+#pragma unroll
+                for (int i = 0; i < HID_P / 2; ++i) dh[i] = nd[i];
+                __syncthreads();
+            });
+#pragma unroll
+            for (int i = 0; i < HID_P / 2; ++i) dh[i] = acts[0][i] > 0.0f ? dh[i] : 0.0f;
+            dw_phase<Plan, 0, WV, XS>(xb, dh, x, wave, acc, lane);
+            float dG[IN0 / 2];
+            layer<true, HID_P, IN0>(im, dh, dG, lane);
+            __syncthreads();
+            // ---- the tile's grid scatter from the wave's own buffer
+            if (t < ntiles) {
+                float lo[3], hi[3];
+                if constexpr (WIN_PTS > 0) tile_bbox(in.px, in.py, in.pz, lo, hi);
+                wave_lds_fence();
+                t32_to_lds<IN0 / 2>(tbuf, dG, lane);
+                wave_lds_fence();
+                scatter_tile<F, WIN_PTS, int>(gv, tbuf, io.pos, nullptr, q.n, t, lane, io.grad, lo,
+                                              hi, reinterpret_cast<int *>(tbuf + IN0 * kStride));
             }
-            dw_flush<IN_P, HID_P, NH, DW_ATOMIC>(q.grad + q.mlp_off, q.n_in, q.width, dw, lane);
-            // FP64 loss of the wave (half 0 holds it), one atomic per wave
-            double l = lacc;
-            for (int off = 16; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
-            if (lane == 0) atomicAdd(q.loss, l);
         }
+        // FP64 loss of the wave (half 0 holds it), one atomic per wave
+        double l = lacc;
+        for (int off = 16; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
+        if (lane == 0 && l != 0.0) atomicAdd(q.loss, l);
     }
 }
 
@@ -228,7 +309,9 @@ static hipError_t launch_group(RoundHdr *hdr, const DevReq *reqs, int r0, int r1
         hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, s, hdr, reqs, r0, r1, chunks, which);
     } else {
         auto k = k_serve_train<IN_P, HID_P, NH, F>;
-        const int lds = (img_bytes_max + 15) / 16 * 16 + 4 * HID_P * kStride * (int)sizeof(float);
+        // images, the exchange buffer, four waves' scatter buffers
+        const int lds = (img_bytes_max + 15) / 16 * 16 + (int)serve_xch_bytes<IN_P, HID_P, NH>() +
+                        4 * HID_P * kStride * (int)sizeof(float);
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         hipLaunchKernelGGL(k, dim3(std::min(blocks, 256)), dim3(256), lds, s, hdr, reqs, r0, r1,
                            chunks, which, img_bytes_max);

@@ -227,15 +227,12 @@ def run_load(server, sids, plan, time_scale=1.0):
         first = min(first, inf.submit_us)
         last = max(last, inf.done_us)
     span_s = (last - first) / 1e6
-    allv = lat_q + lat_t
+
+    def pct(v):
+        return dict(p50=float(np.percentile(v, 50)), p99=float(np.percentile(v, 99))) if v else None
     return dict(requests=len(plan), vertices=verts, wall_s=t1 - t0, span_s=span_s,
                 vertices_per_s=verts / span_s,
                 query_vertices=sum(r["n"] for r in plan if r["kind"] == 0),
                 train_vertices=sum(r["n"] for r in plan if r["kind"] == 1),
-                latency_ms=dict(p50=float(np.percentile(allv, 50)),
-                                p99=float(np.percentile(allv, 99))),
-                query_latency_ms=dict(p50=float(np.percentile(lat_q, 50)),
-                                      p99=float(np.percentile(lat_q, 99))),
-                train_latency_ms=(dict(p50=float(np.percentile(lat_t, 50)),
-                                       p99=float(np.percentile(lat_t, 99))) if lat_t else None),
-                rounds=server.stats().rounds)
+                latency_ms=pct(lat_q + lat_t), query_latency_ms=pct(lat_q),
+                train_latency_ms=pct(lat_t), rounds=server.stats().rounds)
