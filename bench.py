@@ -10,7 +10,7 @@ its pdf per vertex) followed by npm_train_step (forward, KL gradient,
 backward, grid scatter, weight gradients, Adam over all parameters).  The
 default run also reports the serving form, the paper's own network on its
 batch sizes, NPM-product, the learned BSDF-selection probability (on the
-paper's network, staged), and the FP64 oracle on the host cores.
+paper's network, staged and fused), and the FP64 oracle on the host cores.
 
 Prints one JSON line.  `value` is vertices per second through a full step
 (query + train on the same batch), inputs resident in HBM.  The roofline
@@ -341,11 +341,12 @@ def product_bench(reps=20, warm=5):
 
 def selection_bench(reps=20, warm=5):
     """The learned BSDF-selection probability (the Sec. 6.3 extension) on the
-    paper's network with its extra output, on the staged FP32 path that
-    carries it: queries of one 1280x720 wavefront returning the selection
-    probability, and training steps of 2^18 vertices with the selection
-    term; the same network without the output on the same path gives the
-    extension's cost; per-kernel times of the selection training step."""
+    paper's network with its extra output: queries of one 1280x720 wavefront
+    returning the selection probability, and training steps of 2^18 vertices
+    with the selection term, on the staged FP32 path, the fused FP32 path and
+    the fused precision form; the same network without the output on the same
+    path gives the extension's cost; per-kernel times of the fused FP32
+    selection training step."""
     import torch
     from paper_2504_04315_amd import npm as B
     from paper_2504_04315_amd import workload as W
@@ -358,40 +359,44 @@ def selection_bench(reps=20, warm=5):
     bsdf = t(W.make_bsdf(tb, 74))
     lib = B.lib()
     out = {"network": "8 dense levels 8..86 x F=4, MLP 32-64-64-33 (32 lobe outputs + the "
-                      "selection logit), K=8, staged FP32",
-           "query_batch": nq, "train_batch": nt}
-    for label, net in (("selection", W.PAPERS), ("without_output", W.PAPER)):
-        m = B.NPM(B.make_config(net, exec_mode=B.EXEC_STAGED))
-        o = [torch.empty((4, 8, nq), device="cuda"), torch.empty(nq, device="cuda"),
-             torch.empty((3, nq), device="cuda"), torch.empty(nq, device="cuda")]
-        sel = torch.empty(nq, device="cuda")
-        if label == "selection":
-            q = lambda i: B.check(lib.npm_query_select(
-                m.handle, nq, B._ptr(qa[0]), None, B._ptr(qa[1]), i, 0, *map(B._ptr, o),
-                B._ptr(sel), B._stream()))
-            tr = lambda i: m.train_step_select(*ta, bsdf)
-        else:
-            q = lambda i: B.check(lib.npm_query_aux(
-                m.handle, nq, B._ptr(qa[0]), None, B._ptr(qa[1]), i, 0, *map(B._ptr, o),
-                B._stream()))
-            tr = lambda i: m.train_step(*ta)
-        q_ms, t_ms = _median_ms(q, reps, warm), _median_ms(tr, reps, warm)
-        out[label] = {"query_ms": q_ms, "train_ms": t_ms,
-                      "query_vertices_per_s": nq / (q_ms / 1e3),
-                      "train_vertices_per_s": nt / (t_ms / 1e3)}
-        if label == "selection":
-            m.set_timing(True)
-            m.reset_timing()
-            for i in range(reps):
-                tr(i)
-            torch.cuda.synchronize()
-            out[label]["train_kernels_ms"] = {k: round(v[1] / v[0], 4)
-                                              for k, v in m.kernel_times().items() if v[0]}
-            m.set_timing(False)
-        m.close()
-    w, s0 = out["selection"], out["without_output"]
-    out["cost"] = {"query": round(w["query_ms"] / s0["query_ms"] - 1.0, 4),
-                   "train": round(w["train_ms"] / s0["train_ms"] - 1.0, 4)}
+                      "selection logit), K=8", "query_batch": nq, "train_batch": nt}
+    forms = (("staged", B.EXEC_STAGED, "fp32"), ("fused", B.EXEC_FUSED, "fp32"),
+             ("fused_bf16", B.EXEC_FUSED, "bf16"))
+    for form, mode, prec in forms:
+        res = {}
+        for label, net in (("selection", W.PAPERS), ("without_output", W.PAPER)):
+            m = B.NPM(B.make_config(net, exec_mode=mode, precision=prec))
+            o = [torch.empty((4, 8, nq), device="cuda"), torch.empty(nq, device="cuda"),
+                 torch.empty((3, nq), device="cuda"), torch.empty(nq, device="cuda")]
+            sel = torch.empty(nq, device="cuda")
+            if label == "selection":
+                q = lambda i: B.check(lib.npm_query_select(
+                    m.handle, nq, B._ptr(qa[0]), None, B._ptr(qa[1]), i, 0, *map(B._ptr, o),
+                    B._ptr(sel), B._stream()))
+                tr = lambda i: m.train_step_select(*ta, bsdf)
+            else:
+                q = lambda i: B.check(lib.npm_query_aux(
+                    m.handle, nq, B._ptr(qa[0]), None, B._ptr(qa[1]), i, 0, *map(B._ptr, o),
+                    B._stream()))
+                tr = lambda i: m.train_step(*ta)
+            q_ms, t_ms = _median_ms(q, reps, warm), _median_ms(tr, reps, warm)
+            res[label] = {"query_ms": q_ms, "train_ms": t_ms,
+                          "query_vertices_per_s": nq / (q_ms / 1e3),
+                          "train_vertices_per_s": nt / (t_ms / 1e3)}
+            if label == "selection" and form == "fused":
+                m.set_timing(True)
+                m.reset_timing()
+                for i in range(reps):
+                    tr(i)
+                torch.cuda.synchronize()
+                res[label]["train_kernels_ms"] = {k: round(v[1] / v[0], 4)
+                                                  for k, v in m.kernel_times().items() if v[0]}
+                m.set_timing(False)
+            m.close()
+        w, s0 = res["selection"], res["without_output"]
+        res["cost"] = {"query": round(w["query_ms"] / s0["query_ms"] - 1.0, 4),
+                       "train": round(w["train_ms"] / s0["train_ms"] - 1.0, 4)}
+        out[form] = res
     return out
 
 

@@ -141,8 +141,12 @@ enum { NPM_SCATTER_AUTO = 0, NPM_SCATTER_ATOMIC = 1, NPM_SCATTER_BINNED = 2 };
  *   c = 1 / (1 + e^{-c'}) is the probability with which the renderer
  *   samples the BSDF rather than the mixture; it is returned by
  *   npm_query_select and trained by npm_backward_select /
- *   npm_train_step_select.  Runs on the staged path (NPM_EXEC_STAGED, FP32);
- *   the plain calls work on such a network and leave the selection row's
+ *   npm_train_step_select.  The staged path takes any radiance-based or
+ *   NPM-product shape; the fused path (FP32 or the precision form) the
+ *   radiance-based shapes (F, inputs, hidden width x layers) (2, <= 16,
+ *   <= 32 x 2), (4, <= 16, 33..64 x 2), (4, 17..32, 33..64 x 2) and (2,
+ *   17..32, 33..64 x 3) -- the tiny, cfg1, paper and production networks.
+ *   The plain calls work on such a network and leave the selection row's
  *   gradient 0.                                                            */
 typedef struct {
     int32_t grid_kind;

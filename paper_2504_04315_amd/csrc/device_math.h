@@ -365,4 +365,55 @@ __device__ __forceinline__ void sh_bands4(float x, float y, float z, float *o)
 // Wave-wide helpers for the two half-waves of a tile.
 __device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); }
 
+// ------------------------------------------------------------------ selection
+// Selection term of one sample (the learned selection probability): the
+// renderer's one-sample density is p_c = c p_bsdf + (1 - c) V, c = sigmoid(c');
+// with V held fixed, d(-(w/N) log p_c)/dc' = g c (1 - c) (p_bsdf - V) / p_c,
+// g = -w/N.  With t = log p_bsdf - log V and c / (1 - c) = e^c' this is
+//   t <= 0:  g c expm1(t) sigmoid(-(c' + t)),
+//   t > 0:   g (1 - c) (-expm1(-t)) sigmoid(c' + t),
+// and log p_c = log V - softplus(c') + softplus(c' + t) (t <= 0), or
+// log p_bsdf - softplus(-c') + softplus(-c' - t) (t > 0): no cancellation,
+// no division, and p_bsdf = 0 (t = -inf) gives -g c and log V + log(1 - c).
+// Writes the derivative and returns log p_c.
+__device__ __forceinline__ float softplusf(float x)
+{
+    return x > 0.0f ? x + log1pf(expf(-x)) : log1pf(expf(x));
+}
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+__device__ __forceinline__ float select_term(float cp, float pb, float lv, float g, float &ds)
+{
+    const float lp = logf(pb);
+    const float t = lp - lv;
+    if (t <= 0.0f) {
+        ds = g * sigmoidf(cp) * expm1f(t) * sigmoidf(-(cp + t));
+        return lv - softplusf(cp) + softplusf(cp + t);
+    }
+    ds = g * sigmoidf(-cp) * -expm1f(-t) * sigmoidf(cp + t);
+    return lp - softplusf(-cp) + softplusf(-cp - t);
+}
+
+// A BSDF density that takes part in the selection term: finite and >= 0.
+__device__ __forceinline__ bool bsdf_valid(float pb) { return isfinite(pb) && pb >= 0.0f; }
+
+// The selection logit of a tile vertex: the last hidden layer hl (tile
+// layout, HID_P features; the two half-waves hold the two halves) dotted with
+// the selection row wsel (16-byte aligned, HID_P floats, zero past the
+// width).  Both halves return the sum.
+template <int HID_P>
+__device__ __forceinline__ float select_logit(const float *wsel, const float *hl, int h)
+{
+    float p = 0.0f;
+#pragma unroll
+    for (int q = 0; q < HID_P / 8; ++q) {
+        const f32x4 w = *reinterpret_cast<const f32x4 *>(wsel + 8 * q + 4 * h);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) p = fmaf(w[e], hl[4 * q + e], p);
+    }
+    return p + xor32(p);
+}
+
+
 }  // namespace npm

@@ -269,10 +269,13 @@ __device__ __forceinline__ const void *img_at(const void *base, int elems)
     return BF ? (const void *)((const __bf16 *)base + elems) : (const void *)((const float *)base + elems);
 }
 
-// Forward of all layers; hidden activations into acts[NH][HID_P/2] when KEEP.
-template <int IN_P, int HID_P, int NH, bool BF, bool KEEP>
+// Forward of all layers; hidden activations into acts[NH][HID_P/2] when KEEP;
+// with SEL also the selection logit *cp (the last hidden layer dotted with the
+// selection row wsel in LDS).
+template <int IN_P, int HID_P, int NH, bool BF, bool KEEP, bool SEL = false>
 __device__ __forceinline__ void mlp_forward(const void *img, const float *x, float (*acts)[HID_P / 2],
-                                            float *o, int lane)
+                                            float *o, int lane, const float *wsel = nullptr,
+                                            float *cp = nullptr)
 {
     float a[HID_P / 2], b[HID_P / 2];
     layer<BF, IN_P, HID_P>(img, x, a, lane);
@@ -292,6 +295,7 @@ __device__ __forceinline__ void mlp_forward(const void *img, const float *x, flo
             for (int i = 0; i < HID_P / 2; ++i) acts[li][i] = a[i];
         }
     }
+    if constexpr (SEL) *cp = select_logit<HID_P>(wsel, a, lane >> 5);
     layer<BF, HID_P, 32>(img_at<BF>(img, HID_P * IN_P + (NH - 1) * HID_P * HID_P), a, o, lane);
 }
 
@@ -338,6 +342,8 @@ struct QueryIO {
     const float *rec = nullptr;         // with perm: the inputs in visiting order
     const float *aux = nullptr;         // NPM-product inputs [7][n]
     int rec_stride = 8;                 // floats per record (16 with NPM-product)
+    float *sel = nullptr;               // selection probability [n] (selection networks)
+    const float *wsel = nullptr;        // the selection row in LDS (HID_P floats)
 };
 
 // A vertex's inputs in visiting order (written by the spatial sort, 32 bytes
@@ -373,11 +379,11 @@ template <> struct ProductShape<2> { static constexpr int GF = 4, SHD = 2; };
 // 20 h + 4 r + q); then pdf at 16, the sample direction at 17..19 and the
 // sample pdf at 36.
 constexpr int kStageFloats = 40;
-constexpr int kStagePdf = 16, kStageSdir = 17, kStageSpdf = 36;
+constexpr int kStagePdf = 16, kStageSdir = 17, kStageSpdf = 36, kStageSel = 37;
 
 // One 32-vertex tile t of a query: encode, MLP, mappings, pdf at dir, one
 // sample per vertex and its pdf.  img: the forward weight image in LDS.
-template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0>
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0, bool SEL = false>
 __device__ __forceinline__ void query_tile(const GridView &gv, const void *img, const QueryIO &io,
                                            int64_t t, int lane)
 {
@@ -406,8 +412,15 @@ __device__ __forceinline__ void query_tile(const GridView &gv, const void *img, 
         load_aux(io.rec, io.rec_stride, io.aux, n, valid ? v : n - 1, vv, a7);
         aux_fill<IN_P, ProductShape<PG>::GF, ProductShape<PG>::SHD>(h, a7, x);
     }
-    float o[16];
-    mlp_forward<IN_P, HID_P, NH, BF, false>(img, x, nullptr, o, lane);
+    float o[16], cp = 0.0f;
+    mlp_forward<IN_P, HID_P, NH, BF, false, SEL>(img, x, nullptr, o, lane, io.wsel, &cp);
+    if constexpr (SEL) {
+        if (io.sel && valid && h == 0) {
+            const float c = sigmoidf(cp);
+            if (st) st[kStageSel] = c;
+            else io.sel[vv] = c;
+        }
+    }
     Lobe L[4];
     map_half(o, L);
     if (io.lobes && valid) {
@@ -530,6 +543,7 @@ struct TrainIO {
     const float *rec = nullptr;   // with perm: the inputs in visiting order
     const float *aux = nullptr;   // NPM-product inputs [7][n]
     int rec_stride = 8;           // floats per record (16 with NPM-product)
+    const float *bsdf = nullptr;  // BSDF densities [n] (the selection term), or null
 };
 
 // The vertex at position v of the visiting order.
@@ -734,9 +748,10 @@ __device__ __forceinline__ TrainInputs train_inputs(const TrainIO &io, int64_t v
 
 // The KL-gradient head (Sec. 4.2, eq. mcgradients) of a tile: d = d loss /
 // d raw for this half-wave's four lobes, from the raw outputs o; lacc
-// accumulates -w log V (FP64) of half 0's vertices.
-__device__ __forceinline__ void kl_head(const float *o, const TrainInputs &in, bool valid,
-                                        float invN, int h, float *d, double &lacc)
+// accumulates -w log V (FP64) of half 0's vertices.  Returns log V at the
+// sample's direction.
+__device__ __forceinline__ float kl_head(const float *o, const TrainInputs &in, bool valid,
+                                         float invN, int h, float *d, double &lacc)
 {
     const float wgt = valid ? sample_weight(in.rad, in.spdf) : 0.0f;
 #pragma unroll
@@ -753,6 +768,7 @@ __device__ __forceinline__ void kl_head(const float *o, const TrainInputs &in, b
                       expf(L[r].loglam), g, in.wx, in.wy, in.wz, d + 4 * r);
         if (h == 0) lacc -= (double)wgt * (double)lv;
     }
+    return lv;
 }
 
 // The MLP input of a tile vertex in the tile layout: the grid encoding, the
@@ -808,9 +824,12 @@ struct BlockPlan {
     static constexpr int slots() { return (total() + WV - 1) / WV; }
     // rows of the exchange buffer in phase L: the deltas, then the inputs
     static constexpr int rows(int L) { return out_p(L) + in_p(L); }
+    // with the selection output, the output layer's phase also carries the
+    // selection derivative, one row after its deltas and inputs
+    static constexpr int sel_row() { return rows(NH); }
     static constexpr int max_rows()
     {
-        int r = 0;
+        int r = sel_row() + 1;
         for (int l = 0; l <= NH; ++l) r = rows(l) > r ? rows(l) : r;
         return r;
     }

@@ -51,23 +51,34 @@ struct FusedArgs {
     const float *rec;        // inputs in visiting order (with perm), rec_stride floats each
     const float *aux;        // NPM-product inputs [7][n]
     int rec_stride;
+    // learned selection probability (networks with the selection output)
+    const float *wsel;       // the selection row of the last layer (FP32 weights)
+    const float *bsdf;       // BSDF densities [n] of the selection term (backward), or null
+    double *partials_sel;    // per-block FP64 partials of the selection loss
+    float *sel;              // selection probability [n] (query), or null
 };
-template <int IN_P, int HID_P, int NH, int F, bool BF, int PG>
+// SEL: the network has the selection output (its logit is computed from the
+// last hidden layer and the row staged in LDS; a.sel receives sigmoid of it).
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG, bool SEL = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_query_fused(FusedArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ uint32_t s_off[NPM_MAX_LEVELS];
     __shared__ int s_res[NPM_MAX_LEVELS];
+    __shared__ __attribute__((aligned(16))) float s_wsel[SEL ? HID_P : 4];
     {
         const int bytes = a.fwd_elems * (BF ? 2 : 4);
         for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x)
             reinterpret_cast<f32x4 *>(smem)[i] = reinterpret_cast<const f32x4 *>(a.img)[i];
         stage_levels(a.g, s_off, s_res);
+        if constexpr (SEL)
+            for (int i = threadIdx.x; i < HID_P; i += blockDim.x)
+                s_wsel[i] = i < a.width ? a.wsel[i] : 0.0f;
     }
     __syncthreads();
     const GridView gv = grid_view(a.g, s_off, s_res, a.grid32, a.grid16);
     const QueryIO io{a.n, a.pos, a.dir, a.lobes, a.pdf, a.sdir, a.spdf_out, a.seed, a.sid,
-                     a.perm, a.qstage, a.rec, a.aux, a.rec_stride};
+                     a.perm, a.qstage, a.rec, a.aux, a.rec_stride, a.sel, s_wsel};
     const int lane = threadIdx.x & 63;
     const int64_t ntiles = (a.n + 31) / 32;
     const int wpb = blockDim.x / 64, wave = threadIdx.x >> 6;
@@ -82,11 +93,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         const int64_t wpx = (int64_t)(gridDim.x / 8) * wpb, span = (ntiles + 7) / 8;
         const int64_t t0 = xcd * span, t1 = t0 + span < ntiles ? t0 + span : ntiles;
         for (int64_t t = t0 + bl * wpb + wave; t < t1; t += wpx)
-            query_tile<IN_P, HID_P, NH, F, BF, PG>(gv, smem, io, t, lane);
+            query_tile<IN_P, HID_P, NH, F, BF, PG, SEL>(gv, smem, io, t, lane);
     } else {
         const int64_t nwaves = (int64_t)gridDim.x * wpb;
         for (int64_t t = blockIdx.x * (int64_t)wpb + wave; t < ntiles; t += nwaves)
-            query_tile<IN_P, HID_P, NH, F, BF, PG>(gv, smem, io, t, lane);
+            query_tile<IN_P, HID_P, NH, F, BF, PG, SEL>(gv, smem, io, t, lane);
     }
 }
 
@@ -105,7 +116,42 @@ static int64_t staged_elems(const FusedArgs &a, int in_p, int hid_p, int pg)
     return (int64_t)a.fwd_elems + a.bwd_elems - (int64_t)(in0 - dg_rows) * hid_p;
 }
 
-template <int IN_P, int HID_P, int NH, int F, bool BF, int PG, int WV>
+// 32 exchange-buffer values of a and b (16-byte aligned) multiplied and summed.
+__device__ __forceinline__ float dot32(const float *a, const float *b)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const f32x4 x = reinterpret_cast<const f32x4 *>(a)[q];
+        const f32x4 y = reinterpret_cast<const f32x4 *>(b)[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s = fmaf(x[e], y[e], s);
+    }
+    return s;
+}
+__device__ __forceinline__ float dot32(const __bf16 *a, const __bf16 *b)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bf16x8 x = reinterpret_cast<const bf16x8 *>(a)[q];
+        const bf16x8 y = reinterpret_cast<const bf16x8 *>(b)[q];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s = fmaf((float)x[e], (float)y[e], s);
+    }
+    return s;
+}
+
+// SEL: the network has the selection output (the learned BSDF-selection
+// probability).  Its logit c' is the last hidden layer dotted with the
+// selection row (staged in LDS); with BSDF densities the head adds the
+// selection term's derivative d (eq. mcgradients applied to the one-sample
+// density c p_bsdf + (1 - c) V, V fixed) and the chain adds d times the row to
+// the last hidden layer's delta.  The row's weight gradient sums d times the
+// last hidden layer over the round: d goes into the exchange buffer one row
+// after the output layer's deltas and inputs, and lane f of wave q sums
+// feature f over wave q's 32 vertices; the waves' sums add at the end.
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG, int WV, bool SEL = false>
 __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp_weights,
                                                            int tiles_per_block, int img_bytes)
 {
@@ -120,17 +166,22 @@ __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp
     __shared__ uint32_t s_off[NPM_MAX_LEVELS];
     __shared__ int s_res[NPM_MAX_LEVELS];
     __shared__ double red[64 * WV];
+    __shared__ __attribute__((aligned(16))) float s_wsel[SEL ? HID_P : 4];
     // weights: BF16 the packed forward and backward images, FP32 the
     // row-major image (both directions)
     for (int i = threadIdx.x; i < img_bytes / 16; i += blockDim.x)
         reinterpret_cast<f32x4 *>(smem)[i] = reinterpret_cast<const f32x4 *>(a.img)[i];
     stage_levels(a.g, s_off, s_res);
+    if constexpr (SEL)
+        for (int i = threadIdx.x; i < HID_P; i += blockDim.x) s_wsel[i] = i < a.width ? a.wsel[i] : 0.0f;
     __syncthreads();
     XT *xb = reinterpret_cast<XT *>(smem + ((size_t)img_bytes + 15) / 16 * 16);
     const GridView gv = grid_view(a.g, s_off, s_res, a.grid32, a.grid16);
     const TrainIO io{a.n, a.pos, a.dir, a.rad, a.spdf, a.grad, a.invN, a.perm, a.rec, a.aux,
-                     a.rec_stride};
+                     a.rec_stride, a.bsdf};
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, h = lane >> 5;
+    float selacc = 0.0f;          // SEL: the row's gradient, feature `lane`, this wave's vertices
+    double lsel = 0.0;            // SEL: -w log p_c of half 0's vertices
     const float *rm = reinterpret_cast<const float *>(smem);
     const char *fwd = smem;
     const char *bwd = smem + (size_t)a.fwd_elems * ESZ;
@@ -208,13 +259,39 @@ __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp
                                                                   acts[NH - 1], o, lane);
         }
         float d[16];
-        kl_head(o, in, valid, io.invN, h, d, lacc);
+        const float lv = kl_head(o, in, valid, io.invN, h, d, lacc);
+        float ds = 0.0f;            // SEL: d loss / d c'
+        if constexpr (SEL) {
+            const float cp = select_logit<HID_P>(s_wsel, acts[NH - 1], h);
+            const float wgt = valid ? sample_weight(in.rad, in.spdf) : 0.0f;
+            if (wgt != 0.0f && io.bsdf) {
+                const float pb = io.bsdf[vv];
+                if (bsdf_valid(pb)) {
+                    const float lpc = select_term(cp, pb, lv, -wgt * io.invN, ds);
+                    if (h == 0) lsel -= (double)wgt * (double)lpc;
+                }
+            }
+        }
         if (!a.grad) continue;      // loss only (uniform over the grid)
         // ---- output layer: its dW, then the first delta of the chain
         float dh[HID_P / 2];
+        if constexpr (SEL)
+            if (h == 0) xb[Plan::sel_row() * XS + 32 * wave + (lane & 31)] = XT(ds);
         dw_phase<Plan, NH, WV, XS>(xb, d, acts[NH - 1], wave, acc, lane);
+        if constexpr (SEL)
+            if (lane < HID_P)
+                selacc += dot32(xb + Plan::sel_row() * XS + 32 * wave,
+                                xb + (Plan::out_p(NH) + lane) * XS + 32 * wave);
         if constexpr (BF) layer<true, 32, HID_P>(bwd, d, dh, lane);
         else mfma_layer_rm<32, HID_P, Plan::rm_stride(NH), true>(rm + Plan::rm_off(NH), d, dh, lane);
+        if constexpr (SEL) {
+#pragma unroll
+            for (int q = 0; q < HID_P / 8; ++q) {
+                const f32x4 w = *reinterpret_cast<const f32x4 *>(s_wsel + 8 * q + 4 * h);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dh[4 * q + e] = fmaf(ds, w[e], dh[4 * q + e]);
+            }
+        }
         __syncthreads();
         // ---- hidden layers NH-1 .. 1
         const char *im = bwd + (size_t)HID_P * 32 * ESZ;
@@ -259,9 +336,32 @@ __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp
         __syncthreads();
     }
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
+    if constexpr (SEL) {
+        __syncthreads();
+        red[threadIdx.x] = lsel;
+        __syncthreads();
+        for (int w = (int)blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.partials_sel[blockIdx.x] = red[0];
+    }
     if (!a.grad) return;
     dw_write<Plan, NH, WV>(a.dw_part + (int64_t)blockIdx.x * mlp_weights, a.n_in, a.width, wave,
                            acc, lane);
+    if constexpr (SEL) {
+        // the selection row (after the output layer's 32 rows): the waves' sums
+        __syncthreads();
+        red[threadIdx.x] = selacc;
+        __syncthreads();
+        if (wave == 0 && lane < a.width) {
+            float sum = 0.0f;
+            for (int w = 0; w < WV; ++w) sum += (float)red[64 * w + lane];
+            const int64_t row = (int64_t)a.width * a.n_in + (int64_t)(NH - 1) * a.width * a.width +
+                                32 * a.width;
+            a.dw_part[(int64_t)blockIdx.x * mlp_weights + row + lane] = sum;
+        }
+    }
 }
 
 // Aggregated grid scatter of the per-tile dG (stride `rows` rows of 32 per
@@ -333,7 +433,8 @@ __global__ __launch_bounds__(256) void k_query_unstage(int64_t n, const uint32_t
                                                        float *__restrict__ lobes,
                                                        float *__restrict__ pdf,
                                                        float *__restrict__ sdir,
-                                                       float *__restrict__ spdf)
+                                                       float *__restrict__ spdf,
+                                                       float *__restrict__ sel)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -353,6 +454,7 @@ __global__ __launch_bounds__(256) void k_query_unstage(int64_t n, const uint32_t
 #pragma unroll
         for (int d = 0; d < 3; ++d) sdir[(int64_t)d * n + i] = c[kStageSdir + d];
     if (spdf) spdf[i] = c[kStageSpdf];
+    if (sel) sel[i] = c[kStageSel];
 }
 
 // Sum of the blocks' weight-gradient partials into the gradient: a block of
@@ -404,13 +506,13 @@ static FusedArgs fused_args(npm_ctx *ctx, int64_t n, const float *pos)
     return a;
 }
 
-template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0>
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0, bool SEL = false>
 static hipError_t run_query(npm_ctx *ctx, FusedArgs a, hipStream_t s)
 {
     const int64_t tiles = (a.n + 31) / 32;
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2048));
     const size_t lds = (size_t)a.fwd_elems * (BF ? 2 : 4);
-    auto k = k_query_fused<IN_P, HID_P, NH, F, BF, PG>;
+    auto k = k_query_fused<IN_P, HID_P, NH, F, BF, PG, SEL>;
     hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, s, a);
     return hipGetLastError();
@@ -431,7 +533,7 @@ static int backward_blocks(int64_t n)
 // room for the kernel's static arrays (level table, FP64 loss partials).
 constexpr size_t kLdsBytes = 160 * 1024 - 4096;
 
-template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0>
+template <int IN_P, int HID_P, int NH, int F, bool BF, int PG = 0, bool SEL = false>
 static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
 {
     using Plan = BlockPlan<IN_P, HID_P, NH, kTrainWaves>;
@@ -448,7 +550,7 @@ static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
     const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
     if (lds > kLdsBytes) return hipErrorInvalidValue;
     if (!BF) a.img = ctx->mlp_img + ctx->net.mlp.fwd_elems + ctx->net.mlp.bwd_elems;
-    auto k = k_backward_fused<IN_P, HID_P, NH, F, BF, PG, kTrainWaves>;
+    auto k = k_backward_fused<IN_P, HID_P, NH, F, BF, PG, kTrainWaves, SEL>;
     hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * kTrainWaves), lds, s, a, count, tpb, (int)img);
     return hipGetLastError();
@@ -493,10 +595,30 @@ static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
         }                                                                                         \
     } while (0)
 
+// Networks with the selection output: the tiny (4 inputs, width 8), cfg1
+// (16 inputs, 64 x 2), the paper's (32 inputs, 64 x 2) and the production
+// (32 inputs, 64 x 3) shapes.
+#define NPM_FUSED_SEL_DISPATCH(RUN, BFV)                                                          \
+    do {                                                                                          \
+        const MlpDesc &m_ = ctx->net.mlp;                                                         \
+        const int F_ = ctx->net.grid.feat;                                                        \
+        const int key_ = F_ * 1000 + (m_.in_p == 32) * 100 + (m_.hid_p == 64) * 10 + m_.n_hidden; \
+        switch (key_) {                                                                           \
+        case 2002: e = RUN<16, 32, 2, 2, BFV, 0, true>(ctx, a, s); break;                         \
+        case 4012: e = RUN<16, 64, 2, 4, BFV, 0, true>(ctx, a, s); break;                         \
+        case 4112: e = RUN<32, 64, 2, 4, BFV, 0, true>(ctx, a, s); break;                         \
+        case 2113: e = RUN<32, 64, 3, 2, BFV, 0, true>(ctx, a, s); break;                         \
+        default: return hipErrorNotSupported;                                                     \
+        }                                                                                         \
+    } while (0)
+
 #define NPM_FUSED_RUN(RUN)                                                                        \
     do {                                                                                          \
         const bool bf_ = ctx->net.cfg.precision == NPM_PREC_BF16;                                 \
-        if (ctx->net.mlp.sh_degree > 0) {                                                         \
+        if (ctx->net.cfg.learn_selection) {                                                       \
+            if (bf_) NPM_FUSED_SEL_DISPATCH(RUN, true);                                           \
+            else NPM_FUSED_SEL_DISPATCH(RUN, false);                                              \
+        } else if (ctx->net.mlp.sh_degree > 0) {                                                  \
             if (bf_) NPM_FUSED_PRODUCT_DISPATCH(RUN, true);                                       \
             else NPM_FUSED_PRODUCT_DISPATCH(RUN, false);                                          \
         } else {                                                                                  \
@@ -509,6 +631,13 @@ bool fused_shape_supported(const Net &net)
 {
     const MlpDesc &m = net.mlp;
     const int F = net.grid.feat;
+    if (net.cfg.learn_selection) {
+        if (m.sh_degree > 0) return false;
+        switch (F * 1000 + (m.in_p == 32) * 100 + (m.hid_p == 64) * 10 + m.n_hidden) {
+        case 2002: case 4012: case 4112: case 2113: return m.in_p <= 32;
+        default: return false;
+        }
+    }
     if (m.sh_degree > 0) {
         switch (m.sh_degree * 100000 + F * 10000 + m.in_p * 100 + (m.hid_p == 64) * 10 + m.n_hidden) {
         case 429612: case 429613: case 449612: case 449613: case 221602: return true;
@@ -525,7 +654,8 @@ bool fused_shape_supported(const Net &net)
 hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                        const float *dir, uint64_t seed, uint32_t stream_id, float *lobes,
                        float *pdf, float *sdir, float *spdf, const uint32_t *perm,
-                       const uint32_t *inv, const float *rec, float *stage, hipStream_t s)
+                       const uint32_t *inv, const float *rec, float *stage, hipStream_t s,
+                       float *sel)
 {
     FusedArgs a = fused_args(ctx, n, pos);
     a.aux = aux;
@@ -543,6 +673,8 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *a
     a.perm = perm;
     a.qstage = perm ? stage : nullptr;
     a.rec = perm ? rec : nullptr;
+    a.wsel = selection_row(ctx, w.grid32);
+    a.sel = sel;
     hipError_t e = hipSuccess;
     int tok;
     timed_begin(ctx, "fused_query", s, &tok);
@@ -551,7 +683,7 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *a
     if (e != hipSuccess || !perm) return e;
     timed_begin(ctx, "query_unstage", s, &tok);
     hipLaunchKernelGGL(k_query_unstage, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, inv,
-                       stage, lobes, pdf, sdir, spdf);
+                       stage, lobes, pdf, sdir, spdf, sel);
     timed_end(ctx, tok, s);
     return hipGetLastError();
 }
@@ -559,7 +691,7 @@ hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *a
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                           const float *dir, const float *rad, const float *spdf, float *grad,
                           double *loss_out, const uint32_t *perm, const float *rec,
-                          float *dg_tiles, const BinDesc *bins, hipStream_t s)
+                          float *dg_tiles, const BinDesc *bins, hipStream_t s, const float *bsdf)
 {
     FusedArgs a = fused_args(ctx, n, pos);
     a.aux = aux;
@@ -573,6 +705,9 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
     a.partials = ctx->partials;
     a.invN = 1.0f / (float)n;
     a.dg_tiles = grad ? dg_tiles : nullptr;
+    a.wsel = selection_row(ctx, ctx->params);
+    a.bsdf = bsdf;
+    a.partials_sel = ctx->partials + kPartials / 2;
     hipError_t e = hipSuccess;
     int tok;
     timed_begin(ctx, "fused_backward", s, &tok);
@@ -620,8 +755,10 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (loss_out) return launch_reduce_scaled(ctx->partials, blocks, 1.0 / (double)n, loss_out, s);
-    return hipSuccess;
+    if (!loss_out) return hipSuccess;
+    e = launch_reduce_scaled(ctx->partials, blocks, 1.0 / (double)n, loss_out, s);
+    if (e != hipSuccess || !(bsdf && a.wsel)) return e;
+    return launch_reduce_scaled(a.partials_sel, blocks, 1.0 / (double)n, loss_out + 1, s);
 }
 
 }  // namespace npm

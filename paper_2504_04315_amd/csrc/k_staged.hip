@@ -423,35 +423,6 @@ __global__ __launch_bounds__(256) void k_head(int64_t n, const float *__restrict
 }
 
 // ============================================================= loss gradient
-// Selection term of one sample (the learned selection probability): the
-// renderer's one-sample density is p_c = c p_bsdf + (1 - c) V, c = sigmoid(c');
-// with V held fixed, d(-(w/N) log p_c)/dc' = g c (1 - c) (p_bsdf - V) / p_c,
-// g = -w/N.  With t = log p_bsdf - log V and c / (1 - c) = e^c' this is
-//   t <= 0:  g c expm1(t) sigmoid(-(c' + t)),
-//   t > 0:   g (1 - c) (-expm1(-t)) sigmoid(c' + t),
-// and log p_c = log V - softplus(c') + softplus(c' + t) (t <= 0), or
-// log p_bsdf - softplus(-c') + softplus(-c' - t) (t > 0): no cancellation,
-// no division, and p_bsdf = 0 (t = -inf) gives -g c and log V + log(1 - c).
-// Writes the derivative and returns log p_c.
-__device__ __forceinline__ float softplusf(float x)
-{
-    return x > 0.0f ? x + log1pf(expf(-x)) : log1pf(expf(x));
-}
-
-__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
-
-__device__ __forceinline__ float select_term(float cp, float pb, float lv, float g, float &ds)
-{
-    const float lp = logf(pb);
-    const float t = lp - lv;
-    if (t <= 0.0f) {
-        ds = g * sigmoidf(cp) * expm1f(t) * sigmoidf(-(cp + t));
-        return lv - softplusf(cp) + softplusf(cp + t);
-    }
-    ds = g * sigmoidf(-cp) * -expm1f(-t) * sigmoidf(cp + t);
-    return lp - softplusf(-cp) + softplusf(-cp - t);
-}
-
 // draw[kOut (+1)][n] = d loss / d raw, loss partial sums of -w log V in FP64.
 // sel: the network has the selection output (draw row kOut is written: the
 // selection term's derivative where bsdf is given and the sample's density
@@ -633,15 +604,6 @@ struct MlpBwd {
                            ctx->mlp_img + m.fwd_elems, elems, draw, acts, delta, dG, wsel);
     }
 };
-
-// The selection row of the last layer within the flat parameters `flat`, or
-// null when the network has no selection output.
-static const float *selection_row(const npm_ctx *ctx, const float *flat)
-{
-    const npm_layout &L = ctx->net.lay;
-    if (!ctx->net.cfg.learn_selection) return nullptr;
-    return flat + L.layer_offset[L.n_layers - 1] + (int64_t)kOut * ctx->net.mlp.width;
-}
 
 static int tile_blocks(int64_t n)
 {

@@ -133,6 +133,16 @@ inline Weights query_weights(const npm_ctx *c)
     return c->ema ? Weights{c->ema, c->ema_grid16, c->ema_img, c->ema_img16} : trained_weights(c);
 }
 
+// The selection row of the last layer within the flat parameters `flat`
+// (width FP32 weights after the output layer's 4K rows), or null when the
+// network has no selection output.
+inline const float *selection_row(const npm_ctx *c, const float *flat)
+{
+    const npm_layout &L = c->net.lay;
+    if (!c->net.cfg.learn_selection) return nullptr;
+    return flat + L.layer_offset[L.n_layers - 1] + (int64_t)kOut * c->net.mlp.width;
+}
+
 // ---------------------------------------------------------------- launchers
 // All return hipSuccess or the first launch error.  `s` is the stream.
 struct Launch {
@@ -248,13 +258,15 @@ bool fused_shape_supported(const Net &net);
 hipError_t fused_query(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                        const float *dir, uint64_t seed, uint32_t stream_id, float *lobes,
                        float *pdf, float *sdir, float *spdf, const uint32_t *perm,
-                       const uint32_t *inv, const float *rec, float *stage, hipStream_t s);
+                       const uint32_t *inv, const float *rec, float *stage, hipStream_t s,
+                       float *sel = nullptr);
 // perm (optional): the order in which to visit the vertices; dg_tiles: the
 // per-tile dG buffer (required when grad is set); bins (optional): the levels
 // to scatter through the binned pass, with the context's bin buffers
 hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                           const float *dir, const float *rad, const float *spdf, float *grad,
                           double *loss_out, const uint32_t *perm, const float *rec,
-                          float *dg_tiles, const BinDesc *bins, hipStream_t s);
+                          float *dg_tiles, const BinDesc *bins, hipStream_t s,
+                          const float *bsdf = nullptr);
 
 }  // namespace npm

@@ -98,8 +98,6 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     if (!(c.ema_decay >= 0.0f && c.ema_decay < 1.0f)) return bad("ema_decay must be in [0, 1)");
     if (c.sh_degree < 0 || c.sh_degree > 4) return bad("sh_degree must be 0..4");
     if (c.learn_selection != 0 && c.learn_selection != 1) return bad("learn_selection must be 0 or 1");
-    if (c.learn_selection && c.exec_mode != NPM_EXEC_STAGED)
-        return bad("the learned selection probability runs on the staged path (NPM_EXEC_STAGED)");
     if (c.sh_degree > 0 && c.exec_mode == NPM_EXEC_FUSED &&
         !((c.sh_degree == 4 && c.n_levels * c.feat_per_level == 32) ||
           (c.sh_degree == 2 && c.n_levels * c.feat_per_level == 4)))
@@ -191,6 +189,11 @@ npm_status npm::describe(const npm_config *cfg, Net *net, std::string *err)
     const int64_t lowp_grid = c.precision == NPM_PREC_BF16 ? 2 * L.grid_params : 0;
     L.device_bytes = 16 * L.n_params + 6 * img + 4 * m.rm_elems + (int64_t)kPartials * 8 + 64 + lowp_grid +
                      (c.ema_decay > 0.0f ? 4 * L.n_params + 6 * img + lowp_grid : 0);
+    if (c.exec_mode == NPM_EXEC_FUSED && c.learn_selection && !fused_shape_supported(n))
+        return bad("no fused kernels with the selection output for this network shape (fused: "
+                   "radiance-based, as (F, inputs, hidden width x layers): (2, <= 16, <= 32 x 2), "
+                   "(4, <= 16, 33..64 x 2), (4, 17..32, 33..64 x 2), (2, 17..32, 33..64 x 3)); "
+                   "the staged path takes any shape");
     if (c.exec_mode == NPM_EXEC_FUSED && !fused_shape_supported(n))
         return bad("no fused kernels for this network shape (fused: F 1, 2 or 4; 16 or 32 grid "
                    "features; hidden width 32 (16 inputs, 2 hidden layers) or 64 (2 or 3 hidden "
@@ -455,6 +458,42 @@ npm_status npm_query(npm_ctx *ctx, int64_t n, const float *pos, const float *dir
                          sample_pdf, stream);
 }
 
+// The query of npm_query_aux and npm_query_select (sel: the selection
+// probability, selection networks only).
+static npm_status query_impl(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
+                             const float *dir, uint64_t rng_seed, uint32_t rng_stream,
+                             float *lobes, float *pdf, float *sample_dir, float *sample_pdf,
+                             float *sel, hipStream_t s)
+{
+    const bool any = lobes || pdf || sample_dir || sample_pdf || sel;
+    try {
+        if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
+            const uint32_t *perm = nullptr;
+            if (use_order(ctx, n, true) && any) {
+                NPM_HIP(ensure_sort(ctx, n), "order scratch allocation");
+                NPM_HIP(ensure_qstage(ctx, n), "query staging allocation");
+                NPM_HIP(spatial_order(ctx, n, pos, aux, dir, nullptr, nullptr, ctx->s_perm,
+                                      ctx->s_inv, ctx->s_rec, ctx->s_cells, s), "spatial order");
+                perm = ctx->s_perm;
+            }
+            NPM_HIP(fused_query(ctx, n, pos, aux, dir, rng_seed, rng_stream, lobes, pdf,
+                                sample_dir, sample_pdf, perm, ctx->s_inv, ctx->s_rec,
+                                ctx->s_qstage, s, sel), "fused query");
+            return NPM_OK;
+        }
+        NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
+        const Weights w = query_weights(ctx);
+        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w, aux), "encode");
+        NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s, &w), "mlp forward");
+        if (any)
+            NPM_HIP(staged_head(ctx, n, ctx->s_raw, dir, rng_seed, rng_stream, lobes, pdf,
+                                sample_dir, sample_pdf, s, sel), "head");
+    } catch (...) {
+        return fail(NPM_ERR_HIP, "unexpected exception");
+    }
+    return NPM_OK;
+}
+
 npm_status npm_query_aux(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,
                          const float *dir, uint64_t rng_seed, uint32_t rng_stream, float *lobes,
                          float *pdf, float *sample_dir, float *sample_pdf, void *stream)
@@ -467,33 +506,8 @@ npm_status npm_query_aux(npm_ctx *ctx, int64_t n, const float *pos, const float 
                           (const void *)sample_dir, (const void *)sample_pdf})
         if (p && !aligned4(p)) return fail(NPM_ERR_INVALID_ARG, "misaligned buffer");
     if (n == 0) return NPM_OK;
-    hipStream_t s = (hipStream_t)stream;
-    try {
-        if (ctx->net.cfg.exec_mode == NPM_EXEC_FUSED) {
-            const uint32_t *perm = nullptr;
-            if (use_order(ctx, n, true) && (lobes || pdf || sample_dir || sample_pdf)) {
-                NPM_HIP(ensure_sort(ctx, n), "order scratch allocation");
-                NPM_HIP(ensure_qstage(ctx, n), "query staging allocation");
-                NPM_HIP(spatial_order(ctx, n, pos, aux, dir, nullptr, nullptr, ctx->s_perm,
-                                      ctx->s_inv, ctx->s_rec, ctx->s_cells, s), "spatial order");
-                perm = ctx->s_perm;
-            }
-            NPM_HIP(fused_query(ctx, n, pos, aux, dir, rng_seed, rng_stream, lobes, pdf,
-                                sample_dir, sample_pdf, perm, ctx->s_inv, ctx->s_rec,
-                                ctx->s_qstage, s), "fused query");
-            return NPM_OK;
-        }
-        NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
-        const Weights w = query_weights(ctx);
-        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w, aux), "encode");
-        NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s, &w), "mlp forward");
-        if (lobes || pdf || sample_dir || sample_pdf)
-            NPM_HIP(staged_head(ctx, n, ctx->s_raw, dir, rng_seed, rng_stream, lobes, pdf,
-                                sample_dir, sample_pdf, s), "head");
-    } catch (...) {
-        return fail(NPM_ERR_HIP, "unexpected exception");
-    }
-    return NPM_OK;
+    return query_impl(ctx, n, pos, aux, dir, rng_seed, rng_stream, lobes, pdf, sample_dir,
+                      sample_pdf, nullptr, (hipStream_t)stream);
 }
 
 static npm_status check_train(npm_ctx *ctx, int64_t n, const float *pos, const float *dir,
@@ -629,7 +643,7 @@ static npm_status backward_impl(npm_ctx *ctx, int64_t n, const float *pos, const
         if (binned) NPM_HIP(ensure_bins(ctx, bins), "bin scratch allocation");
         NPM_HIP(fused_backward(ctx, n, pos, aux, dir, rad, spdf, grad, loss_out, perm,
                                perm ? ctx->s_rec : nullptr, grad ? ctx->s_dgt : nullptr,
-                               binned ? &bins : nullptr, s),
+                               binned ? &bins : nullptr, s, bsdf),
                 "fused backward");
         return NPM_OK;
     }
@@ -799,7 +813,7 @@ npm_status npm_train_step_aux(npm_ctx *ctx, int64_t n, const float *pos, const f
 }
 
 // ---------------------------------------------------------------------------
-// Learned BSDF-selection probability (staged path)
+// Learned BSDF-selection probability
 static npm_status check_select(npm_ctx *ctx)
 {
     if (!ctx) return fail(NPM_ERR_INVALID_ARG, "null context");
@@ -823,19 +837,8 @@ npm_status npm_query_select(npm_ctx *ctx, int64_t n, const float *pos, const flo
                           (const void *)select_prob})
         if (p && !aligned4(p)) return fail(NPM_ERR_INVALID_ARG, "misaligned buffer");
     if (n == 0) return NPM_OK;
-    hipStream_t s = (hipStream_t)stream;
-    try {
-        NPM_HIP(ensure_scratch(ctx, n), "scratch allocation");
-        const Weights w = query_weights(ctx);
-        NPM_HIP(staged_encode(ctx, n, pos, ctx->s_G, s, &w, aux), "encode");
-        NPM_HIP(staged_mlp_fwd(ctx, n, ctx->s_G, nullptr, ctx->s_raw, s, &w), "mlp forward");
-        if (lobes || pdf || sample_dir || sample_pdf || select_prob)
-            NPM_HIP(staged_head(ctx, n, ctx->s_raw, dir, rng_seed, rng_stream, lobes, pdf,
-                                sample_dir, sample_pdf, s, select_prob), "head");
-    } catch (...) {
-        return fail(NPM_ERR_HIP, "unexpected exception");
-    }
-    return NPM_OK;
+    return query_impl(ctx, n, pos, aux, dir, rng_seed, rng_stream, lobes, pdf, sample_dir,
+                      sample_pdf, select_prob, (hipStream_t)stream);
 }
 
 static npm_status check_train_select(npm_ctx *ctx, int64_t n, const float *pos, const float *aux,

@@ -159,15 +159,23 @@ def test_selection_layout_matches_oracle(O, net):
 
 
 def test_selection_config_rules():
-    """The selection output runs on the staged path; the flag is 0 or 1; the
-    selection calls refuse a null context."""
+    """The selection output runs on the staged path for any shape and fused
+    for the shapes with kernels for it; the flag is 0 or 1; the selection
+    calls refuse a null context."""
+    from dataclasses import replace
     lib = B.lib()
     out = B.npm_layout()
-    c = B.make_config(W.TINYS)
-    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == 0
-    c.exec_mode = B.EXEC_FUSED
+    for net in (W.TINYS, W.CFG1S, W.PAPERS, replace(W.CFG2, select=True)):
+        for mode in (B.EXEC_STAGED, B.EXEC_FUSED):
+            c = B.make_config(net, exec_mode=mode)
+            assert lib.npm_get_layout(C.byref(c), C.byref(out)) == 0, (net, mode)
+    c = B.make_config(replace(W.TINYS, n_hidden=3), exec_mode=B.EXEC_FUSED)
     assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
-    assert b"staged path" in lib.npm_last_error()
+    assert b"selection output" in lib.npm_last_error()
+    c = B.make_config(replace(W.TINYS, sh_degree=2), exec_mode=B.EXEC_FUSED)
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1
+    c.exec_mode = B.EXEC_STAGED
+    assert lib.npm_get_layout(C.byref(c), C.byref(out)) == 0
     c = B.make_config(W.TINYS)
     c.learn_selection = 2
     assert lib.npm_get_layout(C.byref(c), C.byref(out)) == -1

@@ -1,6 +1,6 @@
-"""GPU parity of the learned BSDF-selection probability (the staged path's
-extra output; the Sec. 6.3 extension) against the FP64 oracle, through the
-C ABI.
+"""GPU parity of the learned BSDF-selection probability (the network's extra
+output; the Sec. 6.3 extension) against the FP64 oracle, through the C ABI,
+on the staged and the fused path.
 
 - Query: the raw outputs (4K + 1 rows) to their forward condition scale; the
   selection probability c = sigmoid(c') to the raw tolerance carried through
@@ -18,7 +18,12 @@ C ABI.
   output fail with NPM_ERR_STATE.
 - Sizes: the tiny net at a ragged 997, cfg1 at 16,384 + 17 (several tiles
   and a ragged tail), and the paper's network at its training batch, 2^18,
-  whole.
+  whole (fused: in spatial order); a spatially ordered fused query (staged
+  slots and the un-permute carry c).
+- The fused static backward (no allocation) on a selection network trains
+  the mixture only.
+- Precision form (fused BF16): the gradient's cosine with the oracle's
+  > 0.99 for the grid, the MLP and the selection row; c within 1e-2.
 """
 import math
 
@@ -31,6 +36,7 @@ from paper_2504_04315_amd import workload as W
 
 pytestmark = pytest.mark.gpu
 K = 8
+MODES = {"staged": B.EXEC_STAGED, "fused": B.EXEC_FUSED}
 
 
 @pytest.fixture(scope="module")
@@ -66,12 +72,7 @@ def selection_row(on):
     return slice(off, off + width)
 
 
-@pytest.mark.parametrize("net,n", [(W.TINYS, 997), (W.CFG1S, 16384 + 17)])
-def test_query_select_parity(O, torch, net, n):
-    model = B.NPM(B.make_config(net))
-    on = oracle_net(O, net)
-    params = randomize(model, on, np.random.default_rng(21), grid_sd=0.5)
-    b = W.make_batch("surface", n, seed=22)
+def check_query_select(O, torch, model, on, params, b, n, tag):
     pos, dirs = dev(torch, b.pos), dev(torch, b.dir)
     out = model.query_select(pos, dirs, seed=4, stream_id=2)
     plain = model.query(pos, dirs, seed=4, stream_id=2)
@@ -82,13 +83,36 @@ def test_query_select_parity(O, torch, net, n):
     q = O.query(on, b.pos, params, dirs=b.dir, seed=4, stream=2)
     rr, rs = O.mlp_forward(on, q["G"], params, with_scale=True)
     assert raw.shape == (n, 4 * K + 1)
-    msgs = [P.check_scaled("raw (with the selection logit)", raw, rr, rs)]
+    msgs = [P.check_scaled(f"{tag} raw (with the selection logit)", raw, rr, rs)]
     c = q["sel"]
     bound = P.RTOL * (c + c * (1 - c) * rs[:, 4 * K]) + 1e-30
-    msgs.append(P.assert_within("selection probability", out["select_prob"].cpu().numpy(), c,
-                                bound))
+    msgs.append(P.assert_within(f"{tag} selection probability", out["select_prob"].cpu().numpy(),
+                                c, bound))
     assert 0.05 < np.median(c) < 0.95 and c.std() > 0.01    # a spread of probabilities
-    print("\n".join(msgs))
+    return msgs
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+@pytest.mark.parametrize("net,n", [(W.TINYS, 997), (W.CFG1S, 16384 + 17)])
+def test_query_select_parity(O, torch, net, n, mode):
+    model = B.NPM(B.make_config(net, exec_mode=MODES[mode]))
+    on = oracle_net(O, net)
+    params = randomize(model, on, np.random.default_rng(21), grid_sd=0.5)
+    b = W.make_batch("surface", n, seed=22)
+    print("\n".join(check_query_select(O, torch, model, on, params, b, n, mode)))
+    model.close()
+
+
+def test_query_select_spatial_order(O, torch):
+    """A fused query in spatial order: c goes through the staged slots and the
+    un-permute like the other outputs."""
+    net = W.PAPERS
+    model = B.NPM(B.make_config(net, exec_mode=B.EXEC_FUSED, batch_order=B.ORDER_SPATIAL))
+    on = oracle_net(O, net)
+    params = randomize(model, on, np.random.default_rng(31), grid_sd=0.5)
+    n = 40001
+    b = W.make_batch("surface", n, seed=32)
+    print("\n".join(check_query_select(O, torch, model, on, params, b, n, "ordered")))
     model.close()
 
 
@@ -115,15 +139,17 @@ def check_backward_select(O, torch, model, on, params, batch, bsdf, tag):
     return msgs, g, ref
 
 
+@pytest.mark.parametrize("mode", ["staged", "fused"])
 @pytest.mark.parametrize("net,n", [(W.TINYS, 997), (W.CFG1S, 16384 + 17)])
-def test_backward_select_parity(O, torch, net, n):
-    model = B.NPM(B.make_config(net))
+def test_backward_select_parity(O, torch, net, n, mode):
+    model = B.NPM(B.make_config(net, exec_mode=MODES[mode]))
     on = oracle_net(O, net)
     params = randomize(model, on, np.random.default_rng(23), grid_sd=0.5)
     batch = W.make_batch("surface", n, seed=24)
     bsdf = W.make_bsdf(batch, 24)
     assert np.mean(bsdf == 0) > 0.05                # zero densities are part of the case
-    msgs, _, _ = check_backward_select(O, torch, model, on, params, batch, bsdf, net_name(net))
+    msgs, _, _ = check_backward_select(O, torch, model, on, params, batch, bsdf,
+                                       f"{mode} {net_name(net)}")
     print("\n".join(msgs))
     model.close()
 
@@ -132,26 +158,29 @@ def net_name(net):
     return {W.TINYS: "tiny", W.CFG1S: "cfg1", W.PAPERS: "paper"}[net]
 
 
-def test_backward_select_paper_training_batch(O, torch):
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_backward_select_paper_training_batch(O, torch, mode):
     """The paper's network with the selection output at its training batch
     (2^18 vertices, surface samples), the launch configuration the benchmark
-    times: every gradient entry and both losses."""
-    model = B.NPM(B.make_config(W.PAPERS))
+    times (fused: spatially ordered): every gradient entry and both losses."""
+    model = B.NPM(B.make_config(W.PAPERS, exec_mode=MODES[mode]))
     on = oracle_net(O, W.PAPERS)
     params = randomize(model, on, np.random.default_rng(25), grid_sd=0.5)
     batch = W.make_batch("surface", W.N_PAPER_TRAIN, seed=26)
     bsdf = W.make_bsdf(batch, 26)
-    msgs, _, _ = check_backward_select(O, torch, model, on, params, batch, bsdf, "paper 2^18")
+    msgs, _, _ = check_backward_select(O, torch, model, on, params, batch, bsdf,
+                                       f"{mode} paper 2^18")
     print("\n".join(msgs))
     model.close()
 
 
-def test_train_step_select_against_oracle(O, torch):
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_train_step_select_against_oracle(O, torch, mode):
     """npm_train_step_select = backward (both terms) + Adam, over three steps,
     each from the GPU's own state; the bound adds the Adam update's spread
     when the gradient moves within its parity tolerance."""
     net = W.TINYS
-    model = B.NPM(B.make_config(net))
+    model = B.NPM(B.make_config(net, exec_mode=MODES[mode]))
     on = oracle_net(O, net)
     f = lambda x: float(np.float32(x))
     hp = dict(lr=f(net.lr), beta1=f(net.beta1), beta2=f(net.beta2), eps=f(net.eps))
@@ -180,14 +209,15 @@ def test_train_step_select_against_oracle(O, torch):
         assert st[2] == pytest.approx(float(np.sum(ref["grad"] ** 2)), rel=1e-4)
         p_gpu = model.get_state().astype(np.float64)
         bound = 1e-5 * np.abs(outs[0]) + np.abs(outs[1] - outs[2]) + 1e-9 * hp["lr"]
-        print(P.assert_within(f"selection train step {t} params", p_gpu, outs[0], bound))
+        print(P.assert_within(f"{mode} selection train step {t} params", p_gpu, outs[0], bound))
         assert model.step == t
     model.close()
 
 
-def test_plain_calls_train_the_mixture_only(O, torch):
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_plain_calls_train_the_mixture_only(O, torch, mode):
     net = W.TINYS
-    model = B.NPM(B.make_config(net))
+    model = B.NPM(B.make_config(net, exec_mode=MODES[mode]))
     on = oracle_net(O, net)
     params = randomize(model, on, np.random.default_rng(27), grid_sd=0.5)
     b = W.make_batch("cube", 777, seed=28)
@@ -199,21 +229,36 @@ def test_plain_calls_train_the_mixture_only(O, torch):
     ref = O.backward(on, b.pos, b.dir, b.radiance, b.pdf, params)
     cond = O.backward_cond(on, b.pos, b.dir, b.radiance, b.pdf, params)
     g = grad.cpu().numpy().astype(np.float64)
-    print(P.check_grads("mixture-only grad", g, ref["grad"], cond))
+    print(P.check_grads(f"{mode} mixture-only grad", g, ref["grad"], cond))
     assert np.all(g[selection_row(on)] == 0.0)
     assert float(loss.cpu()[0]) == pytest.approx(ref["loss"], rel=1e-5)
+    if mode == "fused":
+        # the static entry point (no allocation) after a selection call: the
+        # block partials of the selection row are rewritten, not left over
+        model.backward_select(dev(torch, b.pos), dev(torch, b.dir), dev(torch, b.radiance),
+                              dev(torch, b.pdf), dev(torch, W.make_bsdf(b, 28)),
+                              grad=torch.zeros_like(grad))
+        g2 = torch.zeros_like(grad)
+        model.backward_static(dev(torch, b.pos), dev(torch, b.dir), dev(torch, b.radiance),
+                              dev(torch, b.pdf), grad=g2)
+        torch.cuda.synchronize()
+        g2 = g2.cpu().numpy().astype(np.float64)
+        print(P.check_grads("static mixture-only grad", g2, ref["grad"], cond))
+        assert np.all(g2[selection_row(on)] == 0.0)
     model.close()
 
 
-def test_select_edge_cases(O, torch):
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_select_edge_cases(O, torch, mode):
     net = W.TINYS
-    model = B.NPM(B.make_config(net))
+    model = B.NPM(B.make_config(net, exec_mode=MODES[mode]))
     on = oracle_net(O, net)
     params = randomize(model, on, np.random.default_rng(29), grid_sd=0.5)
     b = W.make_batch("cube", 64, seed=30)
     bsdf = W.make_bsdf(b, 30)
     bsdf[:8] = [np.inf, np.nan, -1.0, -np.inf, -0.0, 0.0, 1e-40, 3e38]
-    msgs, _, _ = check_backward_select(O, torch, model, on, params, b, bsdf, "edge densities")
+    msgs, _, _ = check_backward_select(O, torch, model, on, params, b, bsdf,
+                                       f"{mode} edge densities")
     print("\n".join(msgs))
     # n = 0 is a no-op
     empty = torch.zeros((3, 0), device="cuda")
@@ -236,3 +281,40 @@ def test_select_edge_cases(O, torch):
                                 dev(torch, b.pdf), dev(torch, bsdf))
     assert ei.value.status == -6
     plain.close()
+
+
+def test_select_precision_form(O, torch):
+    """The fused precision form (BF16 MLP, FP16 grid) with the selection
+    output, at the paper's training batch: gradient cosine with the oracle's
+    (grid, MLP, selection row) > 0.99, both losses within 1e-2 relative, and
+    the selection probability of a query within 1e-2."""
+    net = W.PAPERS
+    model = B.NPM(B.make_config(net, exec_mode=B.EXEC_FUSED, precision="bf16"))
+    on = oracle_net(O, net)
+    params = model.get_state().astype(np.float64)
+    batch = W.make_batch("surface", W.N_PAPER_TRAIN, seed=33)
+    bsdf = W.make_bsdf(batch, 33)
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(on.n_params, dtype=torch.float32, device="cuda")
+    model.backward_select(dev(torch, batch.pos), dev(torch, batch.dir), dev(torch, batch.radiance),
+                          dev(torch, batch.pdf), dev(torch, bsdf), grad=grad, loss=loss)
+    q = model.query_select(dev(torch, batch.pos[:, :4096]), None, lobes=False, sample=False)
+    torch.cuda.synchronize()
+    ref = O.backward(on, batch.pos, batch.dir, batch.radiance, batch.pdf, params, bsdf=bsdf,
+                     with_abs=False)
+    g = grad.cpu().numpy().astype(np.float64)
+    gp, row = on.grid_params, selection_row(on)
+    for name, sl in (("grid", slice(0, gp)), ("mlp", slice(gp, None)), ("selection row", row)):
+        a, r = g[sl], ref["grad"][sl]
+        cs = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
+        print(f"bf16 selection gradient cosine ({name}): {cs:.6f}")
+        assert cs > 0.99, (name, cs)
+    lv = loss.cpu().numpy()
+    for got, want, name in ((lv[0], ref["loss"], "loss"), (lv[1], ref["loss_sel"], "loss_sel")):
+        print(f"bf16 {name} {got:.7f} vs oracle {want:.7f}")
+        assert abs(got - want) <= 1e-2 * abs(want), name
+    c = O.query(on, batch.pos[:, :4096], params)["sel"]
+    err = np.abs(q["select_prob"].cpu().numpy() - c)
+    print(f"bf16 selection probability: max abs err {err.max():.2e}")
+    assert err.max() <= 1e-2
+    model.close()
