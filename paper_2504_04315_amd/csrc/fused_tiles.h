@@ -806,22 +806,44 @@ __device__ __forceinline__ void tile_input(const GridView &gv, const TrainIO &io
 // Layers are numbered 0 (the first, IN0 inputs) to NH (the output layer, 32
 // outputs); the phases run from NH down to 0, and the dW blocks are numbered
 // in that order, block g belonging to wave g % WV in its slot g / WV.
-template <int IN_P, int HID_P, int NH, int WV>
+template <int IN_P, int HID_P, int NH, int WV, bool SPLIT = true>
 struct BlockPlan {
     static constexpr int IN0 = IN_P < 32 ? 32 : IN_P;
     static constexpr int out_p(int L) { return L == NH ? 32 : HID_P; }
     static constexpr int in_p(int L) { return L == 0 ? IN0 : HID_P; }
     static constexpr int nbi(int L) { return in_p(L) / 32; }
     static constexpr int blocks(int L) { return (out_p(L) / 32) * nbi(L); }
-    // the first block of layer L in phase order
+    // A phase's work items: its blocks, each split into parts(L) ranges of
+    // the round's vertices when whole blocks would leave waves idle at the
+    // phase's barrier (2 blocks on 4 waves: 4 halves); item it = b parts + p
+    static constexpr int parts(int L)
+    {
+        return !SPLIT || blocks(L) % WV == 0 ? 1 : (2 * blocks(L)) % WV == 0 ? 2 : 1;
+    }
+    static constexpr int items(int L) { return blocks(L) * parts(L); }
+    // the first item of layer L in phase order
     static constexpr int first(int L)
     {
         int g = 0;
-        for (int l = NH; l > L; --l) g += blocks(l);
+        for (int l = NH; l > L; --l) g += items(l);
         return g;
     }
     static constexpr int total() { return first(-1); }
     static constexpr int slots() { return (total() + WV - 1) / WV; }
+    // blocks split into parts before layer L in phase order (their partial
+    // sums meet in LDS at the end, 1,024 floats each)
+    static constexpr int split_before(int L)
+    {
+        int c = 0;
+        for (int l = NH; l > L; --l) c += parts(l) > 1 ? blocks(l) : 0;
+        return c;
+    }
+    static constexpr int splits() { return split_before(-1); }
+    // the split blocks' partial sums fit in the exchange buffer
+    static constexpr bool scratch_fits(bool bf)
+    {
+        return splits() * 4096 <= max_rows() * xs(bf) * (bf ? 2 : 4);
+    }
     // rows of the exchange buffer in phase L: the deltas, then the inputs
     static constexpr int rows(int L) { return out_p(L) + in_p(L); }
     // with the selection output, the output layer's phase also carries the
@@ -870,17 +892,18 @@ __device__ __forceinline__ void xch_put(XT *xb, int row0, int wave, const float 
     for (int a = 0; a < REGS; ++a) p[nf(h, a) * XS] = XT(v[a]);
 }
 
-// acc (a 32x32 dW block) += sum over the round's KV vertices of
-// delta[ro + row] input[ri + col], rows of the exchange buffer.  FP32:
-// 32x32x2 steps, the half-wave h supplying the vertices [KV/2 h, KV/2 (h+1))
-// in order, four per 16-byte read.  BF16: 32x32x16 steps, half h supplying
-// the vertices 16 s + 8 h + e.
+// acc (a 32x32 dW block) += sum over KV of the round's vertices, from column
+// c0 on, of delta[ro + row] input[ri + col], rows of the exchange buffer.
+// FP32: 32x32x2 steps, the half-wave h supplying the vertices
+// c0 + [KV/2 h, KV/2 (h+1)) in order, four per 16-byte read.  BF16: 32x32x16
+// steps, half h supplying the vertices c0 + 16 s + 8 h + e.
 template <int KV, int XS>
-__device__ __forceinline__ void dw_block(const float *xb, int ro, int ri, f32x16 &acc, int lane)
+__device__ __forceinline__ void dw_block(const float *xb, int ro, int ri, int c0, f32x16 &acc,
+                                         int lane)
 {
     const int i = lane & 31, h = lane >> 5;
-    const float *pa = xb + (ro + i) * XS + (KV / 2) * h;
-    const float *pb = xb + (ri + i) * XS + (KV / 2) * h;
+    const float *pa = xb + (ro + i) * XS + c0 + (KV / 2) * h;
+    const float *pb = xb + (ri + i) * XS + c0 + (KV / 2) * h;
 #pragma unroll
     for (int q = 0; q < KV / 8; ++q) {
         const f32x4 A = *reinterpret_cast<const f32x4 *>(pa + 4 * q);
@@ -890,11 +913,12 @@ __device__ __forceinline__ void dw_block(const float *xb, int ro, int ri, f32x16
     }
 }
 template <int KV, int XS>
-__device__ __forceinline__ void dw_block(const __bf16 *xb, int ro, int ri, f32x16 &acc, int lane)
+__device__ __forceinline__ void dw_block(const __bf16 *xb, int ro, int ri, int c0, f32x16 &acc,
+                                         int lane)
 {
     const int i = lane & 31, h = lane >> 5;
-    const __bf16 *pa = xb + (ro + i) * XS + 8 * h;
-    const __bf16 *pb = xb + (ri + i) * XS + 8 * h;
+    const __bf16 *pa = xb + (ro + i) * XS + c0 + 8 * h;
+    const __bf16 *pb = xb + (ri + i) * XS + c0 + 8 * h;
 #pragma unroll
     for (int s = 0; s < KV / 16; ++s) {
         const bf16x8 A = *reinterpret_cast<const bf16x8 *>(pa + 16 * s);
@@ -904,7 +928,7 @@ __device__ __forceinline__ void dw_block(const __bf16 *xb, int ro, int ri, f32x1
 }
 
 // Phase L of a round: put this wave's deltas dz and layer inputs hin into the
-// exchange buffer; after the barrier accumulate this wave's dW blocks of the
+// exchange buffer; after the barrier accumulate this wave's dW items of the
 // layer.  The caller runs the next chain step between this and the barrier
 // that ends the phase.
 template <class Plan, int L, int WV, int XS, typename XT, int NS>
@@ -912,42 +936,70 @@ __device__ __forceinline__ void dw_phase(XT *xb, const float *dz, const float *h
                                          f32x16 (&acc)[NS], int lane)
 {
     constexpr int OUT = Plan::out_p(L), IN = Plan::in_p(L);
+    constexpr int P = Plan::parts(L), KV = 32 * WV / P;
     xch_put<OUT / 2, XS>(xb, 0, wave, dz, lane);
     xch_put<IN / 2, XS>(xb, OUT, wave, hin, lane);
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < Plan::blocks(L); ++b) {
+    for (int it = 0; it < Plan::items(L); ++it) {
         constexpr int g0 = Plan::first(L);
-        if ((g0 + b) % WV == wave) {
+        if ((g0 + it) % WV == wave) {
+            const int b = it / P, p = it % P;
             const int bo = b / Plan::nbi(L), bi = b % Plan::nbi(L);
-            dw_block<32 * WV, XS>(xb, 32 * bo, OUT + 32 * bi, acc[(g0 + b) / WV], lane);
+            dw_block<KV, XS>(xb, 32 * bo, OUT + 32 * bi, KV * p, acc[(g0 + it) / WV], lane);
         }
     }
 }
 
-// This wave's dW blocks into the flat layout of the MLP weights at dst
-// (entries outside the real shapes dropped): stored, or with ATOMIC added by
-// FP32 atomics (several blocks add into one buffer).
+// This block's weight gradients into the flat layout of the MLP weights at
+// dst (entries outside the real shapes dropped): stored, or with ATOMIC added
+// by FP32 atomics (several blocks add into one buffer).  The parts of a split
+// block meet in LDS first: the owners of parts p > 0 leave theirs in `scr`
+// (free LDS, 4 KB per split block), and the owner of part 0 adds them and
+// writes.  Every thread of the block calls it (two barriers).
 template <class Plan, int NH, int WV, bool ATOMIC = false, int NS>
 __device__ __forceinline__ void dw_write(float *dst, int n_in, int width, int wave,
-                                         f32x16 (&acc)[NS], int lane)
+                                         f32x16 (&acc)[NS], int lane, float *scr)
 {
     const int h = lane >> 5, j = lane & 31;
+    if constexpr (Plan::splits() > 0) {
+        __syncthreads();                 // the exchange buffer is free
+        static_for_down<NH, 0>([&](auto LC) {
+            constexpr int L = decltype(LC)::value;
+            constexpr int P = Plan::parts(L);
+            if constexpr (P > 1) {
+#pragma unroll
+                for (int it = 0; it < Plan::items(L); ++it) {
+                    const int g = Plan::first(L) + it;
+                    if (it % P == 0 || g % WV != wave) continue;
+                    float *s = scr + (Plan::split_before(L) + it / P) * 1024;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) s[r * 64 + lane] = acc[g / WV][r];
+                }
+            }
+        });
+        __syncthreads();
+    }
     static_for_down<NH, 0>([&](auto LC) {
         constexpr int L = decltype(LC)::value;
+        constexpr int P = Plan::parts(L);
         const int out_r = L == NH ? 32 : width, in_r = L == 0 ? n_in : width;
         float *d = dst + (L == 0 ? 0 : width * n_in + (L - 1) * width * width);
 #pragma unroll
-        for (int b = 0; b < Plan::blocks(L); ++b) {
-            const int g = Plan::first(L) + b;
-            if (g % WV != wave) continue;
+        for (int it = 0; it < Plan::items(L); ++it) {
+            const int g = Plan::first(L) + it;
+            if (it % P != 0 || g % WV != wave) continue;
+            const int b = it / P;
             const int bo = b / Plan::nbi(L), bi = b % Plan::nbi(L);
+            const float *s = scr + (Plan::split_before(L) + b) * 1024;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
+                float v = acc[g / WV][r];
+                if constexpr (P > 1) v += s[r * 64 + lane];
                 const int row = 32 * bo + nf(h, r), col = 32 * bi + j;
                 if (row < out_r && col < in_r) {
-                    if constexpr (ATOMIC) unsafeAtomicAdd(d + row * in_r + col, acc[g / WV][r]);
-                    else d[row * in_r + col] = acc[g / WV][r];
+                    if constexpr (ATOMIC) unsafeAtomicAdd(d + row * in_r + col, v);
+                    else d[row * in_r + col] = v;
                 }
             }
         }

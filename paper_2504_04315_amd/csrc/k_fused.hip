@@ -155,7 +155,9 @@ template <int IN_P, int HID_P, int NH, int F, bool BF, int PG, int WV, bool SEL 
 __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp_weights,
                                                            int tiles_per_block, int img_bytes)
 {
-    using Plan = BlockPlan<IN_P, HID_P, NH, WV>;
+    // the selection instantiations keep whole blocks: the split's extra
+    // accumulator would not fit beside the selection sums in FP32
+    using Plan = BlockPlan<IN_P, HID_P, NH, WV, !SEL>;
     using XT = typename std::conditional<BF, __bf16, float>::type;
     constexpr int IN0 = Plan::IN0;
     constexpr int XS = Plan::xs(BF);
@@ -347,8 +349,9 @@ __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp
         if (threadIdx.x == 0) a.partials_sel[blockIdx.x] = red[0];
     }
     if (!a.grad) return;
+    static_assert(Plan::scratch_fits(BF), "split blocks' sums fit in the exchange buffer");
     dw_write<Plan, NH, WV>(a.dw_part + (int64_t)blockIdx.x * mlp_weights, a.n_in, a.width, wave,
-                           acc, lane);
+                           acc, lane, reinterpret_cast<float *>(xb));
     if constexpr (SEL) {
         // the selection row (after the output layer's 32 rows): the waves' sums
         __syncthreads();

@@ -130,6 +130,7 @@ __global__ __launch_bounds__(256) void k_serve_train(RoundHdr *hdr, const DevReq
     constexpr int XS = Plan::xs(true);
     constexpr int NS = Plan::slots();
     constexpr int WIN_PTS = (HID_P - IN0) * kStride / (2 * F);
+    static_assert(Plan::scratch_fits(true), "split blocks' sums fit in the exchange buffer");
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ uint32_t s_off[NPM_MAX_LEVELS];
     __shared__ int s_res[NPM_MAX_LEVELS];
@@ -156,7 +157,8 @@ __global__ __launch_bounds__(256) void k_serve_train(RoundHdr *hdr, const DevReq
         if (r != cur) {
             if (cur >= 0) {
                 const DevReq &c = reqs[cur];
-                dw_write<Plan, NH, WV, true>(c.grad + c.mlp_off, c.n_in, c.width, wave, acc, lane);
+                dw_write<Plan, NH, WV, true>(c.grad + c.mlp_off, c.n_in, c.width, wave, acc, lane,
+                                             reinterpret_cast<float *>(xb));
 #pragma unroll
                 for (int k = 0; k < NS; ++k)
 #pragma unroll
