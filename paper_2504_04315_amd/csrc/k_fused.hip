@@ -155,9 +155,10 @@ template <int IN_P, int HID_P, int NH, int F, bool BF, int PG, int WV, bool SEL 
 __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp_weights,
                                                            int tiles_per_block, int img_bytes)
 {
-    // the selection instantiations keep whole blocks: the split's extra
-    // accumulator would not fit beside the selection sums in FP32
-    using Plan = BlockPlan<IN_P, HID_P, NH, WV, !SEL>;
+    // the FP32 selection instantiation of the three-hidden-layer network
+    // keeps whole blocks: there the split's extra accumulator would not fit
+    // beside the selection sums (it would spill)
+    using Plan = BlockPlan<IN_P, HID_P, NH, WV, !(SEL && !BF && NH >= 3)>;
     using XT = typename std::conditional<BF, __bf16, float>::type;
     constexpr int IN0 = Plan::IN0;
     constexpr int XS = Plan::xs(BF);
