@@ -718,6 +718,7 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
     NPM_FUSED_RUN(run_backward);
     timed_end(ctx, tok, s);
     if (e != hipSuccess) return e;
+    const int blocks = backward_blocks(n);
     if (grad) {
         const int64_t tiles = (n + 31) / 32;
         const int64_t waves = std::min<int64_t>(tiles, 4096);
@@ -726,12 +727,24 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
         if (bins)
             for (int j = 0; j < bins->nb; ++j) skip |= 1u << bins->lv[j];
         const uint32_t all = ctx->net.grid.n_levels >= 32 ? ~0u : (1u << ctx->net.grid.n_levels) - 1u;
+        // The windowed scatter and the weight-gradient sum write other parts
+        // of the gradient than the binned scatter and read only the per-tile
+        // dG: with bins they run on the side stream, beside the binned passes
+        // (which leave CUs idle in their scan and in the reduce's last wave of
+        // blocks), and the caller's stream waits for both.
+        hipStream_t s2 = s;
+        if (bins) {
+            s2 = ctx->side;
+            e = hipEventRecord(ctx->ev_fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s2, ctx->ev_fork, 0);
+            if (e != hipSuccess) return e;
+        }
         if (skip != all) {
-            timed_begin(ctx, "fused_scatter", s, &tok);
+            timed_begin(ctx, "fused_scatter", s2, &tok);
             const bool fixed = ctx->net.cfg.precision == NPM_PREC_BF16;
             const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
-#define NPM_SCATTER_LAUNCH(FV, WT)                                                                \
-    hipLaunchKernelGGL((k_scatter_tiles<FV, WT>), grid, block, 0, s, ctx->net.grid, n, pos, perm, \
+#define NPM_SCATTER_LAUNCH(FV, WT)                                                                 \
+    hipLaunchKernelGGL((k_scatter_tiles<FV, WT>), grid, block, 0, s2, ctx->net.grid, n, pos, perm, \
                        rec, a.rec_stride, dg_tiles, rows, grad, skip)
             switch (ctx->net.grid.feat) {
             case 1: if (fixed) NPM_SCATTER_LAUNCH(1, int); else NPM_SCATTER_LAUNCH(1, double); break;
@@ -739,25 +752,24 @@ hipError_t fused_backward(npm_ctx *ctx, int64_t n, const float *pos, const float
             default: if (fixed) NPM_SCATTER_LAUNCH(4, int); else NPM_SCATTER_LAUNCH(4, double); break;
             }
 #undef NPM_SCATTER_LAUNCH
-            timed_end(ctx, tok, s);
+            timed_end(ctx, tok, s2);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
+        const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
+        timed_begin(ctx, "fused_dw_sum", s2, &tok);
+        hipLaunchKernelGGL(k_dw_sum, dim3((count + 15) / 16), dim3(256), 0, s2, ctx->s_dw_part,
+                           blocks, count, grad + ctx->net.lay.grid_params);
+        timed_end(ctx, tok, s2);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
         if (bins) {
             e = binned_scatter(ctx, *bins, n, pos, perm, rec, a.rec_stride, dg_tiles, rows, grad,
                                ctx->s_bin_cnt, ctx->s_bin_items, s);
+            if (e == hipSuccess) e = hipEventRecord(ctx->ev_join, s2);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->ev_join, 0);
             if (e != hipSuccess) return e;
         }
-    }
-    const int blocks = backward_blocks(n);
-    if (grad) {
-        const int count = (int)(ctx->net.lay.n_params - ctx->net.lay.grid_params);
-        timed_begin(ctx, "fused_dw_sum", s, &tok);
-        hipLaunchKernelGGL(k_dw_sum, dim3((count + 15) / 16), dim3(256), 0, s, ctx->s_dw_part,
-                           blocks, count, grad + ctx->net.lay.grid_params);
-        timed_end(ctx, tok, s);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
     }
     if (!loss_out) return hipSuccess;
     e = launch_reduce_scaled(ctx->partials, blocks, 1.0 / (double)n, loss_out, s);

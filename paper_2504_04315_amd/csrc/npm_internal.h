@@ -109,6 +109,11 @@ struct npm_ctx {
     // (and the scan's block totals), and the binned items
     uint32_t *s_bin_cnt = nullptr, *s_bin_items = nullptr;
     size_t bin_cnt_words = 0, bin_item_words = 0;
+    // a second stream (default priority) on which the windowed scatter and
+    // the weight-gradient sum run beside the binned scatter, forked from and
+    // joined back to the caller's stream by the two events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     npm::Timing timing;
 };
 

@@ -324,6 +324,9 @@ static void free_ctx(npm_ctx *ctx)
         if (p) hipFree(p);
     for (auto &p : ctx->timing.pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : ctx->timing.free_events) hipEventDestroy(e);
+    if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+    if (ctx->side) hipStreamDestroy(ctx->side);
     delete ctx;
 }
 
@@ -378,6 +381,9 @@ npm_status npm_create(const npm_config *cfg, npm_ctx **out)
         alloc(&ctx->ema_img16, img * 2);
         if (net.cfg.precision == NPM_PREC_BF16) alloc(&ctx->ema_grid16, net.lay.grid_params * 2);
     }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemset(ctx->grads, 0, np * 4);
     if (e == hipSuccess) e = hipMemset(ctx->adam_m, 0, np * 4);
     if (e == hipSuccess) e = hipMemset(ctx->adam_v, 0, np * 4);
