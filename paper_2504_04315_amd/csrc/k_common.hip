@@ -25,7 +25,7 @@ void timed_begin(npm_ctx *ctx, const char *name, hipStream_t s, int *token)
         if (!t.free_events.empty()) { *e = t.free_events.back(); t.free_events.pop_back(); }
         else if (hipEventCreate(e) != hipSuccess) return;
     }
-    hipEventRecord(a, s);
+    (void)hipEventRecord(a, s);      // a failed record only loses the timing
     t.pending.push_back({id, a, b});
     *token = (int)t.pending.size() - 1;
 }
@@ -33,7 +33,7 @@ void timed_begin(npm_ctx *ctx, const char *name, hipStream_t s, int *token)
 void timed_end(npm_ctx *ctx, int token, hipStream_t s)
 {
     if (token < 0) return;
-    hipEventRecord(ctx->timing.pending[token].b, s);
+    (void)hipEventRecord(ctx->timing.pending[token].b, s);
 }
 
 // ---------------------------------------------------------------- init

@@ -517,7 +517,9 @@ static hipError_t run_query(npm_ctx *ctx, FusedArgs a, hipStream_t s)
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2048));
     const size_t lds = (size_t)a.fwd_elems * (BF ? 2 : 4);
     auto k = k_query_fused<IN_P, HID_P, NH, F, BF, PG, SEL>;
-    hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute((const void *)k,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, s, a);
     return hipGetLastError();
 }
@@ -555,7 +557,9 @@ static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
     if (lds > kLdsBytes) return hipErrorInvalidValue;
     if (!BF) a.img = ctx->mlp_img + ctx->net.mlp.fwd_elems + ctx->net.mlp.bwd_elems;
     auto k = k_backward_fused<IN_P, HID_P, NH, F, BF, PG, kTrainWaves, SEL>;
-    hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute((const void *)k,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * kTrainWaves), lds, s, a, count, tpb, (int)img);
     return hipGetLastError();
 }

@@ -276,8 +276,8 @@ hipError_t round_buffers_init(RoundBuffers *b)
 
 void round_buffers_free(RoundBuffers *b)
 {
-    if (b->host) hipHostFree(b->host);
-    if (b->dev) hipFree(b->dev);
+    if (b->host) (void)hipHostFree(b->host);
+    if (b->dev) (void)hipFree(b->dev);
     b->host = b->dev = nullptr;
 }
 
@@ -307,14 +307,18 @@ static hipError_t launch_group(RoundHdr *hdr, const DevReq *reqs, int r0, int r1
     if (!train) {
         auto k = k_serve_query<IN_P, HID_P, NH, F>;
         const int lds = img_bytes_max;
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        const hipError_t e = hipFuncSetAttribute((const void *)k,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, s, hdr, reqs, r0, r1, chunks, which);
     } else {
         auto k = k_serve_train<IN_P, HID_P, NH, F>;
         // images, the exchange buffer, four waves' scatter buffers
         const int lds = (img_bytes_max + 15) / 16 * 16 + (int)serve_xch_bytes<IN_P, HID_P, NH>() +
                         4 * HID_P * kStride * (int)sizeof(float);
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        const hipError_t e = hipFuncSetAttribute((const void *)k,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(std::min(blocks, 256)), dim3(256), lds, s, hdr, reqs, r0, r1,
                            chunks, which, img_bytes_max);
     }

@@ -577,31 +577,38 @@ __global__ __launch_bounds__(256) void k_scatter(GridDesc g, int64_t n, const fl
 
 template <int IN_P, int HID_P, int NH>
 struct MlpFwd {
-    static void run(npm_ctx *ctx, int blocks, int64_t n, const float *G, float *acts, float *raw,
-                    hipStream_t s, const float *img, const float *wsel)
+    static hipError_t run(npm_ctx *ctx, int blocks, int64_t n, const float *G, float *acts,
+                          float *raw, hipStream_t s, const float *img, const float *wsel)
     {
         const MlpDesc &m = ctx->net.mlp;
         const int elems = (int)m.fwd_elems;
-        hipFuncSetAttribute((const void *)k_mlp_fwd<IN_P, HID_P, NH>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, elems * sizeof(float));
+        const hipError_t e = hipFuncSetAttribute((const void *)k_mlp_fwd<IN_P, HID_P, NH>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 elems * sizeof(float));
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mlp_fwd<IN_P, HID_P, NH>), dim3(blocks), dim3(256),
                            elems * sizeof(float), s, n, m.n_in, m.width, img, elems, G,
                            acts, raw, wsel);
+        return hipGetLastError();
     }
 };
 
 template <int IN_P, int HID_P, int NH>
 struct MlpBwd {
-    static void run(npm_ctx *ctx, int blocks, int64_t n, const float *draw, const float *acts,
-                    float *delta, float *dG, hipStream_t s, const float *wsel)
+    static hipError_t run(npm_ctx *ctx, int blocks, int64_t n, const float *draw,
+                          const float *acts, float *delta, float *dG, hipStream_t s,
+                          const float *wsel)
     {
         const MlpDesc &m = ctx->net.mlp;
         const int elems = (int)m.bwd_elems;
-        hipFuncSetAttribute((const void *)k_mlp_bwd<IN_P, HID_P, NH>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, elems * sizeof(float));
+        const hipError_t e = hipFuncSetAttribute((const void *)k_mlp_bwd<IN_P, HID_P, NH>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 elems * sizeof(float));
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mlp_bwd<IN_P, HID_P, NH>), dim3(blocks), dim3(256),
                            elems * sizeof(float), s, n, m.n_in, m.width,
                            ctx->mlp_img + m.fwd_elems, elems, draw, acts, delta, dG, wsel);
+        return hipGetLastError();
     }
 };
 
@@ -620,9 +627,10 @@ hipError_t staged_mlp_fwd(npm_ctx *ctx, int64_t n, const float *G, float *acts, 
     const float *wsel = selection_row(ctx, w ? w->grid32 : ctx->params);
     int tok;
     timed_begin(ctx, acts ? "staged_mlp_fwd_train" : "staged_mlp_fwd", s, &tok);
-    NPM_MLP_DISPATCH(MlpFwd, ::run(ctx, blocks, n, G, acts, raw, s, img, wsel));
+    hipError_t e = hipSuccess;
+    NPM_MLP_DISPATCH(e = MlpFwd, ::run(ctx, blocks, n, G, acts, raw, s, img, wsel));
     timed_end(ctx, tok, s);
-    return hipGetLastError();
+    return e;
 }
 
 hipError_t staged_mlp_bwd(npm_ctx *ctx, int64_t n, const float *draw, const float *acts,
@@ -632,9 +640,10 @@ hipError_t staged_mlp_bwd(npm_ctx *ctx, int64_t n, const float *draw, const floa
     int tok;
     timed_begin(ctx, "staged_mlp_bwd", s, &tok);
     const float *wsel = selection_row(ctx, ctx->params);
-    NPM_MLP_DISPATCH(MlpBwd, ::run(ctx, blocks, n, draw, acts, delta, dG, s, wsel));
+    hipError_t e = hipSuccess;
+    NPM_MLP_DISPATCH(e = MlpBwd, ::run(ctx, blocks, n, draw, acts, delta, dG, s, wsel));
     timed_end(ctx, tok, s);
-    return hipGetLastError();
+    return e;
 }
 
 static constexpr int kDwBlocks = 256;

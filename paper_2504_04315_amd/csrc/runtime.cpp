@@ -304,7 +304,7 @@ npm_status npm_get_layout(const npm_config *cfg, npm_layout *out)
 static void free_scratch(npm_ctx *ctx)
 {
     for (float **p : {&ctx->s_G, &ctx->s_raw, &ctx->s_acts, &ctx->s_delta, &ctx->s_draw, &ctx->s_dG}) {
-        if (*p) hipFree(*p);
+        if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
     ctx->scratch_n = 0;
@@ -321,12 +321,12 @@ static void free_ctx(npm_ctx *ctx)
                     (void *)ctx->s_cells, (void *)ctx->s_dgt, (void *)ctx->s_bin_cnt,
                     (void *)ctx->s_bin_items,
                     (void *)ctx->ema, (void *)ctx->ema_img, ctx->ema_img16, ctx->ema_grid16})
-        if (p) hipFree(p);
-    for (auto &p : ctx->timing.pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
-    for (auto e : ctx->timing.free_events) hipEventDestroy(e);
-    if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
-    if (ctx->side) hipStreamDestroy(ctx->side);
+        if (p) (void)hipFree(p);
+    for (auto &p : ctx->timing.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : ctx->timing.free_events) (void)hipEventDestroy(e);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }
 
@@ -403,7 +403,7 @@ npm_status npm_create(const npm_config *cfg, npm_ctx **out)
 npm_status npm_destroy(npm_ctx *ctx)
 {
     if (!ctx) return NPM_OK;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();   // the frees that follow synchronise too
     free_ctx(ctx);
     return NPM_OK;
 }
@@ -562,14 +562,14 @@ static hipError_t ensure_bins(npm_ctx *ctx, const BinDesc &b)
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
     if (cw > ctx->bin_cnt_words) {
-        if (ctx->s_bin_cnt) hipFree(ctx->s_bin_cnt);
+        if (ctx->s_bin_cnt) (void)hipFree(ctx->s_bin_cnt);
         ctx->s_bin_cnt = nullptr;
         ctx->bin_cnt_words = 0;
         if ((e = hipMalloc((void **)&ctx->s_bin_cnt, cw * 4)) != hipSuccess) return e;
         ctx->bin_cnt_words = cw;
     }
     if (iw > ctx->bin_item_words) {
-        if (ctx->s_bin_items) hipFree(ctx->s_bin_items);
+        if (ctx->s_bin_items) (void)hipFree(ctx->s_bin_items);
         ctx->s_bin_items = nullptr;
         ctx->bin_item_words = 0;
         if ((e = hipMalloc((void **)&ctx->s_bin_items, iw * 4)) != hipSuccess) return e;
@@ -583,7 +583,7 @@ static hipError_t ensure_qstage(npm_ctx *ctx, int64_t n)
     if (n <= ctx->qstage_n) return hipSuccess;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
-    if (ctx->s_qstage) hipFree(ctx->s_qstage);
+    if (ctx->s_qstage) (void)hipFree(ctx->s_qstage);
     ctx->s_qstage = nullptr;
     ctx->qstage_n = 0;
     e = hipMalloc((void **)&ctx->s_qstage, (size_t)n * 40 * sizeof(float));
@@ -597,9 +597,9 @@ static hipError_t ensure_sort(npm_ctx *ctx, int64_t n)
     if (n <= ctx->sort_n) return hipSuccess;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
-    if (ctx->s_perm) hipFree(ctx->s_perm);
-    if (ctx->s_inv) hipFree(ctx->s_inv);
-    if (ctx->s_rec) hipFree(ctx->s_rec);
+    if (ctx->s_perm) (void)hipFree(ctx->s_perm);
+    if (ctx->s_inv) (void)hipFree(ctx->s_inv);
+    if (ctx->s_rec) (void)hipFree(ctx->s_rec);
     ctx->s_perm = ctx->s_inv = nullptr;
     ctx->s_rec = nullptr;
     ctx->sort_n = 0;
@@ -620,7 +620,7 @@ static hipError_t ensure_dgt(npm_ctx *ctx, int64_t n)
     if (tiles <= ctx->dgt_tiles) return hipSuccess;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
-    if (ctx->s_dgt) hipFree(ctx->s_dgt);
+    if (ctx->s_dgt) (void)hipFree(ctx->s_dgt);
     ctx->s_dgt = nullptr;
     ctx->dgt_tiles = 0;
     const int64_t rows = std::max(ctx->net.mlp.in_p, 32);

@@ -199,9 +199,9 @@ void scheduler(npm_server *s)
         hipError_t ee = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (ee == hipSuccess) ee = hipEventRecord(ev, s->stream);
         if (ee != hipSuccess) {
-            if (ev) hipEventDestroy(ev);
+            if (ev) (void)hipEventDestroy(ev);
             ev = nullptr;
-            hipStreamSynchronize(s->stream);
+            (void)hipStreamSynchronize(s->stream);   // the round is marked failed either way
         }
         lk.lock();
         rd.failed = e != hipSuccess || ee != hipSuccess;
@@ -223,8 +223,9 @@ void completer(npm_server *s)
         if (rd.id < 0) break;
         lk.unlock();
         if (rd.done_ev) {
-            hipEventSynchronize(rd.done_ev);
-            hipEventDestroy(rd.done_ev);
+            // a round whose work the device did not complete fails its requests
+            if (hipEventSynchronize(rd.done_ev) != hipSuccess) rd.failed = true;
+            (void)hipEventDestroy(rd.done_ev);
         }
         const double t = now_us();
         lk.lock();
@@ -262,12 +263,12 @@ npm_status npm_server_create(const npm_server_config *cfg, npm_server **out)
     npm_server *s = new (std::nothrow) npm_server();
     if (!s) return sfail(NPM_ERR_OOM, "host allocation");
     s->cfg = *cfg;
-    hipGetDevice(&s->device);
-    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     for (int i = 0; i < kSlots && e == hipSuccess; ++i) e = round_buffers_init(&s->bufs[i]);
     if (e != hipSuccess) {
         for (int i = 0; i < kSlots; ++i) round_buffers_free(&s->bufs[i]);
-        if (s->stream) hipStreamDestroy(s->stream);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
         return sfail(NPM_ERR_HIP, std::string("server create: ") + hipGetErrorString(e));
     }
@@ -312,11 +313,11 @@ npm_status npm_server_destroy(npm_server *s)
     s->cv_sched.notify_all();
     s->sched.join();
     s->completer.join();
-    hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->stream);
     for (auto &se : s->sessions)
         if (se.alive) npm_destroy(se.ctx);
     for (int i = 0; i < kSlots; ++i) round_buffers_free(&s->bufs[i]);
-    hipStreamDestroy(s->stream);
+    (void)hipStreamDestroy(s->stream);
     delete s;
     return NPM_OK;
 }
@@ -384,7 +385,7 @@ npm_status npm_session_destroy(npm_server *s, int32_t sid)
     s->bytes_in_use -= se.bytes;
     s->stats.sessions -= 1;
     lk.unlock();
-    hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->stream);   // npm_destroy synchronises the device as well
     return npm_destroy(ctx);
 }
 
