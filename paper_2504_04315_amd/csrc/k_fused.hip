@@ -153,7 +153,7 @@ __device__ __forceinline__ float dot32(const __bf16 *a, const __bf16 *b)
 // feature f over wave q's 32 vertices; the waves' sums add at the end.
 template <int IN_P, int HID_P, int NH, int F, bool BF, int PG, int WV, bool SEL = false>
 __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp_weights,
-                                                           int tiles_per_block, int img_bytes)
+                                                           int img_bytes)
 {
     // the FP32 selection instantiation of the three-hidden-layer network
     // keeps whole blocks: there the split's extra accumulator would not fit
@@ -196,10 +196,25 @@ __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp
     double lacc = 0.0;
     const int64_t n = a.n;
     const int64_t ntiles = (n + 31) / 32;
-    const int64_t t_first = blockIdx.x * (int64_t)tiles_per_block;
-    const int64_t t_end = t_first + tiles_per_block < ntiles ? t_first + tiles_per_block : ntiles;
+    // Rounds of WV consecutive tiles are dealt to the blocks in turn.
+    // Workgroups are dispatched to the eight XCDs in turn (block b on XCD
+    // b mod 8), each XCD with its own L2: with a multiple of eight blocks each
+    // XCD takes a contiguous eighth of the tiles and its blocks take that
+    // eighth's rounds in turn, so that the rounds an XCD runs at one time are
+    // neighbours in the batch's order and share grid lines in its L2.  A
+    // block with no round still writes its (zero) partials.
+    int64_t t_lo = 0, t_end = ntiles, bl = blockIdx.x, nb = gridDim.x;
+    if (gridDim.x % 8 == 0) {
+        nb = gridDim.x / 8;
+        bl = blockIdx.x / 8;
+        const int64_t span = ((ntiles + 7) / 8 + WV - 1) / WV * WV;
+        t_lo = (int64_t)(blockIdx.x % 8) * span;
+        t_end = t_lo + span < ntiles ? t_lo + span : ntiles;
+    }
+    const int64_t stride = nb * WV;            // tiles from one of this block's rounds to the next
+    const int64_t t_first = t_lo + bl * WV;
     // the visiting slot of this lane in tile tt (the last vertex for a tile
-    // past the run or a lane past the batch)
+    // past the span or a lane past the batch)
     auto slot = [&](int64_t tt) {
         const int64_t v = tt * 32 + (lane & 31);
         return tt < t_end && v < n ? v : n - 1;
@@ -214,11 +229,11 @@ __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp
     constexpr int ING = PG > 0 ? ProductShape<PG>::GF : IN_P;   // grid features
     TileGather<ING, F, BF> gath;
     TrainInputs in_next = train_inputs(io, slot(t_first + wave), visit(io.perm, slot(t_first + wave)));
-    TrainInputs in_after = train_inputs(io, slot(t_first + WV + wave),
-                                        visit(io.perm, slot(t_first + WV + wave)));
+    TrainInputs in_after = train_inputs(io, slot(t_first + stride + wave),
+                                        visit(io.perm, slot(t_first + stride + wave)));
     if (PIPE && t_first < t_end)
         encode_issue<ING, F, BF>(gv, h, in_next.px, in_next.py, in_next.pz, gath);
-    for (int64_t t0 = t_first; t0 < t_end; t0 += WV) {
+    for (int64_t t0 = t_first; t0 < t_end; t0 += stride) {
         // every wave of the block runs every round (the phases synchronise);
         // a wave past the run's end takes a tile with no valid vertex
         const int64_t t = t0 + wave;
@@ -228,7 +243,7 @@ __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp
         const int64_t vv = visit(io.perm, vs);
         const TrainInputs in = in_next;
         in_next = in_after;
-        const int64_t s2 = slot(t + 2 * WV);
+        const int64_t s2 = slot(t + 2 * stride);
         in_after = train_inputs(io, s2, visit(io.perm, s2));
         float x[IN0 / 2];
         if constexpr (PIPE) {
@@ -236,7 +251,7 @@ __global__ __launch_bounds__(64 * WV) void k_backward_fused(FusedArgs a, int mlp
 #pragma unroll
             for (int i = IN_P / 2; i < IN0 / 2; ++i) x[i] = 0.0f;
             // the next round's gathers, in flight while this round's MLP runs
-            if (t0 + WV < t_end)
+            if (t0 + stride < t_end)
                 encode_issue<ING, F, BF>(gv, h, in_next.px, in_next.py, in_next.pz, gath);
         } else {
             tile_input<IN_P, F, BF, PG>(gv, io, in, vs, vv, h, x);
@@ -544,10 +559,6 @@ static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
 {
     using Plan = BlockPlan<IN_P, HID_P, NH, kTrainWaves>;
     const int blocks = backward_blocks(a.n);
-    const int64_t tiles = (a.n + 31) / 32;
-    // a contiguous run of tiles per block, whole rounds of kTrainWaves tiles
-    const int64_t per = (tiles + blocks - 1) / blocks;
-    const int tpb = (int)((per + kTrainWaves - 1) / kTrainWaves * kTrainWaves);
     const size_t img = BF ? (size_t)staged_elems(a, IN_P, HID_P, PG) * 2
                           : (size_t)Plan::rm_elems() * 4;
     if (!BF && (int64_t)Plan::rm_elems() != ctx->net.mlp.rm_elems) return hipErrorInvalidValue;
@@ -560,7 +571,7 @@ static hipError_t run_backward(npm_ctx *ctx, FusedArgs a, hipStream_t s)
     const hipError_t e = hipFuncSetAttribute((const void *)k,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * kTrainWaves), lds, s, a, count, tpb, (int)img);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * kTrainWaves), lds, s, a, count, (int)img);
     return hipGetLastError();
 }
 
