@@ -793,8 +793,8 @@ __device__ __forceinline__ void tile_input(const GridView &gv, const TrainIO &io
 // ------------------------------------------------------------------ block-cooperative weight gradients
 // The training kernel splits the weight gradients of a block among its WV
 // waves.  In every round each wave runs encode, forward, KL-gradient head and
-// delta chain for its own 32-vertex tile (the block takes a contiguous run of
-// tiles, WV at a time); per layer, from the output layer back, the waves put
+// delta chain for its own 32-vertex tile (the block takes WV tiles at a
+// time); per layer, from the output layer back, the waves put
 // the layer's deltas and inputs into a shared LDS exchange buffer, transposed
 // (rows = features, one column per vertex of the round), and each wave
 // accumulates its own share of that layer's 32x32 weight-gradient blocks
