@@ -487,6 +487,13 @@ def main():
     ms_per_step = total_ms / steps
     print(f"timed {steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # ---- achievable rates of this device (after the timed region; not in a
+    # profiled run, whose kernel list it would join)
+    peaks = None if args.profile else B.measure_peaks(reps=3)
+    if peaks is not None:
+        print("achievable: " + ", ".join(f"{k} {v:.0f}" for k, v in peaks.items()),
+              file=sys.stderr, flush=True)
+
     # ---- roofline of the dominant kernel
     sha = kernel_sources_sha()
     traffic = load_profile("traffic", f"cfg2_{args.precision}_{args.mode}", sha)
@@ -531,6 +538,14 @@ def main():
             # (copy-calibrated), null when the kernels changed since
             "traffic": None if tr is None else tr["fetch_bytes"] + tr["write_bytes"],
             "traffic_fetch_write": (None if tr is None else [tr["fetch_bytes"], tr["write_bytes"]])}
+    if peaks is not None:
+        # the same kernel against what this device reaches with a plain kernel
+        # of the bounding kind (matrix instructions alone, or the better of a
+        # 2 GiB read stream and a 1 GiB copy)
+        ach = (peaks["mfma_bf16_tflops" if dtype == "bf16" else "mfma_f32_tflops"]
+               if bound == "mfma" else max(peaks["hbm_copy_gbs"], peaks["hbm_read_gbs"]))
+        roof["achievable_peak"] = round(ach, 2)
+        roof["frac_of_achievable"] = round(achieved / ach, 4)
     mc = measured.get("kernels", {}).get(dom)
     if mc is not None:
         # counter evidence beside the time-derived fraction (rocprofv3 --pmc):
@@ -576,6 +591,8 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+    if peaks is not None:
+        line["achievable_peaks"] = {k: round(v, 1) for k, v in peaks.items()}
     if not (args.no_serving or args.profile):
         print("serving ...", file=sys.stderr, flush=True)
         line["serving"] = serving_bench()

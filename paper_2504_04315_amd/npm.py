@@ -88,6 +88,7 @@ SIGNATURES = {
     "npm_query_select": [_P, _i64, _P, _P, _P, _u64, _u32, _P, _P, _P, _P, _P, _P],
     "npm_backward_select": [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "npm_train_step_select": [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _P],
+    "npm_measure_peaks": [_P, _i32],
 }
 STATIC_MAX_N = 32768
 
@@ -357,3 +358,12 @@ class NPM:
         check(lib().npm_kernel_times(self._ctx, arr, 64, C.byref(cnt)))
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms)
                 for i in range(min(cnt.value, 64))}
+
+
+def measure_peaks(reps=3):
+    """Achievable rates of the current device (include/npm_probe.h): FP32 and
+    BF16 matrix TFLOP/s, HBM read and copy GB/s, each the best of `reps`."""
+    out = (C.c_double * 4)()
+    check(lib().npm_measure_peaks(out, int(reps)))
+    return {"mfma_f32_tflops": out[0], "mfma_bf16_tflops": out[1], "hbm_read_gbs": out[2],
+            "hbm_copy_gbs": out[3]}

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     names = set()
-    for h in ("npm.h", "npm_serve.h"):
+    for h in sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")):
         text = open(os.path.join(ROOT, "include", h)).read()
         names |= set(re.findall(r"^\s*(?:npm_status|const char \*)\s*(npm_\w+)\s*\(", text, re.M))
     return names
@@ -33,7 +33,16 @@ def test_every_declared_symbol_is_exported():
     assert set(S.SIGNATURES) <= names
     assert {"npm_server_create", "npm_submit_train", "npm_server_hold",
             "npm_backward_static", "npm_query_select", "npm_backward_select",
-            "npm_train_step_select"} <= names
+            "npm_train_step_select", "npm_measure_peaks"} <= names
+
+
+def test_peak_probe_validates_before_touching_a_device():
+    lib = B.lib()
+    out = (C.c_double * 4)(-1.0, -1.0, -1.0, -1.0)
+    assert lib.npm_measure_peaks(None, 1) == -1
+    assert lib.npm_measure_peaks(out, 0) == -1
+    assert b"reps" in lib.npm_last_error()
+    assert list(out) == [-1.0] * 4            # written only on success
 
 
 def test_version_and_last_error():
