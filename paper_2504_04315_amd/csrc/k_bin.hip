@@ -6,23 +6,30 @@
 // corner becomes one FP32 atomic request executed at the memory side -- the
 // rate that bounds the plain scatter.  Here the corner contributions of those
 // levels are instead binned by table slice (kBinSliceFloats floats) and each
-// slice is summed by one block:
+// slice is summed by one block.  An item is a pair of x-neighbour corners:
+// the hash takes x unmultiplied, so slot(x + 1) = slot(x) ^ (x ^ (x + 1)),
+// which stays in the slice of slot(x) while the resolution is below the
+// slice's entry count (the plan checks it).  An item holds the key (the
+// lower corner's entry within the slice, and above bit 16 the xor to the
+// upper one), the x fraction f and the F values wy wz dG; the reduce adds
+// (1 - f) times them to the lower entry and f times them to the upper one.
 //
 //   count   per chunk of kBinChunk visiting slots, the number of items of
 //           every (level, slice) bin              -> cnt[bin][chunk]
 //   scan    exclusive prefix sum of cnt in bin-major order: the chunk's run
 //           of items inside its bin's contiguous range
 //   place   the chunk's items, ordered by bin in LDS and written out as
-//           contiguous runs: F values w * dG (FP32) and, in an array of its
-//           own, the 16-bit entry within the slice
+//           contiguous runs (keys, fractions and values in arrays of their
+//           own)
 //   reduce  one block per bin: LDS accumulation of its items -- FP64, or in
 //           the precision form 64-bit fixed point (no FP64) -- then one
 //           coalesced read-add-write of the slice into the gradient
 //
 // Items are recomputed identically by count and place (same inputs, same
 // arithmetic), so place fills each chunk's run exactly; every LDS and global
-// index is still checked against its buffer.  The values are those of the
-// atomic scatter (w * dG with the same w), summed in another order.
+// index is still checked against its buffer.  The values are the atomic
+// scatter's corner weights applied to dG in another grouping (wx (wy wz dG)
+// instead of (wx wy wz) dG) and summed in another order.
 #include <type_traits>
 
 #include "device_math.h"
@@ -59,14 +66,16 @@ __device__ __forceinline__ bool slot_dg(const float *__restrict__ dgt, int rows,
     return any;
 }
 
-// Hashed table slot of corner b of the cell and its trilinear weight (the
-// same expressions as the atomic scatter).
-__device__ __forceinline__ uint32_t corner_slot(const int c[3], const float fr[3], int b,
-                                                uint32_t mask, float &w)
+// Hashed table slot of the lower corner of pair p (y offset p & 1, z offset
+// p >> 1) of the cell, the xor m to its x-neighbour's slot, and the pair's
+// weight wy wz (the same hash as the atomic scatter).
+__device__ __forceinline__ uint32_t pair_slot(const int c[3], const float fr[3], int p,
+                                              uint32_t mask, uint32_t &m, float &wyz)
 {
-    const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-    const uint32_t X = c[0] + bx, Y = c[1] + by, Z = c[2] + bz;
-    w = (bx ? fr[0] : 1.0f - fr[0]) * (by ? fr[1] : 1.0f - fr[1]) * (bz ? fr[2] : 1.0f - fr[2]);
+    const int by = p & 1, bz = (p >> 1) & 1;
+    const uint32_t X = c[0], Y = c[1] + by, Z = c[2] + bz;
+    m = (X ^ (X + 1u)) & mask;
+    wyz = (by ? fr[1] : 1.0f - fr[1]) * (bz ? fr[2] : 1.0f - fr[2]);
     return (X ^ (Y * 2654435761u) ^ (Z * 805459861u)) & mask;
 }
 
@@ -120,9 +129,10 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_count(GridDesc g, BinDesc bd,
 #pragma unroll
             for (int a = 0; a < 3; ++a) lattice_cell(p[a], s_res[l], c[a], fr[a]);
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                float w;
-                const uint32_t slot = corner_slot(c, fr, b, g.table_mask, w);
+            for (int pr = 0; pr < 4; ++pr) {
+                uint32_t m;
+                float wyz;
+                const uint32_t slot = pair_slot(c, fr, pr, g.table_mask, m, wyz);
                 atomicAdd(&hist[j * bd.ns + (int)(slot >> bd.log2s)], 1u);
             }
         }
@@ -212,8 +222,8 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
                                                          const uint32_t *__restrict__ off,
                                                          uint32_t *__restrict__ items)
 {
-    constexpr int W = 1 + F;                 // words per item
-    constexpr int CAP = kBinChunk * 8;       // items of one chunk and level
+    constexpr int W = 2 + F;                 // words per item: key, fraction, F values
+    constexpr int CAP = kBinChunk * 4;       // items (corner pairs) of one chunk and level
     __shared__ uint32_t st[CAP * W];
     __shared__ uint16_t sb[CAP];
     __shared__ int s_lv[NPM_MAX_LEVELS], s_res[NPM_MAX_LEVELS];
@@ -239,8 +249,9 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
     float p[3] = {0.0f, 0.0f, 0.0f};
     if (live) slot_position(pos, perm, rec, rec_stride, n, s, p);
     const uint32_t smask = (1u << bd.log2s) - 1u;
-    float *vals = reinterpret_cast<float *>(items);
-    uint16_t *ents = reinterpret_cast<uint16_t *>(vals + (size_t)bd.cap * F);
+    uint32_t *keys = items;
+    float *fxs = reinterpret_cast<float *>(items + bd.cap);
+    float *vals = fxs + bd.cap;
     __syncthreads();
     for (int j = 0; j < bd.nb; ++j) {
         // local base of the chunk's run of each bin of the level
@@ -268,15 +279,17 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
 #pragma unroll
             for (int a = 0; a < 3; ++a) lattice_cell(p[a], s_res[l], c[a], fr[a]);
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                float w;
-                const uint32_t slot = corner_slot(c, fr, b, g.table_mask, w);
+            for (int pr = 0; pr < 4; ++pr) {
+                uint32_t m;
+                float wyz;
+                const uint32_t slot = pair_slot(c, fr, pr, g.table_mask, m, wyz);
                 const int k = (int)(slot >> bd.log2s);
                 const uint32_t q = lb[k] + atomicAdd(&rk[k], 1u);
                 if (q < lb[k + 1] && q < (uint32_t)CAP) {
-                    st[q * W] = slot & smask;
+                    st[q * W] = (slot & smask) | (m << 16);
+                    st[q * W + 1] = __float_as_uint(fr[0]);
 #pragma unroll
-                    for (int f = 0; f < F; ++f) st[q * W + 1 + f] = __float_as_uint(w * d[f]);
+                    for (int f = 0; f < F; ++f) st[q * W + 2 + f] = __float_as_uint(wyz * d[f]);
                     sb[q] = (uint16_t)k;
                 }
             }
@@ -288,9 +301,10 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
             if (k >= bd.ns) continue;
             const uint32_t dst = gd[j * bd.ns + k] + (q - lb[k]);
             if (dst < bd.cap) {
+                keys[dst] = st[q * W];
+                fxs[dst] = __uint_as_float(st[q * W + 1]);
 #pragma unroll
-                for (int f = 0; f < F; ++f) vals[(size_t)dst * F + f] = __uint_as_float(st[q * W + 1 + f]);
-                ents[dst] = (uint16_t)st[q * W];
+                for (int f = 0; f < F; ++f) vals[(size_t)dst * F + f] = __uint_as_float(st[q * W + 2 + f]);
             }
         }
         __syncthreads();
@@ -301,11 +315,11 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
 // read-add-write of the slice into the gradient.  The sums are FP64 (LDS
 // FP64 atomic adds run several times faster than FP32 ones on this chip, and
 // the wider sum rounds once, when it is added to the FP32 gradient), or, in
-// the precision form (FIXED), 64-bit fixed point: with every item below the
-// batch's largest |dG|, M < 2^e, and c items in the bin (c <= 2^b), the scale
-// 2^(62 - e - b) keeps every entry's sum below 2^62; each item is rounded to
-// a multiple of 2^(e + b - 62) (below 1e-12 of M for any bin of at most 2^23
-// items) and the sum is exact in any order.
+// the precision form (FIXED), 64-bit fixed point: with every corner value
+// below the batch's largest |dG|, M < 2^e, and 2c corner values in the bin of
+// c items (2c <= 2^b), the scale 2^(62 - e - b) keeps every entry's sum below
+// 2^62; each value is rounded to a multiple of 2^(e + b - 62) (below 1e-12 of
+// M for any bin of at most 2^22 items) and the sum is exact in any order.
 template <int F, bool FIXED>
 __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, BinDesc bd,
                                                                   const uint32_t *__restrict__ off,
@@ -316,8 +330,9 @@ __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, Bi
     constexpr int NT = kBinReduceThreads, U = kBinReduceBatch;
     using AccT = typename std::conditional<FIXED, unsigned long long, double>::type;
     __shared__ AccT acc[kBinSliceFloats];
-    const float *vals = reinterpret_cast<const float *>(items);
-    const uint16_t *ents = reinterpret_cast<const uint16_t *>(vals + (size_t)bd.cap * F);
+    const uint32_t *keys = items;
+    const float *fxs = reinterpret_cast<const float *>(items + bd.cap);
+    const float *vals = fxs + bd.cap;
     const int k = blockIdx.x, j = k / bd.ns, slice = k - j * bd.ns;
     const uint32_t S = 1u << bd.log2s;
     const int nf = (int)S * F;
@@ -329,23 +344,28 @@ __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, Bi
         if (!(M > 0.0f) || end <= beg) return;   // nothing to add (block-uniform)
         int e;
         frexpf(M, &e);                           // M < 2^e
-        const uint64_t c = end - beg;
+        const uint64_t c = 2 * (end - beg);                            // corner values
         const int b = c > 1 ? 64 - __clzll((long long)(c - 1)) : 0;   // c <= 2^b
         kx = 62 - e - b;
     }
     for (int i = threadIdx.x; i < nf; i += NT) acc[i] = AccT(0);
     __syncthreads();
-    auto add = [&](uint32_t e, const float *v) {
-        if (e < S) {
+    auto add1 = [&](uint32_t e, float v) {
+        if constexpr (FIXED)
+            __hip_atomic_fetch_add(&acc[e], (unsigned long long)__float2ll_rn(ldexpf(v, kx)),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            __hip_atomic_fetch_add(&acc[e], (double)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    // item: (1 - fx) v to the lower corner's entry, fx v to the upper one's
+    auto add = [&](uint32_t key, float fx, const float *v) {
+        const uint32_t e0 = key & 0xffffu, e1 = e0 ^ (key >> 16);
+        if (e0 < S && e1 < S) {
+            const float w0 = 1.0f - fx;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                if constexpr (FIXED)
-                    __hip_atomic_fetch_add(&acc[e * F + f],
-                                           (unsigned long long)__float2ll_rn(ldexpf(v[f], kx)),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                else
-                    __hip_atomic_fetch_add(&acc[e * F + f], (double)v[f], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                add1(e0 * F + f, w0 * v[f]);
+                add1(e1 * F + f, fx * v[f]);
             }
         }
     };
@@ -353,22 +373,23 @@ __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, Bi
     // U items in flight per thread: all loads issued before the first add
     for (; i + (uint64_t)(U - 1) * NT < end; i += (uint64_t)U * NT) {
         uint32_t e[U];
-        float v[U][F];
+        float fx[U], v[U][F];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t ii = i + (uint64_t)u * NT;
-            e[u] = ents[ii];
+            e[u] = keys[ii];
+            fx[u] = fxs[ii];
 #pragma unroll
             for (int f = 0; f < F; ++f) v[u][f] = vals[ii * F + f];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) add(e[u], v[u]);
+        for (int u = 0; u < U; ++u) add(e[u], fx[u], v[u]);
     }
     for (; i < end; i += NT) {
         float v[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) v[f] = vals[i * F + f];
-        add(ents[i], v);
+        add(keys[i], fxs[i], v);
     }
     __syncthreads();
     float *dst = grad + ((size_t)g.offset[bd.lv[j]] + (size_t)slice * S) * F;
@@ -398,15 +419,18 @@ bool bin_plan(const npm_ctx *ctx, int64_t n, bool ordered, BinDesc *out)
     if (b.nb == 0) return false;
     int log2t = 0;
     while ((1u << log2t) <= g.table_mask) ++log2t;
-    static_assert(kBinSliceFloats <= 65536, "slice entries are stored in 16 bits");
+    static_assert(kBinSliceFloats <= 65536, "slice entries and their xor are stored in 16 bits");
     int log2s = 0;
     while ((1 << (log2s + 1)) * F <= kBinSliceFloats) ++log2s;
     b.log2s = std::min(log2s, log2t);
     b.ns = 1 << (log2t - b.log2s);
     b.nbins = b.nb * b.ns;
     if (b.ns > kBinMaxSlices || b.nbins > kBinMaxBins) return false;
+    // an x-neighbour pair shares a slice while x + 1 <= D_l < 2^log2s
+    for (int j = 0; j < b.nb; ++j)
+        if ((int64_t)g.res[b.lv[j]] >= ((int64_t)1 << b.log2s)) return false;
     b.n_chunks = (n + kBinChunk - 1) / kBinChunk;
-    b.cap = n * 8 * b.nb;
+    b.cap = n * 4 * b.nb;
     if (b.cap >= ((int64_t)1 << 32) - 1 || (int64_t)b.nbins * b.n_chunks + 1 >= ((int64_t)1 << 31))
         return false;
     *out = b;
@@ -421,10 +445,10 @@ size_t bin_count_words(const BinDesc &b)
     return (size_t)m + (size_t)((m + 1023) / 1024) + (size_t)b.n_chunks + 1;
 }
 
-// items: cap x F FP32 values, then cap 16-bit slice entries
+// items: cap keys, cap x fractions, then cap x F FP32 values
 size_t bin_item_words(const BinDesc &b, int feat)
 {
-    return (size_t)b.cap * (size_t)feat + ((size_t)b.cap + 1) / 2;
+    return (size_t)b.cap * (size_t)(2 + feat);
 }
 
 template <int F>

@@ -213,9 +213,10 @@ constexpr size_t kSortCellWords = ((size_t)1 << 18) + 256;
 
 // Binned scatter of the hashed levels (k_bin.hip).  The corner contributions
 // of a training batch are binned by (level, table slice) in chunks of
-// kBinChunk visiting slots, and each bin (a slice of kBinSliceFloats table
-// floats) is summed by one block in FP64 LDS, replacing one memory-side FP32
-// atomic per corner.
+// kBinChunk visiting slots, as pairs of x-neighbour corners (which the hash
+// keeps in one slice), and each bin (a slice of kBinSliceFloats table floats)
+// is summed by one block in LDS, replacing one memory-side FP32 atomic per
+// corner.
 constexpr int kBinChunk = 512;
 constexpr int kBinSliceFloats = 16384;      // table floats per bin (8,192 entries at F = 2)
 constexpr int kBinReduceThreads = 1024;
@@ -240,7 +241,7 @@ struct BinDesc {
     int32_t ns;                        // slices per level
     int32_t nbins;                     // nb * ns
     int64_t n_chunks;                  // ceil(n / kBinChunk)
-    int64_t cap;                       // item capacity: n * 8 * nb
+    int64_t cap;                       // item (corner pair) capacity: n * 4 * nb
 };
 // false when the batch has no level to bin or exceeds the pass's limits
 bool bin_plan(const npm_ctx *ctx, int64_t n, bool ordered, BinDesc *out);
