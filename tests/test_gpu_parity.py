@@ -257,6 +257,29 @@ def test_binned_scatter_other_feature_counts(O, torch, net, order):
     model.close()
 
 
+# a hashed grid whose finest resolution (2048) reaches its small table's
+# slice size (T = 2^10: a single 1,024-entry slice per level): an x-neighbour
+# pair of corners may then straddle slices, so the binned mode leaves the
+# hashed levels to the atomic scatter; the gradient must not change
+WIDE_RES_SMALL_TABLE = W.NetConfig(n_levels=6, feat=2, base_res=16, max_res=2048, log2_table=10,
+                                   dense_only=False, n_hidden=2, width=32, grid_init="uniform",
+                                   grid_init_scale=0.1, seed=16)
+
+
+def test_binned_mode_with_pairs_straddling_slices(O, torch):
+    """The binned mode on a grid whose x-neighbour pairs can leave a slice:
+    the plan refuses the binned pass and the atomic scatter takes the hashed
+    levels, with the same gradient (against the oracle)."""
+    model = B.NPM(B.make_config(WIDE_RES_SMALL_TABLE, exec_mode=B.EXEC_FUSED,
+                                batch_order=B.ORDER_SPATIAL, scatter_mode=B.SCATTER_BINNED))
+    on = oracle_net(O, WIDE_RES_SMALL_TABLE)
+    params = randomize(model, on, np.random.default_rng(16), grid_sd=0.5)
+    batch = W.make_batch("surface", 4099, seed=28)
+    msgs, _, _ = check_backward(O, torch, model, on, params, batch, "pairs straddle slices")
+    print("\n".join(msgs))
+    model.close()
+
+
 @pytest.mark.parametrize("scatter", ["atomic", "binned"])
 def test_backward_accumulates_into_grad(O, torch, scatter):
     """npm_backward adds into grad_out: two calls give twice the gradient
