@@ -22,7 +22,10 @@
  *   - Work is enqueued on the caller's HIP stream (`stream` is a hipStream_t;
  *     NULL is the null stream) and the call returns without waiting.
  *     Outputs are valid once the stream has reached the call.  Calls on one
- *     context must not run concurrently on different streams.
+ *     context must not run concurrently on different streams.  A fused
+ *     training step may fork part of its grid scatter onto a stream of the
+ *     context (default priority) and joins it back to `stream` with events
+ *     before returning, so the caller's ordering on `stream` still holds.
  *   - n == 0 is a no-op that returns NPM_OK.  Optional outputs may be NULL,
  *     and the work that only feeds them is skipped.
  *   - The library owns parameters, gradients, Adam state and scratch; they
