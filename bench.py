@@ -68,13 +68,13 @@ WORK = {
 }
 # Binned scatter of the production grid's hashed levels in a spatially
 # ordered batch: levels 6-15 (D >= 100), 2^19 entries x F = 2 each, in slices
-# of 8,192 entries: 640 bins; chunks of 512 vertices; one 16-byte item (the
+# of 8,192 entries: 640 bins; chunks of 1,024 vertices; one 16-byte item (the
 # key, the x fraction, 2 FP32 values) per pair of x-neighbour corners and
 # level.  Levels 0-5 keep the windowed scatter.
 L_BINNED, L_WINDOW, T_HASH = 10, 6, 1 << 19
 BIN_ITEM_B = 16
 BIN_ITEMS_B = L_BINNED * 4 * BIN_ITEM_B           # 640 B per vertex
-BIN_COUNTERS_B = 4 * 640 / 512                    # one counter per bin and chunk
+BIN_COUNTERS_B = 4 * 640 / 1024                   # one counter per bin and chunk
 BIN_WORK = {
     # positions, dG of the binned levels; counters written
     "bin_count": dict(bytes=16 + L_BINNED * 2 * 4 + BIN_COUNTERS_B, flops=0),

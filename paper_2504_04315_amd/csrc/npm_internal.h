@@ -217,7 +217,7 @@ constexpr size_t kSortCellWords = ((size_t)1 << 18) + 256;
 // keeps in one slice), and each bin (a slice of kBinSliceFloats table floats)
 // is summed by one block in LDS, replacing one memory-side FP32 atomic per
 // corner.
-constexpr int kBinChunk = 512;
+constexpr int kBinChunk = 1024;           // 512 with one item per corner (its LDS then capped it)
 constexpr int kBinSliceFloats = 16384;      // table floats per bin (8,192 entries at F = 2)
 constexpr int kBinReduceThreads = 1024;
 constexpr int kBinReduceBatch = 4;         // items in flight per thread
