@@ -157,6 +157,35 @@ def test_hashed_indices_in_range(O):
     assert np.all(d == (cx ^ (cx + 1)))
 
 
+@pytest.mark.parametrize("feat,log2_slice", [(1, 14), (2, 13), (4, 12)])
+def test_x_neighbour_pairs_share_a_slice(O, feat, log2_slice):
+    """The binned grid scatter stores one item per pair of x-neighbour
+    corners.  That rests on the hash taking x unmultiplied: at every hashed
+    level and for every (y, z) corner pair, slot(x + 1) = slot(x) XOR
+    (x XOR (x + 1)), so the two corners fall in the same table slice of
+    2^log2_slice entries whenever the resolution is below the slice size
+    (the slice sizes the pass uses at F = 1, 2, 4)."""
+    net = O.Net(16, feat, 16, 2048, 19, False, 2, 32)
+    rng = np.random.default_rng(7 + feat)
+    pos = rng.random((3, 3000)).astype(np.float32)
+    idx, _ = O.corners(net, pos)
+    checked = 0
+    for l in range(16):
+        if not net.hashed[l]:
+            continue
+        D = net.res[l]
+        assert D < (1 << log2_slice)
+        off = net.level_offset[l]
+        cx = np.minimum(np.floor(pos[0] * np.float32(D)), D - 1).astype(np.int64)
+        for yz in range(4):                 # corners b = 2 yz (x) and 2 yz + 1 (x + 1)
+            lo = idx[:, l, 2 * yz] - off
+            hi = idx[:, l, 2 * yz + 1] - off
+            np.testing.assert_array_equal(hi, lo ^ (cx ^ (cx + 1)))
+            np.testing.assert_array_equal(hi >> log2_slice, lo >> log2_slice)
+            checked += 1
+    assert checked >= 4 * 10
+
+
 def test_mlp_matches_numpy(O):
     net = O.Net(16, 2, 16, 2048, 19, False, 3, 64)
     rng = np.random.default_rng(6)
