@@ -19,8 +19,7 @@
 //   scan    exclusive prefix sum of cnt in bin-major order: the chunk's run
 //           of items inside its bin's contiguous range
 //   place   the chunk's items, ordered by bin in LDS and written out as
-//           contiguous runs (keys, fractions and values in arrays of their
-//           own)
+//           contiguous runs of (key, fraction, F values) records
 //   reduce  one block per bin: LDS accumulation of its items -- FP64, or in
 //           the precision form 64-bit fixed point (no FP64) -- then one
 //           coalesced read-add-write of the slice into the gradient
@@ -249,9 +248,6 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
     float p[3] = {0.0f, 0.0f, 0.0f};
     if (live) slot_position(pos, perm, rec, rec_stride, n, s, p);
     const uint32_t smask = (1u << bd.log2s) - 1u;
-    uint32_t *keys = items;
-    float *fxs = reinterpret_cast<float *>(items + bd.cap);
-    float *vals = fxs + bd.cap;
     __syncthreads();
     for (int j = 0; j < bd.nb; ++j) {
         // local base of the chunk's run of each bin of the level
@@ -301,10 +297,15 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
             if (k >= bd.ns) continue;
             const uint32_t dst = gd[j * bd.ns + k] + (q - lb[k]);
             if (dst < bd.cap) {
-                keys[dst] = st[q * W];
-                fxs[dst] = __uint_as_float(st[q * W + 1]);
+                uint32_t *it = items + (size_t)dst * W;
+                if constexpr (W == 4) {
+                    uint4 r;
+                    r.x = st[q * W]; r.y = st[q * W + 1]; r.z = st[q * W + 2]; r.w = st[q * W + 3];
+                    *reinterpret_cast<uint4 *>(it) = r;
+                } else {
 #pragma unroll
-                for (int f = 0; f < F; ++f) vals[(size_t)dst * F + f] = __uint_as_float(st[q * W + 2 + f]);
+                    for (int w = 0; w < W; ++w) it[w] = st[q * W + w];
+                }
             }
         }
         __syncthreads();
@@ -330,9 +331,7 @@ __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, Bi
     constexpr int NT = kBinReduceThreads, U = kBinReduceBatch;
     using AccT = typename std::conditional<FIXED, unsigned long long, double>::type;
     __shared__ AccT acc[kBinSliceFloats];
-    const uint32_t *keys = items;
-    const float *fxs = reinterpret_cast<const float *>(items + bd.cap);
-    const float *vals = fxs + bd.cap;
+    constexpr int W = 2 + F;                 // words per item: key, fraction, F values
     const int k = blockIdx.x, j = k / bd.ns, slice = k - j * bd.ns;
     const uint32_t S = 1u << bd.log2s;
     const int nf = (int)S * F;
@@ -371,25 +370,32 @@ __global__ __launch_bounds__(kBinReduceThreads) void k_bin_reduce(GridDesc g, Bi
     };
     uint64_t i = beg + threadIdx.x;
     // U items in flight per thread: all loads issued before the first add
+    // one item: its W words (one 16-byte load at F = 2)
+    auto load = [&](uint64_t ii, uint32_t &e, float &fx, float *v) {
+        const uint32_t *it = items + ii * W;
+        if constexpr (W == 4) {
+            const uint4 r = *reinterpret_cast<const uint4 *>(it);
+            e = r.x; fx = __uint_as_float(r.y); v[0] = __uint_as_float(r.z); v[1] = __uint_as_float(r.w);
+        } else {
+            e = it[0];
+            fx = __uint_as_float(it[1]);
+#pragma unroll
+            for (int f = 0; f < F; ++f) v[f] = __uint_as_float(it[2 + f]);
+        }
+    };
     for (; i + (uint64_t)(U - 1) * NT < end; i += (uint64_t)U * NT) {
         uint32_t e[U];
         float fx[U], v[U][F];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t ii = i + (uint64_t)u * NT;
-            e[u] = keys[ii];
-            fx[u] = fxs[ii];
-#pragma unroll
-            for (int f = 0; f < F; ++f) v[u][f] = vals[ii * F + f];
-        }
+        for (int u = 0; u < U; ++u) load(i + (uint64_t)u * NT, e[u], fx[u], v[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) add(e[u], fx[u], v[u]);
     }
     for (; i < end; i += NT) {
-        float v[F];
-#pragma unroll
-        for (int f = 0; f < F; ++f) v[f] = vals[i * F + f];
-        add(keys[i], fxs[i], v);
+        uint32_t e;
+        float fx, v[F];
+        load(i, e, fx, v);
+        add(e, fx, v);
     }
     __syncthreads();
     float *dst = grad + ((size_t)g.offset[bd.lv[j]] + (size_t)slice * S) * F;
@@ -445,7 +451,7 @@ size_t bin_count_words(const BinDesc &b)
     return (size_t)m + (size_t)((m + 1023) / 1024) + (size_t)b.n_chunks + 1;
 }
 
-// items: cap keys, cap x fractions, then cap x F FP32 values
+// items: cap records of (key, x fraction, F FP32 values)
 size_t bin_item_words(const BinDesc &b, int feat)
 {
     return (size_t)b.cap * (size_t)(2 + feat);
