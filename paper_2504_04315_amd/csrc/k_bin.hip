@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
 {
     constexpr int W = 2 + F;                 // words per item: key, fraction, F values
     constexpr int CAP = kBinChunk * 4;       // items (corner pairs) of one chunk and level
-    __shared__ uint32_t st[CAP * W];
+    __shared__ __attribute__((aligned(16))) uint32_t st[CAP * W];
     __shared__ uint16_t sb[CAP];
     __shared__ int s_lv[NPM_MAX_LEVELS], s_res[NPM_MAX_LEVELS];
     // sized by the launch: each bin's run start and length, then the level's
@@ -282,10 +282,19 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
                 const int k = (int)(slot >> bd.log2s);
                 const uint32_t q = lb[k] + atomicAdd(&rk[k], 1u);
                 if (q < lb[k + 1] && q < (uint32_t)CAP) {
-                    st[q * W] = (slot & smask) | (m << 16);
-                    st[q * W + 1] = __float_as_uint(fr[0]);
+                    if constexpr (W == 4) {
+                        uint4 r;
+                        r.x = (slot & smask) | (m << 16);
+                        r.y = __float_as_uint(fr[0]);
+                        r.z = __float_as_uint(wyz * d[0]);
+                        r.w = __float_as_uint(wyz * d[1]);
+                        *reinterpret_cast<uint4 *>(st + q * W) = r;
+                    } else {
+                        st[q * W] = (slot & smask) | (m << 16);
+                        st[q * W + 1] = __float_as_uint(fr[0]);
 #pragma unroll
-                    for (int f = 0; f < F; ++f) st[q * W + 2 + f] = __float_as_uint(wyz * d[f]);
+                        for (int f = 0; f < F; ++f) st[q * W + 2 + f] = __float_as_uint(wyz * d[f]);
+                    }
                     sb[q] = (uint16_t)k;
                 }
             }
@@ -299,9 +308,7 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_place(GridDesc g, BinDesc bd,
             if (dst < bd.cap) {
                 uint32_t *it = items + (size_t)dst * W;
                 if constexpr (W == 4) {
-                    uint4 r;
-                    r.x = st[q * W]; r.y = st[q * W + 1]; r.z = st[q * W + 2]; r.w = st[q * W + 3];
-                    *reinterpret_cast<uint4 *>(it) = r;
+                    *reinterpret_cast<uint4 *>(it) = *reinterpret_cast<const uint4 *>(st + q * W);
                 } else {
 #pragma unroll
                     for (int w = 0; w < W; ++w) it[w] = st[q * W + w];
