@@ -602,6 +602,29 @@ template <> struct WinScale<int> {
     __device__ __forceinline__ float dec(int s) const { return ldexpf((float)s, -k); }
 };
 
+// fn(integral_constant<int, 0>) ... fn(integral_constant<int, N - 1>), in order
+template <int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn &&fn)
+{
+    if constexpr (N > 0) {
+        static_for<N - 1>(fn);
+        fn(std::integral_constant<int, N - 1>{});
+    }
+}
+
+// Lane J of each 16-lane row, to every lane of the row (DPP row_newbcast:J);
+// a lane the broadcast does not write keeps its own value.
+template <int J>
+__device__ __forceinline__ int row_bcast(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, 0x150 + J, 0xf, 0xf, false);
+}
+template <int J>
+__device__ __forceinline__ float row_bcast(float v)
+{
+    return __int_as_float(row_bcast<J>(__float_as_int(v)));
+}
+
 template <int F, int WIN_PTS, typename WT = float>
 __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dGt,
                                              const float *__restrict__ pos, const uint32_t *perm,
@@ -613,12 +636,18 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
 {
     constexpr int LPV = 8 * F;              // lanes per vertex-level
     constexpr int VPI = 64 / LPV;           // vertex-levels per instruction
+    constexpr int NJ = 32 / VPI;            // vertex-levels per lane and level
+    // F >= 2: the LPV lanes of a vertex-level fill whole 16-lane rows, so lane
+    // i of a row holds vertex (i mod NJ) VPI + q, forms its lattice cell once
+    // per level, and the row reads it by a DPP row broadcast when that
+    // vertex's turn comes (F = 1: every lane forms the cells it uses)
+    constexpr bool BC = F >= 2;
     const int q = lane / LPV, sub = lane % LPV, b = sub / F, f = sub % F;
     const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-    float px[32 / VPI], py[32 / VPI], pz[32 / VPI];
+    float px[BC ? 1 : NJ], py[BC ? 1 : NJ], pz[BC ? 1 : NJ];
 #pragma unroll
-    for (int jj = 0; jj < 32 / VPI; ++jj) {
-        const int64_t v = t * 32 + jj * VPI + q;
+    for (int jj = 0; jj < (BC ? 1 : NJ); ++jj) {
+        const int64_t v = t * 32 + (BC ? ((lane & 15) % NJ) : jj) * VPI + q;
         if (rec) {
             const f32x4 a = *reinterpret_cast<const f32x4 *>(rec + (size_t)(v < n ? v : n - 1) * rec_stride);
             px[jj] = a[0]; py[jj] = a[1]; pz[jj] = a[2];
@@ -661,17 +690,11 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
             for (int i = lane; i < nw; i += 64) win[i] = WT(0);
             wave_lds_fence();
         }
-#pragma unroll
-        for (int jj = 0; jj < 32 / VPI; ++jj) {
-            const int j = jj * VPI + q;
-            if (t * 32 + j >= n) continue;
+        // corner (bx, by, bz), feature f of vertex j of the tile
+        auto corner = [&](int j, int cx, int cy, int cz, float fx, float fy, float fz) {
+            if (t * 32 + j >= n) return;
             const float d = dGt[(l * F + f) * kStride + j];
-            if (d == 0.0f) continue;
-            int cx, cy, cz;
-            float fx, fy, fz;
-            lattice_cell(px[jj], D, cx, fx);
-            lattice_cell(py[jj], D, cy, fy);
-            lattice_cell(pz[jj], D, cz, fz);
+            if (d == 0.0f) return;
             const uint32_t X = cx + bx, Y = cy + by, Z = cz + bz;
             const float w = (bx ? fx : 1.0f - fx) * (by ? fy : 1.0f - fy) * (bz ? fz : 1.0f - fz);
             const uint32_t wx = X - (uint32_t)x0, wy = Y - (uint32_t)y0, wz = Z - (uint32_t)z0;
@@ -680,6 +703,28 @@ __device__ __forceinline__ void scatter_tile(const GridView &gv, const float *dG
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             else
                 unsafeAtomicAdd(grad + (size_t)entry(X, Y, Z) * F + f, w * d);
+        };
+        if constexpr (BC) {
+            int cxv, cyv, czv;
+            float fxv, fyv, fzv;
+            lattice_cell(px[0], D, cxv, fxv);
+            lattice_cell(py[0], D, cyv, fyv);
+            lattice_cell(pz[0], D, czv, fzv);
+            static_for<NJ>([&](auto J) {
+                constexpr int jj = decltype(J)::value;
+                corner(jj * VPI + q, row_bcast<jj>(cxv), row_bcast<jj>(cyv), row_bcast<jj>(czv),
+                       row_bcast<jj>(fxv), row_bcast<jj>(fyv), row_bcast<jj>(fzv));
+            });
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                int cx, cy, cz;
+                float fx, fy, fz;
+                lattice_cell(px[jj], D, cx, fx);
+                lattice_cell(py[jj], D, cy, fy);
+                lattice_cell(pz[jj], D, cz, fz);
+                corner(jj * VPI + q, cx, cy, cz, fx, fy, fz);
+            }
         }
         if (use_win) {
             wave_lds_fence();
