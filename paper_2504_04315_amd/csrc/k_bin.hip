@@ -111,10 +111,15 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_count(GridDesc g, BinDesc bd,
                                                          uint32_t *__restrict__ cnt,
                                                          uint32_t *__restrict__ cmax)
 {
-    __shared__ uint32_t hist[kBinMaxBins];
+    // NC copies of the histogram, lane t counting in copy t mod NC: fewer lanes of
+    // one instruction on one counter (the copies sit HS words apart, off each
+    // other's banks); the chunk's count is their sum (precision-form step
+    // 2.06 -> 2.04 ms, FP32 within noise)
+    constexpr int NC = 4, HS = kBinMaxBins + 1;
+    __shared__ uint32_t hist[NC * HS];
     __shared__ int s_lv[NPM_MAX_LEVELS], s_res[NPM_MAX_LEVELS];
     __shared__ uint32_t s_max;
-    for (int k = threadIdx.x; k < bd.nbins; k += kBinChunk) hist[k] = 0u;
+    for (int k = threadIdx.x; k < NC * HS; k += kBinChunk) hist[k] = 0u;
     if (threadIdx.x == 0) s_max = 0u;
     if (threadIdx.x < NPM_MAX_LEVELS) {
         s_lv[threadIdx.x] = bd.lv[threadIdx.x];
@@ -124,6 +129,7 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_count(GridDesc g, BinDesc bd,
     if (blockIdx.x == 0 && threadIdx.x == 0) cnt[(size_t)bd.nbins * bd.n_chunks] = 0u;
     __syncthreads();
     const int64_t s = blockIdx.x * (int64_t)kBinChunk + threadIdx.x;
+    uint32_t *hc = hist + (threadIdx.x & (NC - 1)) * HS;
     float dmax = 0.0f;      // largest |dG| the chunk bins (bounds every item)
     if (s < n) {
         float p[3];
@@ -147,15 +153,19 @@ __global__ __launch_bounds__(kBinChunk) void k_bin_count(GridDesc g, BinDesc bd,
                 uint32_t m;
                 float wyz;
                 const uint32_t slot = pair_slot(c, fr, pr, g.table_mask, m, wyz);
-                atomicAdd(&hist[j * bd.ns + (int)(slot >> bd.log2s)], 1u);
+                atomicAdd(&hc[j * bd.ns + (int)(slot >> bd.log2s)], 1u);
             }
         }
     }
     // non-negative floats order as their bit patterns
     atomicMax(&s_max, __float_as_uint(dmax));
     __syncthreads();
-    for (int k = threadIdx.x; k < bd.nbins; k += kBinChunk)
-        cnt[(size_t)k * bd.n_chunks + blockIdx.x] = hist[k];
+    for (int k = threadIdx.x; k < bd.nbins; k += kBinChunk) {
+        uint32_t c = 0u;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) c += hist[r * HS + k];
+        cnt[(size_t)k * bd.n_chunks + blockIdx.x] = c;
+    }
     if (threadIdx.x == 0) cmax[blockIdx.x] = s_max;
 }
 
